@@ -1,0 +1,189 @@
+/*
+ * isprime.h -- C ABI of the MI355X (gfx950) library for elementwise
+ * primality of unsigned 64-bit integers.
+ *
+ * The operation is the one the paper's isprime_fast computes (section 1: an
+ * array in, a logical array of the same size out; section 2: the domain is
+ * every 64-bit unsigned integer): out[i] = 1 if n[i] is prime, else 0.
+ *
+ * How each element is decided (all exact integer arithmetic):
+ *   n < 2, even n > 2      -> 0;  n == 2 -> 1
+ *   odd n < 2^32           -> one bit of a device-resident odd-only sieve
+ *                             table (sections 1 and 6.1.3: sieve once, then
+ *                             test membership; here an O(1) bit lookup)
+ *   odd n >= 2^32          -> exact divisibility by small odd primes
+ *                             (section 6.1.2: shrink the array first), then
+ *                             the strong probable-prime test of section 2.1
+ *                             (Eq. 1-3) over the seven bases of Eq. 4,
+ *                             2, 325, 9375, 28178, 450775, 9780504,
+ *                             1795265022, with Montgomery arithmetic.
+ *
+ * Conventions for every entry point:
+ *   - Returns ISP_OK (0) or a negative ISP_E* status.  Argument errors are
+ *     reported synchronously, before anything is enqueued.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it and is asynchronous: results are valid once the
+ *     stream is synchronised.  A device fault behind an ISP_EDEVICE may be
+ *     reported by this call, a later call, or the caller's synchronisation;
+ *     isp_last_device_error() returns the hipError_t behind the last one.
+ *   - Device pointers are owned by the caller; the library owns the sieve
+ *     table (256 MiB per device, built once) and its workspaces.
+ *   - There are no per-element errors: every uint64 value is in the domain.
+ *   - Thread safety: all entry points may be called from several host
+ *     threads.  Calls on different streams may overlap on the device (the
+ *     table is read-only after isp_init; workspaces are per stream); calls on
+ *     one stream are ordered by it.
+ */
+#ifndef ISPRIME_H
+#define ISPRIME_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ISP_OK = 0,
+    ISP_EINVAL = -1,    /* bad argument (NULL pointer with len > 0, bad config) */
+    ISP_ENOMEM = -2,    /* device or pinned host allocation failed */
+    ISP_EDEVICE = -3,   /* a HIP call failed; see isp_last_device_error() */
+    ISP_EBUSY = -4,     /* server: request not admissible now (non-blocking) */
+    ISP_ETIMEDOUT = -5, /* server: wait timed out */
+    ISP_ENOENT = -6     /* server: unknown ticket */
+};
+
+/* Build the odd-only sieve table for n < 2^32 on `device` (bit i of the
+ * table is 1 iff 2i+1 is prime; 2^31 bits = 256 MiB in HBM), together with
+ * the base primes and filter constants.  Blocking; idempotent; thread-safe.
+ * Every other entry point calls it lazily for the current device.
+ * Paper: section 1 (sieve of Eratosthenes), section 4 (odd numbers only). */
+int isp_init(int device);
+
+/* Free every device table, workspace and cached graph.  No call may be in
+ * flight on any stream. */
+void isp_shutdown(void);
+
+/* out[i] = primality of n[i] for 0 <= i < len.
+ *   n    device pointer to len uint64 values (read only; 8-byte aligned)
+ *   out  device pointer to len bytes, each written 0 or 1
+ *   len  0 returns ISP_OK without launching
+ * n == NULL or out == NULL with len > 0 -> ISP_EINVAL.  n and out must not
+ * overlap.  Uses the calling thread's current HIP device.
+ * Paper: section 1 (inputs and outputs of isprime_fast), sections 2-6. */
+int isprime_u64(const uint64_t *n, uint8_t *out, size_t len, void *stream);
+
+/* Many independent arrays in one call: for each a < num_arrays and
+ * i < lens[a], out_ptrs[a][i] = primality of n_ptrs[a][i].
+ *   n_ptrs, out_ptrs, lens  HOST arrays of num_arrays entries; the pointers
+ *                           they hold are device pointers owned by the caller
+ * All arrays are classified by one persistent launch sequence that the
+ * library records once as a HIP graph and replays; results are identical to
+ * num_arrays separate isprime_u64 calls.  Empty arrays are allowed.  NULL
+ * data pointers with a nonzero length -> ISP_EINVAL.  The host arrays may be
+ * reused as soon as the call returns.  At most 2^30 elements in total per
+ * call (ISP_EINVAL beyond). */
+int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
+                        const uint64_t *lens, size_t num_arrays, void *stream);
+
+/* Bytes of device workspace a call over `len` elements may use. */
+size_t isp_workspace_bytes(size_t len);
+
+/* The hipError_t (as int) behind the most recent ISP_EDEVICE. */
+int isp_last_device_error(void);
+
+/* A static string for a status code. */
+const char *isp_strerror(int status);
+
+/* Launch and algorithm parameters.  None of them changes any output bit;
+ * the autotuner picks them per workload class.  A zero field means
+ * "library default". */
+typedef struct {
+    int32_t classify_block;    /* threads per classify block: 64..1024, multiple of 64 */
+    int32_t classify_ept;      /* elements per classify thread: 1, 2, 4 or 8 */
+    int32_t filter_primes;     /* odd primes in the trial filter: -1 (none) or 1..256 */
+    int32_t mr_block;          /* threads per Miller-Rabin block: 64..256, multiple of 64 */
+    int32_t mr_bins;           /* -1: no magnitude binning pass; 1: binning on */
+    int32_t mr_window;         /* fixed window width for bases other than 2: 1..4 */
+    int32_t mr_blocks_per_cu;  /* persistent Miller-Rabin blocks per compute unit: 1..32 */
+    int32_t batch_tile;        /* elements per batched tile: 256..1048576 */
+} isp_config;
+
+/* Read / replace the process-wide configuration (ISP_EINVAL if out of range). */
+int isp_get_config(isp_config *cfg);
+int isp_set_config(const isp_config *cfg);
+
+/* Diagnostics, used by the tests.
+ * isp_montmul_u64: out[i] = a[i] * b[i] mod n[i] computed on the device by
+ * converting to Montgomery form, one Montgomery product and converting back.
+ * Requires odd n[i] >= 3 with a[i], b[i] < n[i] (otherwise out[i] is
+ * unspecified).  Device pointers.  Paper: section 2.3 (ModMultiply). */
+int isp_montmul_u64(const uint64_t *a, const uint64_t *b, const uint64_t *n, uint64_t *out,
+                    size_t len, void *stream);
+
+/* The device address and word count of the sieve table of `device` (built
+ * on first use).  The table is read-only; the pointer stays valid until
+ * isp_shutdown. */
+int isp_table(int device, const uint32_t **table, size_t *words);
+
+/* Counters of the last isprime_u64 / batched call on `stream`, read back
+ * synchronously (the stream is synchronised): survivors of the trial filter
+ * and base-2 passers sent to the remaining six bases. */
+int isp_last_counts(void *stream, uint64_t *survivors, uint64_t *candidates);
+
+/* Per-stage timing with HIP events, for measurement.  While enabled, every
+ * plain isprime_u64 call on the current device records an event before and
+ * after each of its kernels on the call's own stream, waits for the last
+ * one, and adds the elapsed times to per-stage totals (so calls become
+ * synchronous).  isp_profile(1) also resets the totals; isp_profile(0)
+ * stops recording.  Meant for one measuring thread.
+ * isp_profile_read: ms[ISP_NUM_STAGES] totals and the number of calls. */
+enum {
+    ISP_STAGE_RESET = 0,    /* counter reset kernel */
+    ISP_STAGE_CLASSIFY = 1, /* dispatch + table lookup + trial filter + compaction */
+    ISP_STAGE_BIN = 2,      /* bit-length binning */
+    ISP_STAGE_MR_BASE2 = 3, /* Miller-Rabin base 2 over all survivors */
+    ISP_STAGE_MR_REST = 4,  /* Miller-Rabin bases 325 .. 1795265022 over base-2 passers */
+    ISP_NUM_STAGES = 5
+};
+int isp_profile(int enable);
+int isp_profile_read(double *ms, uint64_t *calls);
+
+/* ---------------------------------------------------------------- serving
+ * A request loop with continuous batching.  Requests carry HOST buffers
+ * that the caller owns until isp_wait/isp_poll reports completion.  The
+ * server admits a request when an in-flight slot and `mem_budget_bytes` of
+ * device memory allow it; requests that arrive while others run are packed
+ * into the next batch as soon as capacity frees up, and batches on
+ * different streams overlap on the device.  Every result equals the plain
+ * isprime_u64 result for the same input. */
+typedef struct isp_server isp_server;
+
+typedef struct {
+    int32_t device;            /* HIP device ordinal */
+    int32_t max_inflight;      /* batches on the device at once: 1..8 (0 = 3) */
+    uint64_t mem_budget_bytes; /* device bytes for request data (0 = 1 GiB) */
+    uint64_t max_batch_elems;  /* elements per batch (0 = 4,194,304) */
+    int32_t max_batch_reqs;    /* requests per batch (0 = 1024) */
+    int32_t block_on_full;     /* 1: isp_submit waits for capacity; 0: ISP_EBUSY */
+} isp_server_config;
+
+int isp_server_create(const isp_server_config *cfg, isp_server **srv);
+/* Queue one request; `ticket` receives its id.  len may be 0.  A request
+ * larger than the memory budget is split into pieces internally. */
+int isp_submit(isp_server *srv, const uint64_t *host_n, uint8_t *host_out, size_t len,
+               uint64_t *ticket);
+/* 1 done, 0 pending, <0 error (ISP_ENOENT for an unknown or consumed ticket). */
+int isp_poll(isp_server *srv, uint64_t ticket);
+/* Block until the request is done (timeout_us < 0: no limit).  Consumes the
+ * ticket on success. */
+int isp_wait(isp_server *srv, uint64_t ticket, int64_t timeout_us);
+/* Drain every request, stop the worker threads, free the server. */
+int isp_server_destroy(isp_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISPRIME_H */

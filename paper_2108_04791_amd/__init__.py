@@ -1,0 +1,323 @@
+"""Elementwise primality of uint64 arrays on MI355X (gfx950).
+
+A thin ctypes binding over ``libisprime.so`` (built from ``csrc/`` by
+``_build.py``): argument marshalling only.  Every step of the computation
+runs in the library's HIP kernels; there is no CPU path.  PyTorch supplies
+device memory and streams.
+
+    >>> import torch, paper_2108_04791_amd as isp
+    >>> isp.isprime(torch.tensor([1, 2, 3, 4, 5], dtype=torch.uint64, device="cuda"))
+    tensor([False,  True,  True, False,  True], device='cuda:0')
+
+The inputs and outputs follow the paper's isprime_fast (section 1): an array
+of any shape in, a logical array of the same shape out.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libisprime.so")
+
+ISP_OK = 0
+ISP_EINVAL = -1
+ISP_ENOMEM = -2
+ISP_EDEVICE = -3
+ISP_EBUSY = -4
+ISP_ETIMEDOUT = -5
+ISP_ENOENT = -6
+
+_lib = None
+_lock = threading.Lock()
+
+
+class IsprimeError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        msg = "%s failed: %s (%d)" % (what, _strerror(status), status)
+        if status == ISP_EDEVICE and _lib is not None:
+            msg += ", hipError %d" % _lib.isp_last_device_error()
+        super().__init__(msg)
+
+
+class Config(ctypes.Structure):
+    """Launch and algorithm parameters (mirrors isp_config); 0 = default."""
+    _fields_ = [
+        ("classify_block", ctypes.c_int32),
+        ("classify_ept", ctypes.c_int32),
+        ("filter_primes", ctypes.c_int32),
+        ("mr_block", ctypes.c_int32),
+        ("mr_bins", ctypes.c_int32),
+        ("mr_window", ctypes.c_int32),
+        ("mr_blocks_per_cu", ctypes.c_int32),
+        ("batch_tile", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int32),
+        ("max_inflight", ctypes.c_int32),
+        ("mem_budget_bytes", ctypes.c_uint64),
+        ("max_batch_elems", ctypes.c_uint64),
+        ("max_batch_reqs", ctypes.c_int32),
+        ("block_on_full", ctypes.c_int32),
+    ]
+
+
+# name: (restype, argtypes); every symbol include/isprime.h declares
+_P, _SZ, _I, _U64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_uint64
+SIGNATURES = {
+    "isp_init": (_I, [_I]),
+    "isp_shutdown": (None, []),
+    "isprime_u64": (_I, [_P, _P, _SZ, _P]),
+    "isprime_u64_batched": (_I, [_P, _P, _P, _SZ, _P]),
+    "isp_workspace_bytes": (_SZ, [_SZ]),
+    "isp_last_device_error": (_I, []),
+    "isp_strerror": (ctypes.c_char_p, [_I]),
+    "isp_get_config": (_I, [ctypes.POINTER(Config)]),
+    "isp_set_config": (_I, [ctypes.POINTER(Config)]),
+    "isp_montmul_u64": (_I, [_P, _P, _P, _P, _SZ, _P]),
+    "isp_table": (_I, [_I, ctypes.POINTER(_P), ctypes.POINTER(_SZ)]),
+    "isp_last_counts": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
+    "isp_profile": (_I, [_I]),
+    "isp_profile_read": (_I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_U64)]),
+    "isp_server_create": (_I, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_P)]),
+    "isp_submit": (_I, [_P, _P, _P, _SZ, ctypes.POINTER(_U64)]),
+    "isp_poll": (_I, [_P, _U64]),
+    "isp_wait": (_I, [_P, _U64, ctypes.c_int64]),
+    "isp_server_destroy": (_I, [_P]),
+}
+
+
+_SERVING = {"isp_server_create", "isp_submit", "isp_poll", "isp_wait", "isp_server_destroy"}
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(
+                    "libisprime.so is not built (run `python -m paper_2108_04791_amd._build`); "
+                    "this package has no CPU fallback")
+            L = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in SIGNATURES.items():
+                if name in _SERVING and not hasattr(L, name):
+                    continue  # serving entry points not built yet
+                fn = getattr(L, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = L
+            _hip()
+        return _lib
+
+
+_hiprt = None
+
+
+def _hip() -> ctypes.CDLL:
+    """The HIP runtime the library links (for the table copy diagnostic)."""
+    global _hiprt
+    if _hiprt is None:
+        h = ctypes.CDLL("libamdhip64.so", mode=ctypes.RTLD_GLOBAL)
+        h.hipMemcpy.restype = ctypes.c_int
+        h.hipMemcpy.argtypes = [_P, _P, _SZ, ctypes.c_int]
+        _hiprt = h
+    return _hiprt
+
+
+def _strerror(status: int) -> str:
+    if _lib is None:
+        return "status %d" % status
+    return _lib.isp_strerror(status).decode()
+
+
+def _check(status: int, what: str) -> None:
+    if status != ISP_OK:
+        raise IsprimeError(status, what)
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _as_u64(t: torch.Tensor) -> torch.Tensor:
+    if t.dtype not in (torch.uint64, torch.int64):
+        raise TypeError("expected a torch.uint64 (or int64-viewed) tensor, got %s" % t.dtype)
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    return t.contiguous()
+
+
+def init(device: int | None = None) -> None:
+    """Build the device's sieve table now (otherwise on first use)."""
+    if device is None:
+        device = torch.cuda.current_device()
+    _check(lib().isp_init(device), "isp_init")
+
+
+def shutdown() -> None:
+    lib().isp_shutdown()
+
+
+def isprime_into(n: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """out[i] = 1 if n[i] is prime else 0 (uint8/bool out, same numel)."""
+    n = _as_u64(n)
+    if out.dtype not in (torch.uint8, torch.bool) or not out.is_contiguous():
+        raise TypeError("out must be a contiguous uint8 or bool tensor")
+    if out.numel() != n.numel():
+        raise ValueError("out has %d elements, n has %d" % (out.numel(), n.numel()))
+    with torch.cuda.device(n.device):
+        _check(lib().isprime_u64(n.data_ptr(), out.data_ptr(), n.numel(), _stream_handle(stream)),
+               "isprime_u64")
+    return out
+
+
+def isprime(n: torch.Tensor, stream=None) -> torch.Tensor:
+    """Boolean tensor of n's shape: True where the element is prime."""
+    n = _as_u64(n)
+    out = torch.empty(n.shape, dtype=torch.bool, device=n.device)
+    return isprime_into(n, out, stream)
+
+
+def isprime_batched(arrays, outs=None, stream=None):
+    """Many arrays in one graph-replayed launch sequence; returns the outputs."""
+    arrays = [_as_u64(a) for a in arrays]
+    if outs is None:
+        outs = [torch.empty(a.shape, dtype=torch.bool, device=a.device) for a in arrays]
+    k = len(arrays)
+    if k == 0:
+        return outs
+    NP = ctypes.c_uint64 * k
+    nps = NP(*[a.data_ptr() if a.numel() else 0 for a in arrays])
+    ops = NP(*[o.data_ptr() if o.numel() else 0 for o in outs])
+    lens = NP(*[a.numel() for a in arrays])
+    with torch.cuda.device(arrays[0].device):
+        _check(lib().isprime_u64_batched(ctypes.cast(nps, _P), ctypes.cast(ops, _P),
+                                         ctypes.cast(lens, _P), k, _stream_handle(stream)),
+               "isprime_u64_batched")
+    return outs
+
+
+def montmul(a: torch.Tensor, b: torch.Tensor, n: torch.Tensor, stream=None) -> torch.Tensor:
+    """Diagnostic: a*b mod n on the device through Montgomery form (odd n >= 3)."""
+    a, b, n = _as_u64(a), _as_u64(b), _as_u64(n)
+    out = torch.empty_like(n)
+    _check(lib().isp_montmul_u64(a.data_ptr(), b.data_ptr(), n.data_ptr(), out.data_ptr(),
+                                 n.numel(), _stream_handle(stream)), "isp_montmul_u64")
+    return out
+
+
+def table(device: int | None = None) -> torch.Tensor:
+    """A copy of the device's sieve table (uint32, 2^26 words)."""
+    if device is None:
+        device = torch.cuda.current_device()
+    ptr, words = _P(), _SZ()
+    _check(lib().isp_table(device, ctypes.byref(ptr), ctypes.byref(words)), "isp_table")
+    out = torch.empty(words.value, dtype=torch.int32, device="cuda:%d" % device)
+    torch.cuda.synchronize(device)
+    err = _hip().hipMemcpy(out.data_ptr(), ptr.value, words.value * 4, 3)  # device to device
+    if err != 0:
+        raise RuntimeError("table copy failed: hipError %d" % err)
+    return out
+
+
+def last_counts(stream=None):
+    """(trial-filter survivors, base-2 passers) of the last call on the stream."""
+    s, c = _U64(), _U64()
+    _check(lib().isp_last_counts(_stream_handle(stream), ctypes.byref(s), ctypes.byref(c)),
+           "isp_last_counts")
+    return s.value, c.value
+
+
+STAGES = ("reset", "classify", "bin", "mr_base2", "mr_rest")
+
+
+def profile(enable: bool) -> None:
+    """Per-stage HIP-event timing of plain calls (calls become synchronous)."""
+    _check(lib().isp_profile(1 if enable else 0), "isp_profile")
+
+
+def profile_read() -> dict:
+    """{stage: total ms} and the number of profiled calls under 'calls'."""
+    ms = (ctypes.c_double * len(STAGES))()
+    calls = _U64()
+    _check(lib().isp_profile_read(ms, ctypes.byref(calls)), "isp_profile_read")
+    d = dict(zip(STAGES, list(ms)))
+    d["calls"] = calls.value
+    return d
+
+
+def get_config() -> dict:
+    c = Config()
+    _check(lib().isp_get_config(ctypes.byref(c)), "isp_get_config")
+    return c.as_dict()
+
+
+def set_config(**kw) -> dict:
+    """Update some fields of the configuration; returns the previous one."""
+    prev = get_config()
+    c = Config(**{**prev, **kw})
+    _check(lib().isp_set_config(ctypes.byref(c)), "isp_set_config")
+    return prev
+
+
+def workspace_bytes(n: int) -> int:
+    return lib().isp_workspace_bytes(n)
+
+
+class Server:
+    """Continuous-batching request server over host buffers (isp_server_*)."""
+
+    def __init__(self, device: int = 0, max_inflight: int = 0, mem_budget_bytes: int = 0,
+                 max_batch_elems: int = 0, max_batch_reqs: int = 0, block_on_full: bool = True):
+        cfg = ServerConfig(device, max_inflight, mem_budget_bytes, max_batch_elems,
+                           max_batch_reqs, 1 if block_on_full else 0)
+        h = _P()
+        _check(lib().isp_server_create(ctypes.byref(cfg), ctypes.byref(h)), "isp_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, n, out) -> int:
+        """Queue host arrays n (uint64) -> out (uint8); both must stay alive."""
+        import numpy as np
+        assert n.dtype == np.uint64 and out.dtype == np.uint8 and n.size == out.size
+        assert n.flags["C_CONTIGUOUS"] and out.flags["C_CONTIGUOUS"]
+        t = _U64()
+        _check(lib().isp_submit(self._h, n.ctypes.data, out.ctypes.data, n.size, ctypes.byref(t)),
+               "isp_submit")
+        self._keep[t.value] = (n, out)
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        r = lib().isp_poll(self._h, ticket)
+        if r < 0:
+            raise IsprimeError(r, "isp_poll")
+        return r == 1
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> None:
+        _check(lib().isp_wait(self._h, ticket, timeout_us), "isp_wait")
+        self._keep.pop(ticket, None)
+
+    def close(self) -> None:
+        if self._h:
+            _check(lib().isp_server_destroy(self._h), "isp_server_destroy")
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,709 @@
+// api.hip -- the C ABI: device initialisation, the plain and batched entry
+// points, configuration and diagnostics.  Host code only enqueues work; every
+// step of the path runs in the kernels of sieve.hip, classify.hip and mr.hip.
+//
+// Plain call (isprime_u64), all on the caller's stream:
+//   reset_kernel -> classify_kernel -> bin_kernel -> mr_phase1 -> mr_phase2
+// Batched call: the same sequence with classify_batched_kernel, recorded once
+// into a HIP graph per (device, stream) together with the host-to-device copy
+// of the descriptor table, then replayed for every call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+
+using namespace isp;
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+// A plain call is split into pieces of at most this many elements, so the
+// 32-bit device counters never overflow and a workspace stays below 8 GiB.
+constexpr size_t PLAIN_PIECE = (size_t)1 << 28;
+// Elements per batched call (its survivors share one 32-bit counter).
+constexpr uint64_t BATCH_MAX_ELEMS = (uint64_t)1 << 30;
+
+std::mutex g_init_mu;
+DeviceState g_dev[MAX_DEVICES];
+std::atomic<int> g_last_err{0};
+
+std::mutex g_cfg_mu;
+isp_config g_cfg = {256, 4, 24, 256, 1, 3, 8, 8192};
+
+int fail(hipError_t e)
+{
+    g_last_err.store((int)e);
+    return e == hipErrorOutOfMemory ? ISP_ENOMEM : ISP_EDEVICE;
+}
+
+bool valid_config(const isp_config &c)
+{
+    auto blk = [](int b) { return b >= 64 && b <= 1024 && b % 64 == 0; };
+    return blk(c.classify_block) &&
+           (c.classify_ept == 1 || c.classify_ept == 2 || c.classify_ept == 4 ||
+            c.classify_ept == 8) &&
+           (c.filter_primes == -1 || (c.filter_primes >= 1 && c.filter_primes <= MAX_FILTER_PRIMES)) &&
+           blk(c.mr_block) && c.mr_block <= MR_MAX_BLOCK &&
+           (c.mr_bins == -1 || c.mr_bins == 1) && c.mr_window >= 1 &&
+           c.mr_window <= 4 && c.mr_blocks_per_cu >= 1 && c.mr_blocks_per_cu <= 32 &&
+           c.batch_tile >= 256 && c.batch_tile <= (1 << 20);
+}
+
+Tuning tuning_snapshot()
+{
+    std::lock_guard<std::mutex> g(g_cfg_mu);
+    Tuning t;
+    t.classify_block = g_cfg.classify_block;
+    t.classify_ept = g_cfg.classify_ept;
+    t.filter_primes = g_cfg.filter_primes < 0 ? 0 : g_cfg.filter_primes;
+    t.mr_block = g_cfg.mr_block;
+    t.mr_bins = g_cfg.mr_bins;
+    t.mr_window = g_cfg.mr_window;
+    t.mr_blocks_per_cu = g_cfg.mr_blocks_per_cu;
+    t.batch_tile = g_cfg.batch_tile;
+    return t;
+}
+
+bool same_tuning(const Tuning &a, const Tuning &b) { return std::memcmp(&a, &b, sizeof(Tuning)) == 0; }
+
+// ------------------------------------------------------------ workspaces
+
+struct StreamWs {
+    std::mutex mu;  // held while a call enqueues work that uses the buffers
+    int device = -1;
+    Workspace ws;
+};
+
+std::mutex g_ws_mu;
+std::map<std::pair<int, void *>, std::unique_ptr<StreamWs>> g_ws;
+std::map<std::pair<int, void *>, Counters *> g_last_ctr;
+
+void free_ws(Workspace &ws)
+{
+    if (ws.ctr)
+        (void)hipFree(ws.ctr);
+    if (ws.surv)
+        (void)hipFree(ws.surv);
+    if (ws.sorted)
+        (void)hipFree(ws.sorted);
+    ws = Workspace();
+}
+
+// Grows `ws` to hold `cap` survivors in each list.  Caller holds the
+// workspace mutex; `stream` is synchronised before old buffers are freed.
+int ensure_ws(Workspace &ws, size_t cap, hipStream_t stream)
+{
+    if (ws.ctr && ws.cap >= cap)
+        return ISP_OK;
+    size_t newcap = 1 << 16;
+    while (newcap < cap)
+        newcap <<= 1;
+    if (ws.ctr) {
+        hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess)
+            return fail(e);
+    }
+    free_ws(ws);
+    hipError_t e = hipMalloc(&ws.ctr, sizeof(Counters));
+    if (e == hipSuccess)
+        e = hipMalloc(&ws.surv, newcap * sizeof(Survivor));
+    if (e == hipSuccess)
+        e = hipMalloc(&ws.sorted, newcap * sizeof(Survivor));
+    if (e != hipSuccess) {
+        free_ws(ws);
+        return fail(e);
+    }
+    ws.cap = newcap;
+    return ISP_OK;
+}
+
+StreamWs *stream_ws(int dev, void *stream)
+{
+    std::lock_guard<std::mutex> g(g_ws_mu);
+    auto &p = g_ws[{dev, stream}];
+    if (!p) {
+        p.reset(new StreamWs());
+        p->device = dev;
+    }
+    return p.get();
+}
+
+void note_counters(int dev, void *stream, Counters *c)
+{
+    std::lock_guard<std::mutex> g(g_ws_mu);
+    g_last_ctr[{dev, stream}] = c;
+}
+
+// Per-stage event timing (isp_profile).  Used by one measuring thread.
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+hipEvent_t g_prof_ev[ISP_NUM_STAGES + 1];
+int g_prof_dev = -1;
+double g_prof_ms[ISP_NUM_STAGES];
+uint64_t g_prof_calls = 0;
+
+// Enqueues the whole plain path.
+int run_plain(const uint64_t *n, uint8_t *out, size_t len, const DeviceState &ds,
+              const Workspace &ws, const Tuning &t, hipStream_t s)
+{
+    std::unique_lock<std::mutex> pg(g_prof_mu);
+    const bool prof = g_prof_on && g_prof_dev == ds.device;
+    if (!prof)
+        pg.unlock();
+    hipError_t e = hipSuccess;
+    auto mark = [&](int k) {
+        if (prof && e == hipSuccess)
+            e = hipEventRecord(g_prof_ev[k], s);
+    };
+    mark(0);
+    if (e == hipSuccess)
+        e = launch_reset(ws.ctr, s);
+    mark(1);
+    if (e == hipSuccess)
+        e = launch_classify(n, out, len, ds, ws, t, s);
+    mark(2);
+    if (e == hipSuccess && t.mr_bins > 0)
+        e = launch_bin(ws, t, ds.cus, s);
+    mark(3);
+    if (e == hipSuccess)
+        e = launch_mr1(ws, t, ds.cus, s);
+    mark(4);
+    if (e == hipSuccess)
+        e = launch_mr2(ws, t, ds.cus, s);
+    mark(5);
+    if (prof && e == hipSuccess) {
+        e = hipEventSynchronize(g_prof_ev[ISP_NUM_STAGES]);
+        for (int k = 0; k < ISP_NUM_STAGES && e == hipSuccess; ++k) {
+            float ms = 0;
+            e = hipEventElapsedTime(&ms, g_prof_ev[k], g_prof_ev[k + 1]);
+            g_prof_ms[k] += ms;
+        }
+        ++g_prof_calls;
+    }
+    return e == hipSuccess ? ISP_OK : fail(e);
+}
+
+int current_device(int *dev)
+{
+    hipError_t e = hipGetDevice(dev);
+    if (e != hipSuccess)
+        return fail(e);
+    if (*dev < 0 || *dev >= MAX_DEVICES)
+        return ISP_EINVAL;
+    return isp_init(*dev);
+}
+
+// -------------------------------------------------------------- batched
+
+struct BatchCtx {
+    std::mutex mu;
+    int device = -1;
+    Workspace ws;
+    size_t arr_cap = 0;
+    size_t desc_bytes = 0;
+    void *d_desc = nullptr;
+    void *h_desc = nullptr;  // pinned
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    bool pending = false;  // `done` recorded after the last replay
+    Tuning tuned{};
+};
+
+std::mutex g_batch_mu;
+std::map<std::pair<int, void *>, std::unique_ptr<BatchCtx>> g_batch;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Descriptor layout: BatchDesc header, then n_ptrs, out_ptrs, lens,
+// tile_prefix (num_arrays + 1).
+size_t desc_size(size_t arrays)
+{
+    size_t b = align_up(sizeof(BatchDesc), 64);
+    b += 3 * arrays * 8;
+    b += (arrays + 1) * 4;
+    return align_up(b, 64);
+}
+
+void free_batch(BatchCtx &c)
+{
+    if (c.exec)
+        (void)hipGraphExecDestroy(c.exec);
+    if (c.d_desc)
+        (void)hipFree(c.d_desc);
+    if (c.h_desc)
+        (void)hipHostFree(c.h_desc);
+    if (c.cap_stream)
+        (void)hipStreamDestroy(c.cap_stream);
+    if (c.done)
+        (void)hipEventDestroy(c.done);
+    free_ws(c.ws);
+    c.exec = nullptr;
+    c.d_desc = c.h_desc = nullptr;
+    c.cap_stream = nullptr;
+    c.done = nullptr;
+    c.arr_cap = 0;
+    c.desc_bytes = 0;
+    c.pending = false;
+}
+
+int build_graph(BatchCtx &c, const DeviceState &ds, const Tuning &t)
+{
+    if (c.exec) {
+        (void)hipGraphExecDestroy(c.exec);
+        c.exec = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return fail(e);
+    hipError_t ee = hipMemcpyAsync(c.d_desc, c.h_desc, c.desc_bytes, hipMemcpyHostToDevice,
+                                   c.cap_stream);
+    if (ee == hipSuccess)
+        ee = launch_reset(c.ws.ctr, c.cap_stream);
+    if (ee == hipSuccess) {
+        const uint32_t grid = (uint32_t)ds.cus * (uint32_t)std::max(1, 2048 / t.classify_block);
+        ee = launch_classify_batched(reinterpret_cast<const BatchDesc *>(c.d_desc), grid, ds, c.ws,
+                                     t, c.cap_stream);
+    }
+    if (ee == hipSuccess && t.mr_bins > 0)
+        ee = launch_bin(c.ws, t, ds.cus, c.cap_stream);
+    if (ee == hipSuccess)
+        ee = launch_mr1(c.ws, t, ds.cus, c.cap_stream);
+    if (ee == hipSuccess)
+        ee = launch_mr2(c.ws, t, ds.cus, c.cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c.cap_stream, &g);
+    if (ee != hipSuccess) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return fail(ee);
+    }
+    if (e != hipSuccess)
+        return fail(e);
+    e = hipGraphInstantiate(&c.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c.exec = nullptr;
+        return fail(e);
+    }
+    c.tuned = t;
+    return ISP_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+int isp_init(int device)
+{
+    if (device < 0 || device >= MAX_DEVICES)
+        return ISP_EINVAL;
+    std::lock_guard<std::mutex> g(g_init_mu);
+    DeviceState &ds = g_dev[device];
+    if (ds.table)
+        return ISP_OK;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess)
+        return fail(e);
+    if (device >= ndev)
+        return ISP_EINVAL;
+    int prev = 0;
+    e = hipGetDevice(&prev);
+    if (e != hipSuccess)
+        return fail(e);
+    e = hipSetDevice(device);
+    if (e != hipSuccess)
+        return fail(e);
+    hipDeviceProp_t prop;
+    hipStream_t s = nullptr;
+    e = hipGetDeviceProperties(&prop, device);
+    DeviceState st;
+    st.device = device;
+    st.cus = prop.multiProcessorCount;
+    if (e == hipSuccess)
+        e = hipMalloc(&st.table, TABLE_WORDS * sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMalloc(&st.base_primes, MAX_BASE_PRIMES * sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMalloc(&st.base_count, sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMalloc(&st.filter, MAX_FILTER_PRIMES * sizeof(FilterPrime));
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = launch_base_primes(st, s);
+    if (e == hipSuccess)
+        e = launch_sieve(st, s);
+    if (e == hipSuccess)
+        e = launch_filter_consts(st, s);
+    uint32_t count = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&count, st.base_count, sizeof(count), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (s)
+        (void)hipStreamDestroy(s);
+    if (e == hipSuccess && count != 6541)
+        e = hipErrorUnknown;  // the base-prime sieve must find all 6541 odd primes < 2^16
+    if (e != hipSuccess) {
+        (void)hipFree(st.table);
+        (void)hipFree(st.base_primes);
+        (void)hipFree(st.base_count);
+        (void)hipFree(st.filter);
+        (void)hipSetDevice(prev);
+        return fail(e);
+    }
+    st.num_base_primes = (int)count;
+    ds = st;
+    (void)hipSetDevice(prev);
+    return ISP_OK;
+}
+
+void isp_shutdown(void)
+{
+    {
+        std::lock_guard<std::mutex> g(g_batch_mu);
+        for (auto &kv : g_batch) {
+            std::lock_guard<std::mutex> gg(kv.second->mu);
+            free_batch(*kv.second);
+        }
+        g_batch.clear();
+    }
+    {
+        std::lock_guard<std::mutex> g(g_ws_mu);
+        for (auto &kv : g_ws) {
+            std::lock_guard<std::mutex> gg(kv.second->mu);
+            free_ws(kv.second->ws);
+        }
+        g_ws.clear();
+        g_last_ctr.clear();
+    }
+    std::lock_guard<std::mutex> g(g_init_mu);
+    for (auto &ds : g_dev) {
+        if (!ds.table)
+            continue;
+        (void)hipFree(ds.table);
+        (void)hipFree(ds.base_primes);
+        (void)hipFree(ds.base_count);
+        (void)hipFree(ds.filter);
+        ds = DeviceState();
+    }
+}
+
+int isprime_u64(const uint64_t *n, uint8_t *out, size_t len, void *stream)
+{
+    if (len == 0)
+        return ISP_OK;
+    if (!n || !out)
+        return ISP_EINVAL;
+    int dev = 0;
+    int st = current_device(&dev);
+    if (st != ISP_OK)
+        return st;
+    const Tuning t = tuning_snapshot();
+    StreamWs *sw = stream_ws(dev, stream);
+    std::lock_guard<std::mutex> g(sw->mu);
+    hipStream_t s = (hipStream_t)stream;
+    st = ensure_ws(sw->ws, std::min(len, PLAIN_PIECE), s);
+    if (st != ISP_OK)
+        return st;
+    for (size_t off = 0; off < len && st == ISP_OK; off += PLAIN_PIECE)
+        st = run_plain(n + off, out + off, std::min(PLAIN_PIECE, len - off), g_dev[dev], sw->ws,
+                       t, s);
+    note_counters(dev, stream, sw->ws.ctr);
+    return st;
+}
+
+int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
+                        const uint64_t *lens, size_t num_arrays, void *stream)
+{
+    if (num_arrays == 0)
+        return ISP_OK;
+    if (!n_ptrs || !out_ptrs || !lens)
+        return ISP_EINVAL;
+    if (num_arrays > 0x7fffffffu)
+        return ISP_EINVAL;
+    const Tuning t = tuning_snapshot();
+    uint64_t total = 0, tiles = 0;
+    for (size_t a = 0; a < num_arrays; ++a) {
+        if (lens[a] && (!n_ptrs[a] || !out_ptrs[a]))
+            return ISP_EINVAL;
+        total += lens[a];
+        tiles += (lens[a] + (uint64_t)t.batch_tile - 1) / (uint64_t)t.batch_tile;
+    }
+    if (tiles > 0xffffffffull - 1 || total > BATCH_MAX_ELEMS)
+        return ISP_EINVAL;
+    if (total == 0)
+        return ISP_OK;
+    int dev = 0;
+    int st = current_device(&dev);
+    if (st != ISP_OK)
+        return st;
+    const DeviceState &ds = g_dev[dev];
+    hipStream_t s = (hipStream_t)stream;
+
+    BatchCtx *c;
+    {
+        std::lock_guard<std::mutex> g(g_batch_mu);
+        auto &p = g_batch[{dev, stream}];
+        if (!p) {
+            p.reset(new BatchCtx());
+            p->device = dev;
+        }
+        c = p.get();
+    }
+    std::lock_guard<std::mutex> g(c->mu);
+    hipError_t e;
+    // (Re)size the descriptor buffers and the workspace; both are baked into
+    // the graph, so any change re-records it.
+    bool rebuild = !c->exec || !same_tuning(c->tuned, t);
+    if (num_arrays > c->arr_cap || !c->ws.ctr || c->ws.cap < total) {
+        if (c->pending) {
+            e = hipEventSynchronize(c->done);
+            if (e != hipSuccess)
+                return fail(e);
+            c->pending = false;
+        }
+        size_t arr_cap = std::max<size_t>(c->arr_cap, 1024);
+        while (arr_cap < num_arrays)
+            arr_cap <<= 1;
+        if (num_arrays > c->arr_cap || !c->d_desc) {
+            if (c->d_desc)
+                (void)hipFree(c->d_desc);
+            if (c->h_desc)
+                (void)hipHostFree(c->h_desc);
+            c->d_desc = c->h_desc = nullptr;
+            c->desc_bytes = desc_size(arr_cap);
+            e = hipMalloc(&c->d_desc, c->desc_bytes);
+            if (e == hipSuccess)
+                e = hipHostMalloc(&c->h_desc, c->desc_bytes, hipHostMallocDefault);
+            if (e != hipSuccess) {
+                free_batch(*c);
+                return fail(e);
+            }
+            c->arr_cap = arr_cap;
+        }
+        st = ensure_ws(c->ws, total, s);
+        if (st != ISP_OK) {
+            free_batch(*c);
+            return st;
+        }
+        rebuild = true;
+    }
+    if (!c->cap_stream) {
+        e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&c->done, hipEventDisableTiming);
+        if (e != hipSuccess)
+            return fail(e);
+    }
+    // The previous replay's copy reads h_desc: wait for it before rewriting.
+    if (c->pending) {
+        e = hipEventSynchronize(c->done);
+        if (e != hipSuccess)
+            return fail(e);
+        c->pending = false;
+    }
+    char *h = static_cast<char *>(c->h_desc);
+    char *d = static_cast<char *>(c->d_desc);
+    const size_t off_n = align_up(sizeof(BatchDesc), 64);
+    const size_t off_o = off_n + c->arr_cap * 8;
+    const size_t off_l = off_o + c->arr_cap * 8;
+    const size_t off_p = off_l + c->arr_cap * 8;
+    BatchDesc hd;
+    hd.num_arrays = (uint32_t)num_arrays;
+    hd.num_tiles = (uint32_t)tiles;
+    hd.n_ptrs = reinterpret_cast<const uint64_t *const *>(d + off_n);
+    hd.out_ptrs = reinterpret_cast<uint8_t *const *>(d + off_o);
+    hd.lens = reinterpret_cast<const uint64_t *>(d + off_l);
+    hd.tile_prefix = reinterpret_cast<const uint32_t *>(d + off_p);
+    std::memcpy(h, &hd, sizeof(hd));
+    std::memcpy(h + off_n, n_ptrs, num_arrays * 8);
+    std::memcpy(h + off_o, out_ptrs, num_arrays * 8);
+    std::memcpy(h + off_l, lens, num_arrays * 8);
+    uint32_t *pre = reinterpret_cast<uint32_t *>(h + off_p);
+    uint32_t acc = 0;
+    for (size_t a = 0; a < num_arrays; ++a) {
+        pre[a] = acc;
+        acc += (uint32_t)((lens[a] + (uint64_t)t.batch_tile - 1) / (uint64_t)t.batch_tile);
+    }
+    pre[num_arrays] = acc;
+    if (rebuild) {
+        st = build_graph(*c, ds, t);
+        if (st != ISP_OK)
+            return st;
+    }
+    e = hipGraphLaunch(c->exec, s);
+    if (e == hipSuccess)
+        e = hipEventRecord(c->done, s);
+    if (e != hipSuccess)
+        return fail(e);
+    c->pending = true;
+    note_counters(dev, stream, c->ws.ctr);
+    return ISP_OK;
+}
+
+size_t isp_workspace_bytes(size_t len)
+{
+    size_t cap = 1 << 16;
+    while (cap < len)
+        cap <<= 1;
+    return sizeof(Counters) + 2 * cap * sizeof(Survivor);
+}
+
+int isp_last_device_error(void) { return g_last_err.load(); }
+
+const char *isp_strerror(int status)
+{
+    switch (status) {
+    case ISP_OK:
+        return "ok";
+    case ISP_EINVAL:
+        return "invalid argument";
+    case ISP_ENOMEM:
+        return "out of memory";
+    case ISP_EDEVICE:
+        return "device error";
+    case ISP_EBUSY:
+        return "busy: request not admissible now";
+    case ISP_ETIMEDOUT:
+        return "timed out";
+    case ISP_ENOENT:
+        return "unknown ticket";
+    default:
+        return "unknown status";
+    }
+}
+
+int isp_get_config(isp_config *cfg)
+{
+    if (!cfg)
+        return ISP_EINVAL;
+    std::lock_guard<std::mutex> g(g_cfg_mu);
+    *cfg = g_cfg;
+    return ISP_OK;
+}
+
+int isp_set_config(const isp_config *cfg)
+{
+    if (!cfg)
+        return ISP_EINVAL;
+    isp_config c = *cfg;
+    const isp_config d = {256, 4, 24, 256, 1, 3, 8, 8192};
+    if (!c.classify_block) c.classify_block = d.classify_block;
+    if (!c.classify_ept) c.classify_ept = d.classify_ept;
+    if (!c.filter_primes) c.filter_primes = d.filter_primes;
+    if (!c.mr_block) c.mr_block = d.mr_block;
+    if (!c.mr_bins) c.mr_bins = d.mr_bins;
+    if (!c.mr_window) c.mr_window = d.mr_window;
+    if (!c.mr_blocks_per_cu) c.mr_blocks_per_cu = d.mr_blocks_per_cu;
+    if (!c.batch_tile) c.batch_tile = d.batch_tile;
+    if (!valid_config(c))
+        return ISP_EINVAL;
+    std::lock_guard<std::mutex> g(g_cfg_mu);
+    g_cfg = c;
+    return ISP_OK;
+}
+
+int isp_montmul_u64(const uint64_t *a, const uint64_t *b, const uint64_t *n, uint64_t *out,
+                    size_t len, void *stream)
+{
+    if (len == 0)
+        return ISP_OK;
+    if (!a || !b || !n || !out)
+        return ISP_EINVAL;
+    hipError_t e = launch_montmul_test(a, b, n, out, len, (hipStream_t)stream);
+    return e == hipSuccess ? ISP_OK : fail(e);
+}
+
+int isp_profile(int enable)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(e);
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (enable && g_prof_dev != dev) {
+        if (g_prof_dev >= 0)
+            for (auto &ev : g_prof_ev)
+                (void)hipEventDestroy(ev);
+        g_prof_dev = -1;
+        for (auto &ev : g_prof_ev) {
+            e = hipEventCreate(&ev);
+            if (e != hipSuccess)
+                return fail(e);
+        }
+        g_prof_dev = dev;
+    }
+    g_prof_on = enable != 0;
+    for (double &m : g_prof_ms)
+        m = 0;
+    g_prof_calls = 0;
+    return ISP_OK;
+}
+
+int isp_profile_read(double *ms, uint64_t *calls)
+{
+    if (!ms || !calls)
+        return ISP_EINVAL;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (int k = 0; k < ISP_NUM_STAGES; ++k)
+        ms[k] = g_prof_ms[k];
+    *calls = g_prof_calls;
+    return ISP_OK;
+}
+
+int isp_table(int device, const uint32_t **table, size_t *words)
+{
+    if (!table || !words)
+        return ISP_EINVAL;
+    int st = isp_init(device);
+    if (st != ISP_OK)
+        return st;
+    *table = g_dev[device].table;
+    *words = TABLE_WORDS;
+    return ISP_OK;
+}
+
+int isp_last_counts(void *stream, uint64_t *survivors, uint64_t *candidates)
+{
+    if (!survivors || !candidates)
+        return ISP_EINVAL;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(e);
+    Counters *c = nullptr;
+    {
+        std::lock_guard<std::mutex> g(g_ws_mu);
+        auto it = g_last_ctr.find({dev, stream});
+        if (it != g_last_ctr.end())
+            c = it->second;
+    }
+    if (!c) {
+        *survivors = *candidates = 0;
+        return ISP_OK;
+    }
+    e = hipStreamSynchronize((hipStream_t)stream);
+    Counters h;
+    if (e == hipSuccess)
+        e = hipMemcpy(&h, c, sizeof(h), hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return fail(e);
+    *survivors = h.survivors;
+    *candidates = h.candidates;
+    return ISP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,172 @@
+// sieve.hip -- the device-resident odd-only sieve table for n < 2^32, and the
+// small constant tables derived from it.
+//
+// Paper: section 1 describes the sieve of Eratosthenes (cross off the
+// multiples of each prime); section 4 restricts candidates to odd numbers
+// (the 2-wheel); section 6.1.3 sieves once up to the maximum and then only
+// tests membership.  Here the sieve runs once per device up to 2^32 and
+// membership is a single bit.
+//
+// Layout: uint32_t table[2^26]; bit (i & 31) of word (i >> 5) is 1 iff the
+// odd number 2i+1 is prime.  256 MiB in HBM, read-only after the build.
+//
+// Kernels:
+//   base_primes_kernel  one workgroup sieves the 32768 odd numbers below 2^16
+//                       in LDS and writes the 6541 odd primes in order.
+//   sieve_kernel        one workgroup per 32 KiB segment (2^18 odd numbers).
+//                       Multiples of 3..31 come from a periodic word mask
+//                       (pre-sieve); each larger base prime p is crossed off
+//                       from max(p^2, segment start) by a whole wavefront,
+//                       lane l taking the multiples l, l+64, l+128, ... of
+//                       the stride p (in bit units), with LDS atomic ANDs.
+//   filter_consts_kernel  inverse mod 2^64 and floor((2^64-1)/p) of the first
+//                       odd primes, for the division-free divisibility test.
+#include "internal.h"
+#include "mont.h"
+
+namespace isp {
+
+namespace {
+
+constexpr int SEG_WORDS = 8192;        // 32 KiB of LDS per workgroup
+constexpr int SEG_BITS = SEG_WORDS * 32;
+constexpr int SIEVE_THREADS = 1024;
+constexpr int FIRST_CROSSED = 10;      // index of 37 in the odd-prime list
+
+// Bits j < 32 with j = 0 (mod p).
+__device__ __forceinline__ uint32_t period_mask(uint32_t p)
+{
+    uint32_t m = 0;
+    for (uint32_t j = 0; j < 32; j += p)
+        m |= 1u << j;
+    return m;
+}
+
+// Inclusive scan of one value per lane across a 64-lane wavefront.
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x, int lane)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o)
+            x += y;
+    }
+    return x;
+}
+
+__global__ void __launch_bounds__(1024) base_primes_kernel(uint32_t *primes, uint32_t *count)
+{
+    __shared__ uint32_t bits[1024];  // bit i <-> 2i+1 < 65536
+    __shared__ uint32_t wave_sum[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    bits[tid] = tid == 0 ? 0xfffffffeu : 0xffffffffu;  // 1 is not prime
+    __syncthreads();
+    // Crossing off the multiples of composite odd p as well is harmless.
+    for (uint32_t p = 3; p * p < 65536; p += 2)
+        for (uint32_t m = p * p + 2 * p * tid; m < 65536; m += 2 * p * blockDim.x)
+            atomicAnd(&bits[m >> 6], ~(1u << ((m >> 1) & 31)));
+    __syncthreads();
+    const uint32_t w = bits[tid];
+    const uint32_t c = __popc(w);
+    const uint32_t incl = wave_inclusive_scan(c, lane);
+    if (lane == 63)
+        wave_sum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < wave; ++k)
+        before += wave_sum[k];
+    uint32_t pos = before + incl - c;
+    for (uint32_t b = 0; b < 32; ++b)
+        if ((w >> b) & 1)
+            primes[pos++] = 2 * (32 * tid + b) + 1;
+    if (tid == blockDim.x - 1)
+        *count = pos;
+}
+
+__global__ void __launch_bounds__(SIEVE_THREADS) sieve_kernel(uint32_t *__restrict__ table,
+                                                              const uint32_t *__restrict__ primes,
+                                                              const uint32_t *__restrict__ pcount)
+{
+    __shared__ uint32_t seg[SEG_WORDS];
+    const uint32_t w0 = blockIdx.x * SEG_WORDS;   // first table word of the segment
+    const uint32_t lo = 2u * (w0 * 32u) + 1u;     // smallest odd number in it
+
+    // Pre-sieve 3..31: in word w, bit j stands for 2(32w+j)+1, which p
+    // divides iff j = (p-1)/2 - 32w (mod p).
+    constexpr uint32_t SMALL[10] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
+    for (int k = threadIdx.x; k < SEG_WORDS; k += blockDim.x) {
+        const uint32_t w = w0 + k;
+        uint32_t word = 0xffffffffu;
+#pragma unroll
+        for (int q = 0; q < 10; ++q) {
+            const uint32_t p = SMALL[q];
+            const uint32_t r = ((p - 1) / 2 + p - (32u * w) % p) % p;
+            word &= ~(period_mask(p) << r);
+        }
+        seg[k] = word;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        uint32_t keep = 0;  // the pre-sieved primes themselves stay prime
+#pragma unroll
+        for (int q = 0; q < 10; ++q)
+            keep |= 1u << ((SMALL[q] - 1) / 2);
+        seg[0] = (seg[0] | keep) & ~1u;  // and 1 is not prime
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int np = (int)*pcount;
+    const uint64_t hi = (uint64_t)lo + 2ull * SEG_BITS;  // exclusive
+    for (int k = FIRST_CROSSED + wave; k < np; k += nwaves) {
+        const uint32_t p = primes[k];
+        uint64_t start = (uint64_t)p * p;
+        if (start >= hi)
+            break;  // primes increase, so every later one starts beyond too
+        if (start < lo) {
+            uint32_t q = (uint32_t)(((uint64_t)lo + p - 1) / p);
+            q |= 1u;  // odd multiples only
+            start = (uint64_t)q * p;
+        }
+        for (uint32_t j = (uint32_t)((start - lo) >> 1) + (uint32_t)lane * p; j < (uint32_t)SEG_BITS;
+             j += 64u * p)
+            atomicAnd(&seg[j >> 5], ~(1u << (j & 31)));
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < SEG_WORDS; k += blockDim.x)
+        table[w0 + k] = seg[k];
+}
+
+__global__ void filter_consts_kernel(const uint32_t *__restrict__ primes, FilterPrime *__restrict__ f)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= MAX_FILTER_PRIMES)
+        return;
+    const uint64_t p = primes[k];
+    f[k].inv = inv64(p);
+    f[k].lim = ~(uint64_t)0 / p;
+}
+
+}  // namespace
+
+hipError_t launch_base_primes(DeviceState &ds, hipStream_t s)
+{
+    base_primes_kernel<<<1, 1024, 0, s>>>(ds.base_primes, ds.base_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_sieve(DeviceState &ds, hipStream_t s)
+{
+    static_assert(TABLE_WORDS % SEG_WORDS == 0, "segments tile the table");
+    sieve_kernel<<<(unsigned)(TABLE_WORDS / SEG_WORDS), SIEVE_THREADS, 0, s>>>(
+        ds.table, ds.base_primes, ds.base_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter_consts(DeviceState &ds, hipStream_t s)
+{
+    filter_consts_kernel<<<(MAX_FILTER_PRIMES + 255) / 256, 256, 0, s>>>(ds.base_primes, ds.filter);
+    return hipGetLastError();
+}
+
+}  // namespace isp

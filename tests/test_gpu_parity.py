@@ -1,0 +1,218 @@
+"""GPU parity: the HIP path against the oracle, element by element, through
+the C ABI.  Tolerance is zero mismatching bytes everywhere (primality is a
+function; there is no rounding anywhere on either side)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+U64 = (1 << 64) - 1
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def isp():
+    import paper_2108_04791_amd as isp
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    isp.init()
+    return isp
+
+
+def to_dev(a: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def gpu_isprime(isp, a: np.ndarray) -> np.ndarray:
+    out = isp.isprime(to_dev(a))
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.uint8)
+
+
+def expect(a: np.ndarray, use_table=None) -> np.ndarray:
+    out, _ = oracle.isprime_array(a, nthreads=NTHREADS, use_table=use_table)
+    return out
+
+
+def assert_same(a, got, exp, what):
+    bad = np.nonzero(got != exp)[0]
+    if bad.size:
+        i = bad[:10]
+        raise AssertionError("%s: %d mismatches, first %s values %s gpu %s oracle %s" % (
+            what, bad.size, i.tolist(), a[i].tolist(), got[i].tolist(), exp[i].tolist()))
+
+
+EDGES = [0, 1, 2, 3, 4, 5, 9, 15, 25, 49, 121, 2047, 65521, 65535, 65537, (1 << 31) - 1,
+         (1 << 32) - 5, (1 << 32) - 3, (1 << 32) - 1, 1 << 32, (1 << 32) + 1, (1 << 32) + 15,
+         (1 << 32) + 17, 4294967291 * 4294967279, (1 << 61) - 1, (1 << 62) + 135,
+         (1 << 63) - 25, (1 << 63) + 29, (1 << 63) + 1, U64 - 58, U64 - 2, U64 - 1, U64,
+         3215031751, 3825123056546413051, 341550071728321, 2152302898747, 3474749660383,
+         18446744073709551557, 18446744073709551533, 4611686018427388039,
+         6700417 * 641, 1000000007 * 998244353]
+
+
+def test_worked_example(isp):
+    """Section 1: [1, 2, 3, 4, 5] -> 0 1 1 0 1, shape kept."""
+    t = torch.tensor([[1, 2, 3, 4, 5]], dtype=torch.int64, device="cuda")
+    out = isp.isprime(t)
+    assert out.shape == t.shape and out.dtype == torch.bool
+    assert out.cpu().int().tolist() == [[0, 1, 1, 0, 1]]
+
+
+def test_table_equals_oracle(isp, oracle_table):
+    tab = isp.table().cpu().numpy().view(np.uint32)
+    assert tab.size == 1 << 26
+    assert int(tab[0]) == 0x64B4CB6E
+    neq = np.nonzero(tab != oracle_table)[0]
+    assert neq.size == 0, "table words differ at %s" % neq[:10].tolist()
+
+
+def test_montmul_against_python(isp):
+    rng = np.random.default_rng(11)
+    mods = [(1 << 32) + 15, (1 << 63) - 25, (1 << 63) + 29, U64 - 58, U64, 3, 5, 65537,
+            (1 << 61) - 1]
+    mods += [int(x) | 1 for x in rng.integers(0, 1 << 63, size=200, dtype=np.uint64) * 2 + 1]
+    A, B, N = [], [], []
+    for n in mods:
+        vals = [0, 1, 2 % n, n - 1, n - 2, n // 2] + [int(x) % n for x in
+                                                     rng.integers(0, 1 << 63, size=8, dtype=np.uint64)]
+        for a in vals:
+            for b in vals[:6]:
+                A.append(a)
+                B.append(b)
+                N.append(n)
+    a, b, n = (np.array(x, dtype=np.uint64) for x in (A, B, N))
+    got = isp.montmul(to_dev(a), to_dev(b), to_dev(n)).cpu().numpy().view(np.uint64)
+    exp = np.array([x * y % m for x, y, m in zip(A, B, N)], dtype=np.uint64)
+    assert_same(a, got, exp, "montmul")
+
+
+def test_edge_values(isp):
+    a = np.array(EDGES, dtype=np.uint64)
+    got = gpu_isprime(isp, a)
+    assert_same(a, got, expect(a, use_table=False), "edges")
+    # known verdicts
+    v = dict(zip(EDGES, got.tolist()))
+    assert v[(1 << 61) - 1] == 1 and v[U64 - 58] == 1 and v[(1 << 32) + 15] == 1
+    assert v[2047] == 0 and v[3215031751] == 0 and v[(1 << 32) + 1] == 0 and v[U64] == 0
+
+
+def test_all_below_2_20(isp):
+    a = np.arange(1 << 20, dtype=np.uint64)
+    assert_same(a, gpu_isprime(isp, a), expect(a, use_table=False), "0..2^20")
+
+
+def test_window_around_table_bound(isp):
+    a = np.arange((1 << 32) - 50000, (1 << 32) + 50000, dtype=np.uint64)
+    assert_same(a, gpu_isprime(isp, a), expect(a, use_table=False), "2^32 +- 50000")
+
+
+def test_c1_full(isp):
+    a = W.c1_uniform20()
+    assert_same(a, gpu_isprime(isp, a), expect(a, use_table=False), "C1")
+
+
+@pytest.mark.parametrize("size", [1, 2, 3, 63, 64, 65, 255, 256, 257, 1023, 1024, 1025, 4097,
+                                  100003])
+def test_ragged_sizes(isp, size):
+    a = W.c3_mixed(size, start=size * 7)
+    a[: min(size, 8)] = np.array(EDGES[-8:], dtype=np.uint64)[: min(size, 8)]
+    assert_same(a, gpu_isprime(isp, a), expect(a, use_table=False), "ragged %d" % size)
+
+
+def test_unaligned_views(isp):
+    a = W.c2_mr64(5000)
+    t = to_dev(a)
+    for off in (1, 3):
+        out = isp.isprime(t[off:])
+        torch.cuda.synchronize()
+        assert_same(a[off:], out.cpu().numpy().astype(np.uint8), expect(a[off:]), "offset %d" % off)
+
+
+def test_empty_and_invalid(isp):
+    t = torch.empty(0, dtype=torch.int64, device="cuda")
+    assert isp.isprime(t).numel() == 0
+    L = isp.lib()
+    assert L.isprime_u64(None, None, 0, None) == isp.ISP_OK
+    assert L.isprime_u64(None, None, 5, None) == isp.ISP_EINVAL
+    assert L.isprime_u64(t.data_ptr() or 8, None, 5, None) == isp.ISP_EINVAL
+    with pytest.raises(isp.IsprimeError):
+        isp.set_config(classify_ept=3)
+
+
+def test_c2_full(isp):
+    a = W.c2_mr64()
+    got = gpu_isprime(isp, a)
+    assert_same(a, got, expect(a), "C2")
+    assert 0.02 < got.mean() < 0.05
+
+
+def test_c3_full(isp, oracle_table):
+    a = W.c3_mixed()
+    got = gpu_isprime(isp, a)
+    assert_same(a, got, expect(a, use_table=True), "C3")
+
+
+def test_counts_match_host_accounting(isp):
+    """Survivors = odd elements >= 2^32 with no factor among the filter
+    primes; candidates = survivors passing the base-2 round."""
+    a = W.c2_mr64(1 << 16)
+    cfg = isp.get_config()
+    gpu_isprime(isp, a)
+    surv, cand = isp.last_counts()
+    F = cfg["filter_primes"]
+    primes = [p for p in range(3, 2000, 2) if oracle.trial_is_prime(p)][:F]
+    big = a[(a >= np.uint64(1 << 32)) & ((a & np.uint64(1)) == 1)]
+    keep = np.ones(big.size, dtype=bool)
+    for p in primes:
+        keep &= (big % np.uint64(p)) != 0
+    assert surv == int(keep.sum())
+    assert cand == sum(oracle.strong_probable_prime(int(n), 2) for n in big[keep])
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(classify_ept=1, classify_block=64),
+    dict(classify_ept=2, classify_block=1024),
+    dict(classify_ept=8, classify_block=128),
+    dict(filter_primes=-1),
+    dict(filter_primes=256),
+    dict(mr_bins=-1),
+    dict(mr_window=1), dict(mr_window=2), dict(mr_window=4),
+    dict(mr_block=64, mr_blocks_per_cu=1),
+    dict(mr_block=128, mr_blocks_per_cu=32),
+])
+def test_configs_do_not_change_bits(isp, cfg):
+    a = np.concatenate([np.array(EDGES, dtype=np.uint64), W.c3_mixed(30011, start=99),
+                        W.chernick_values()])
+    prev = isp.set_config(**cfg)
+    try:
+        got = gpu_isprime(isp, a)
+    finally:
+        isp.set_config(**prev)
+    assert_same(a, got, expect(a, use_table=False), str(cfg))
+
+
+def test_permutation_metamorphic(isp):
+    a = W.c3_mixed(50000, start=12345)
+    perm = np.random.default_rng(5).permutation(a.size)
+    g1 = gpu_isprime(isp, a)
+    g2 = gpu_isprime(isp, a[perm])
+    assert np.array_equal(g1[perm], g2)
+
+
+def test_two_streams(isp):
+    a = W.c2_mr64(300000, start=777)
+    b = W.c3_mixed(300000, start=888)
+    ta, tb = to_dev(a), to_dev(b)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    oa = isp.isprime(ta, stream=s1)
+    ob = isp.isprime(tb, stream=s2)
+    torch.cuda.synchronize()
+    assert_same(a, oa.cpu().numpy().astype(np.uint8), expect(a), "stream 1")
+    assert_same(b, ob.cpu().numpy().astype(np.uint8), expect(b, use_table=False), "stream 2")

@@ -1,0 +1,75 @@
+"""CPU-side checks of the C ABI library: it loads, exports every symbol the
+header declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "isprime.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*\b((?:isp|isprime)_[a-z_0-9]+)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def isp():
+    import paper_2108_04791_amd as isp
+    if not os.path.exists(isp.LIB_PATH):
+        from paper_2108_04791_amd import _build
+        _build.build()
+    return isp
+
+
+def test_header_parses():
+    names = declared_functions()
+    for n in ("isprime_u64", "isprime_u64_batched", "isp_init", "isp_server_create"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(isp):
+    L = ctypes.CDLL(isp.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(declared_functions()) == set(isp.SIGNATURES)
+
+
+def test_argument_errors_without_device(isp):
+    L = isp.lib()
+    assert L.isprime_u64(None, None, 0, None) == isp.ISP_OK
+    assert L.isprime_u64(None, None, 7, None) == isp.ISP_EINVAL
+    assert L.isp_montmul_u64(None, None, None, None, 3, None) == isp.ISP_EINVAL
+    assert L.isp_init(-1) == isp.ISP_EINVAL
+    assert L.isprime_u64_batched(None, None, None, 0, None) == isp.ISP_OK
+    assert L.isp_strerror(isp.ISP_EBUSY).decode().startswith("busy")
+    assert L.isp_workspace_bytes(1 << 20) >= 32 * (1 << 20)
+
+
+def test_config_validation(isp):
+    prev = isp.get_config()
+    try:
+        for bad in (dict(classify_block=100), dict(classify_ept=3), dict(filter_primes=300),
+                    dict(mr_window=5), dict(mr_bins=2), dict(batch_tile=10),
+                    dict(mr_block=512)):
+            with pytest.raises(isp.IsprimeError):
+                isp.set_config(**bad)
+        isp.set_config(mr_window=4)
+        assert isp.get_config()["mr_window"] == 4
+    finally:
+        isp.set_config(**prev)
+    assert isp.get_config() == prev
+
+
+def test_no_oracle_in_product_path():
+    """The product package never imports or loads the oracle."""
+    pkg = os.path.join(ROOT, "paper_2108_04791_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "liboracle" not in text, f
