@@ -83,7 +83,8 @@ int isprime_u64(const uint64_t *n, uint8_t *out, size_t len, void *stream);
  * num_arrays separate isprime_u64 calls.  Empty arrays are allowed.  NULL
  * data pointers with a nonzero length -> ISP_EINVAL.  The host arrays may be
  * reused as soon as the call returns.  At most 2^30 elements in total per
- * call (ISP_EINVAL beyond). */
+ * call (ISP_EINVAL beyond); the workspace kept for the stream grows to the
+ * largest call seen. */
 int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
                         const uint64_t *lens, size_t num_arrays, void *stream);
 
@@ -100,14 +101,14 @@ const char *isp_strerror(int status);
  * the autotuner picks them per workload class.  A zero field means
  * "library default". */
 typedef struct {
-    int32_t classify_block;    /* threads per classify block: 64..1024, multiple of 64 */
-    int32_t classify_ept;      /* elements per classify thread: 1, 2, 4 or 8 */
-    int32_t filter_primes;     /* odd primes in the trial filter: -1 (none) or 1..256 */
-    int32_t mr_block;          /* threads per Miller-Rabin block: 64..256, multiple of 64 */
-    int32_t mr_bins;           /* -1: no magnitude binning pass; 1: binning on */
-    int32_t mr_window;         /* fixed window width for bases other than 2: 1..4 */
-    int32_t mr_blocks_per_cu;  /* persistent Miller-Rabin blocks per compute unit: 1..32 */
-    int32_t batch_tile;        /* elements per batched tile: 256..1048576 */
+    int32_t classify_block;         /* threads per classify block: 64..1024, multiple of 64 */
+    int32_t classify_ept;           /* elements per classify thread and pass: 1, 2, 4 or 8 */
+    int32_t classify_blocks_per_cu; /* classify grid = CUs x this (at most 4096): 1..16 */
+    int32_t filter_primes;          /* odd primes in the trial filter: -1 (none) or 1..256 */
+    int32_t sort_survivors;         /* 1: order survivors by bit length; -1: keep input order */
+    int32_t mr_block;               /* threads per Miller-Rabin block: 64..256, multiple of 64 */
+    int32_t mr_blocks_per_cu;       /* Miller-Rabin grids = CUs x this (at most 4096): 1..16 */
+    int32_t mr_window;              /* fixed window width for bases other than 2: 1..4 */
 } isp_config;
 
 /* Read / replace the process-wide configuration (ISP_EINVAL if out of range). */
@@ -140,12 +141,10 @@ int isp_last_counts(void *stream, uint64_t *survivors, uint64_t *candidates);
  * stops recording.  Meant for one measuring thread.
  * isp_profile_read: ms[ISP_NUM_STAGES] totals and the number of calls. */
 enum {
-    ISP_STAGE_RESET = 0,    /* counter reset kernel */
-    ISP_STAGE_CLASSIFY = 1, /* dispatch + table lookup + trial filter + compaction */
-    ISP_STAGE_BIN = 2,      /* bit-length binning */
-    ISP_STAGE_MR_BASE2 = 3, /* Miller-Rabin base 2 over all survivors */
-    ISP_STAGE_MR_REST = 4,  /* Miller-Rabin bases 325 .. 1795265022 over base-2 passers */
-    ISP_NUM_STAGES = 5
+    ISP_STAGE_CLASSIFY = 0, /* dispatch + table lookup + trial filter + compaction */
+    ISP_STAGE_MR_BASE2 = 1, /* Miller-Rabin base 2 over all survivors */
+    ISP_STAGE_MR_REST = 2,  /* Miller-Rabin bases 325 .. 1795265022 over base-2 passers */
+    ISP_NUM_STAGES = 3
 };
 int isp_profile(int enable);
 int isp_profile_read(double *ms, uint64_t *calls);

@@ -49,12 +49,12 @@ class Config(ctypes.Structure):
     _fields_ = [
         ("classify_block", ctypes.c_int32),
         ("classify_ept", ctypes.c_int32),
+        ("classify_blocks_per_cu", ctypes.c_int32),
         ("filter_primes", ctypes.c_int32),
+        ("sort_survivors", ctypes.c_int32),
         ("mr_block", ctypes.c_int32),
-        ("mr_bins", ctypes.c_int32),
-        ("mr_window", ctypes.c_int32),
         ("mr_blocks_per_cu", ctypes.c_int32),
-        ("batch_tile", ctypes.c_int32),
+        ("mr_window", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -241,7 +241,7 @@ def last_counts(stream=None):
     return s.value, c.value
 
 
-STAGES = ("reset", "classify", "bin", "mr_base2", "mr_rest")
+STAGES = ("classify", "mr_base2", "mr_rest")
 
 
 def profile(enable: bool) -> None:

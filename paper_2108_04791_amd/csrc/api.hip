@@ -3,10 +3,12 @@
 // step of the path runs in the kernels of sieve.hip, classify.hip and mr.hip.
 //
 // Plain call (isprime_u64), all on the caller's stream:
-//   reset_kernel -> classify_kernel -> bin_kernel -> mr_phase1 -> mr_phase2
-// Batched call: the same sequence with classify_batched_kernel, recorded once
-// into a HIP graph per (device, stream) together with the host-to-device copy
-// of the descriptor table, then replayed for every call.
+//   classify_kernel -> mr_phase1_kernel -> mr_phase2_kernel
+// Each kernel writes one count per workgroup and the next scans them, so no
+// counter needs clearing and no kernel uses a global atomic.
+// Batched call: the same three kernels over the virtual concatenation of the
+// arrays, recorded once into a HIP graph per (device, stream) together with
+// the host-to-device copy of the descriptor table, then replayed per call.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,7 +38,8 @@ DeviceState g_dev[MAX_DEVICES];
 std::atomic<int> g_last_err{0};
 
 std::mutex g_cfg_mu;
-isp_config g_cfg = {256, 4, 24, 256, 1, 3, 8, 8192};
+constexpr isp_config DEFAULT_CONFIG = {256, 4, 8, 24, 1, 256, 8, 3};
+isp_config g_cfg = DEFAULT_CONFIG;
 
 int fail(hipError_t e)
 {
@@ -46,15 +49,15 @@ int fail(hipError_t e)
 
 bool valid_config(const isp_config &c)
 {
-    auto blk = [](int b) { return b >= 64 && b <= 1024 && b % 64 == 0; };
-    return blk(c.classify_block) &&
+    auto blk = [](int b, int mx) { return b >= 64 && b <= mx && b % 64 == 0; };
+    return blk(c.classify_block, 1024) &&
            (c.classify_ept == 1 || c.classify_ept == 2 || c.classify_ept == 4 ||
             c.classify_ept == 8) &&
+           c.classify_blocks_per_cu >= 1 && c.classify_blocks_per_cu <= 16 &&
            (c.filter_primes == -1 || (c.filter_primes >= 1 && c.filter_primes <= MAX_FILTER_PRIMES)) &&
-           blk(c.mr_block) && c.mr_block <= MR_MAX_BLOCK &&
-           (c.mr_bins == -1 || c.mr_bins == 1) && c.mr_window >= 1 &&
-           c.mr_window <= 4 && c.mr_blocks_per_cu >= 1 && c.mr_blocks_per_cu <= 32 &&
-           c.batch_tile >= 256 && c.batch_tile <= (1 << 20);
+           (c.sort_survivors == -1 || c.sort_survivors == 1) && blk(c.mr_block, MR_MAX_BLOCK) &&
+           c.mr_blocks_per_cu >= 1 && c.mr_blocks_per_cu <= 16 && c.mr_window >= 1 &&
+           c.mr_window <= 4;
 }
 
 Tuning tuning_snapshot()
@@ -63,14 +66,16 @@ Tuning tuning_snapshot()
     Tuning t;
     t.classify_block = g_cfg.classify_block;
     t.classify_ept = g_cfg.classify_ept;
+    t.classify_blocks_per_cu = g_cfg.classify_blocks_per_cu;
     t.filter_primes = g_cfg.filter_primes < 0 ? 0 : g_cfg.filter_primes;
+    t.sort_survivors = g_cfg.sort_survivors > 0;
     t.mr_block = g_cfg.mr_block;
-    t.mr_bins = g_cfg.mr_bins;
-    t.mr_window = g_cfg.mr_window;
     t.mr_blocks_per_cu = g_cfg.mr_blocks_per_cu;
-    t.batch_tile = g_cfg.batch_tile;
+    t.mr_window = g_cfg.mr_window;
     return t;
 }
+
+unsigned grid_of(int cus, int per_cu) { return (unsigned)std::min(MAX_GRID, std::max(1, cus * per_cu)); }
 
 bool same_tuning(const Tuning &a, const Tuning &b) { return std::memcmp(&a, &b, sizeof(Tuning)) == 0; }
 
@@ -84,39 +89,47 @@ struct StreamWs {
 
 std::mutex g_ws_mu;
 std::map<std::pair<int, void *>, std::unique_ptr<StreamWs>> g_ws;
-std::map<std::pair<int, void *>, Counters *> g_last_ctr;
+// The counts of the last call per (device, stream): classify and base-2
+// grids and the workspace that holds them.
+struct LastCounts {
+    const uint32_t *counts = nullptr;
+    unsigned grid_c = 0, grid1 = 0;
+};
+std::map<std::pair<int, void *>, LastCounts> g_last;
 
 void free_ws(Workspace &ws)
 {
-    if (ws.ctr)
-        (void)hipFree(ws.ctr);
     if (ws.surv)
         (void)hipFree(ws.surv);
-    if (ws.sorted)
-        (void)hipFree(ws.sorted);
+    if (ws.cand)
+        (void)hipFree(ws.cand);
+    if (ws.counts)
+        (void)hipFree(ws.counts);
     ws = Workspace();
 }
 
-// Grows `ws` to hold `cap` survivors in each list.  Caller holds the
+// Grows `ws` to serve calls of up to `cap` elements.  Caller holds the
 // workspace mutex; `stream` is synchronised before old buffers are freed.
 int ensure_ws(Workspace &ws, size_t cap, hipStream_t stream)
 {
-    if (ws.ctr && ws.cap >= cap)
+    if (ws.surv && ws.cap >= cap)
         return ISP_OK;
     size_t newcap = 1 << 16;
     while (newcap < cap)
         newcap <<= 1;
-    if (ws.ctr) {
+    if (ws.surv) {
         hipError_t e = hipStreamSynchronize(stream);
         if (e != hipSuccess)
             return fail(e);
     }
     free_ws(ws);
-    hipError_t e = hipMalloc(&ws.ctr, sizeof(Counters));
+    // classify regions are rounded up to 64 elements each; passer regions
+    // to one element each
+    hipError_t e = hipMalloc(&ws.surv, (newcap + 64 * (size_t)MAX_GRID) * sizeof(Survivor));
     if (e == hipSuccess)
-        e = hipMalloc(&ws.surv, newcap * sizeof(Survivor));
+        e = hipMalloc(&ws.cand, (newcap + (size_t)MAX_GRID) * sizeof(Survivor));
     if (e == hipSuccess)
-        e = hipMalloc(&ws.sorted, newcap * sizeof(Survivor));
+        e = hipMalloc(&ws.counts, 2 * (size_t)MAX_GRID * sizeof(uint32_t));
     if (e != hipSuccess) {
         free_ws(ws);
         return fail(e);
@@ -136,10 +149,32 @@ StreamWs *stream_ws(int dev, void *stream)
     return p.get();
 }
 
-void note_counters(int dev, void *stream, Counters *c)
+void note_counts(int dev, void *stream, const Workspace &ws, unsigned grid_c, unsigned grid1)
 {
     std::lock_guard<std::mutex> g(g_ws_mu);
-    g_last_ctr[{dev, stream}] = c;
+    g_last[{dev, stream}] = LastCounts{ws.counts, grid_c, grid1};
+}
+
+// Arguments of the three kernels for one call.
+void make_args(const DeviceState &ds, const Workspace &ws, const Tuning &t, ClassifyArgs &ca,
+               MrArgs &ma, unsigned &grid_c, unsigned &grid1)
+{
+    grid_c = grid_of(ds.cus, t.classify_blocks_per_cu);
+    grid1 = grid_of(ds.cus, t.mr_blocks_per_cu);
+    ca = ClassifyArgs();
+    ca.table = ds.table;
+    ca.filter = ds.filter;
+    ca.nfilter = t.filter_primes;
+    ca.sorted = t.sort_survivors;
+    ca.surv = ws.surv;
+    ca.counts = ws.counts;
+    ma = MrArgs();
+    ma.grid_c = grid_c;
+    ma.surv = ws.surv;
+    ma.counts_c = ws.counts;
+    ma.grid1 = grid1;
+    ma.cand = ws.cand;
+    ma.counts1 = ws.counts + MAX_GRID;
 }
 
 // Per-stage event timing (isp_profile).  Used by one measuring thread.
@@ -158,6 +193,14 @@ int run_plain(const uint64_t *n, uint8_t *out, size_t len, const DeviceState &ds
     const bool prof = g_prof_on && g_prof_dev == ds.device;
     if (!prof)
         pg.unlock();
+    ClassifyArgs ca;
+    MrArgs ma;
+    unsigned grid_c, grid1;
+    make_args(ds, ws, t, ca, ma, grid_c, grid1);
+    ca.n = n;
+    ca.out = out;
+    ca.total = len;
+    ma.total = len;
     hipError_t e = hipSuccess;
     auto mark = [&](int k) {
         if (prof && e == hipSuccess)
@@ -165,20 +208,14 @@ int run_plain(const uint64_t *n, uint8_t *out, size_t len, const DeviceState &ds
     };
     mark(0);
     if (e == hipSuccess)
-        e = launch_reset(ws.ctr, s);
+        e = launch_classify(ca, grid_c, t.classify_block, t.classify_ept, s);
     mark(1);
     if (e == hipSuccess)
-        e = launch_classify(n, out, len, ds, ws, t, s);
+        e = launch_mr1(ma, t.mr_block, s);
     mark(2);
-    if (e == hipSuccess && t.mr_bins > 0)
-        e = launch_bin(ws, t, ds.cus, s);
+    if (e == hipSuccess)
+        e = launch_mr2(ma, grid1, t.mr_block, t.mr_window, s);
     mark(3);
-    if (e == hipSuccess)
-        e = launch_mr1(ws, t, ds.cus, s);
-    mark(4);
-    if (e == hipSuccess)
-        e = launch_mr2(ws, t, ds.cus, s);
-    mark(5);
     if (prof && e == hipSuccess) {
         e = hipEventSynchronize(g_prof_ev[ISP_NUM_STAGES]);
         for (int k = 0; k < ISP_NUM_STAGES && e == hipSuccess; ++k) {
@@ -216,6 +253,7 @@ struct BatchCtx {
     hipEvent_t done = nullptr;
     bool pending = false;  // `done` recorded after the last replay
     Tuning tuned{};
+    unsigned grid_c = 0, grid1 = 0;
 };
 
 std::mutex g_batch_mu;
@@ -223,13 +261,12 @@ std::map<std::pair<int, void *>, std::unique_ptr<BatchCtx>> g_batch;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// Descriptor layout: BatchDesc header, then n_ptrs, out_ptrs, lens,
-// tile_prefix (num_arrays + 1).
+// Descriptor layout: BatchDesc header, then n_ptrs, out_ptrs (num_arrays
+// each) and elem_prefix (num_arrays + 1).
 size_t desc_size(size_t arrays)
 {
     size_t b = align_up(sizeof(BatchDesc), 64);
-    b += 3 * arrays * 8;
-    b += (arrays + 1) * 4;
+    b += 3 * arrays * 8 + 8;
     return align_up(b, 64);
 }
 
@@ -261,24 +298,24 @@ int build_graph(BatchCtx &c, const DeviceState &ds, const Tuning &t)
         (void)hipGraphExecDestroy(c.exec);
         c.exec = nullptr;
     }
+    ClassifyArgs ca;
+    MrArgs ma;
+    unsigned grid_c, grid1;
+    make_args(ds, c.ws, t, ca, ma, grid_c, grid1);
+    const BatchDesc *d = reinterpret_cast<const BatchDesc *>(c.d_desc);
+    ca.desc = d;
+    ma.total_dev = &d->total;
     hipError_t e = hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess)
         return fail(e);
     hipError_t ee = hipMemcpyAsync(c.d_desc, c.h_desc, c.desc_bytes, hipMemcpyHostToDevice,
                                    c.cap_stream);
     if (ee == hipSuccess)
-        ee = launch_reset(c.ws.ctr, c.cap_stream);
-    if (ee == hipSuccess) {
-        const uint32_t grid = (uint32_t)ds.cus * (uint32_t)std::max(1, 2048 / t.classify_block);
-        ee = launch_classify_batched(reinterpret_cast<const BatchDesc *>(c.d_desc), grid, ds, c.ws,
-                                     t, c.cap_stream);
-    }
-    if (ee == hipSuccess && t.mr_bins > 0)
-        ee = launch_bin(c.ws, t, ds.cus, c.cap_stream);
+        ee = launch_classify(ca, grid_c, t.classify_block, t.classify_ept, c.cap_stream);
     if (ee == hipSuccess)
-        ee = launch_mr1(c.ws, t, ds.cus, c.cap_stream);
+        ee = launch_mr1(ma, t.mr_block, c.cap_stream);
     if (ee == hipSuccess)
-        ee = launch_mr2(c.ws, t, ds.cus, c.cap_stream);
+        ee = launch_mr2(ma, grid1, t.mr_block, t.mr_window, c.cap_stream);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(c.cap_stream, &g);
     if (ee != hipSuccess) {
@@ -295,6 +332,8 @@ int build_graph(BatchCtx &c, const DeviceState &ds, const Tuning &t)
         return fail(e);
     }
     c.tuned = t;
+    c.grid_c = grid_c;
+    c.grid1 = grid1;
     return ISP_OK;
 }
 
@@ -387,7 +426,7 @@ void isp_shutdown(void)
             free_ws(kv.second->ws);
         }
         g_ws.clear();
-        g_last_ctr.clear();
+        g_last.clear();
     }
     std::lock_guard<std::mutex> g(g_init_mu);
     for (auto &ds : g_dev) {
@@ -421,7 +460,8 @@ int isprime_u64(const uint64_t *n, uint8_t *out, size_t len, void *stream)
     for (size_t off = 0; off < len && st == ISP_OK; off += PLAIN_PIECE)
         st = run_plain(n + off, out + off, std::min(PLAIN_PIECE, len - off), g_dev[dev], sw->ws,
                        t, s);
-    note_counters(dev, stream, sw->ws.ctr);
+    note_counts(dev, stream, sw->ws, grid_of(g_dev[dev].cus, t.classify_blocks_per_cu),
+                grid_of(g_dev[dev].cus, t.mr_blocks_per_cu));
     return st;
 }
 
@@ -435,14 +475,13 @@ int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
     if (num_arrays > 0x7fffffffu)
         return ISP_EINVAL;
     const Tuning t = tuning_snapshot();
-    uint64_t total = 0, tiles = 0;
+    uint64_t total = 0;
     for (size_t a = 0; a < num_arrays; ++a) {
         if (lens[a] && (!n_ptrs[a] || !out_ptrs[a]))
             return ISP_EINVAL;
         total += lens[a];
-        tiles += (lens[a] + (uint64_t)t.batch_tile - 1) / (uint64_t)t.batch_tile;
     }
-    if (tiles > 0xffffffffull - 1 || total > BATCH_MAX_ELEMS)
+    if (total > BATCH_MAX_ELEMS)
         return ISP_EINVAL;
     if (total == 0)
         return ISP_OK;
@@ -465,20 +504,20 @@ int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
     }
     std::lock_guard<std::mutex> g(c->mu);
     hipError_t e;
-    // (Re)size the descriptor buffers and the workspace; both are baked into
-    // the graph, so any change re-records it.
+    // The descriptor buffers and the workspace are baked into the graph, so
+    // growing either re-records it.
     bool rebuild = !c->exec || !same_tuning(c->tuned, t);
-    if (num_arrays > c->arr_cap || !c->ws.ctr || c->ws.cap < total) {
+    if (num_arrays > c->arr_cap || !c->ws.surv || c->ws.cap < total) {
         if (c->pending) {
             e = hipEventSynchronize(c->done);
             if (e != hipSuccess)
                 return fail(e);
             c->pending = false;
         }
-        size_t arr_cap = std::max<size_t>(c->arr_cap, 1024);
-        while (arr_cap < num_arrays)
-            arr_cap <<= 1;
         if (num_arrays > c->arr_cap || !c->d_desc) {
+            size_t arr_cap = std::max<size_t>(c->arr_cap, 1024);
+            while (arr_cap < num_arrays)
+                arr_cap <<= 1;
             if (c->d_desc)
                 (void)hipFree(c->d_desc);
             if (c->h_desc)
@@ -519,24 +558,22 @@ int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
     char *d = static_cast<char *>(c->d_desc);
     const size_t off_n = align_up(sizeof(BatchDesc), 64);
     const size_t off_o = off_n + c->arr_cap * 8;
-    const size_t off_l = off_o + c->arr_cap * 8;
-    const size_t off_p = off_l + c->arr_cap * 8;
+    const size_t off_p = off_o + c->arr_cap * 8;
     BatchDesc hd;
+    std::memset(&hd, 0, sizeof(hd));
     hd.num_arrays = (uint32_t)num_arrays;
-    hd.num_tiles = (uint32_t)tiles;
+    hd.total = total;
     hd.n_ptrs = reinterpret_cast<const uint64_t *const *>(d + off_n);
     hd.out_ptrs = reinterpret_cast<uint8_t *const *>(d + off_o);
-    hd.lens = reinterpret_cast<const uint64_t *>(d + off_l);
-    hd.tile_prefix = reinterpret_cast<const uint32_t *>(d + off_p);
+    hd.elem_prefix = reinterpret_cast<const uint64_t *>(d + off_p);
     std::memcpy(h, &hd, sizeof(hd));
     std::memcpy(h + off_n, n_ptrs, num_arrays * 8);
     std::memcpy(h + off_o, out_ptrs, num_arrays * 8);
-    std::memcpy(h + off_l, lens, num_arrays * 8);
-    uint32_t *pre = reinterpret_cast<uint32_t *>(h + off_p);
-    uint32_t acc = 0;
+    uint64_t *pre = reinterpret_cast<uint64_t *>(h + off_p);
+    uint64_t acc = 0;
     for (size_t a = 0; a < num_arrays; ++a) {
         pre[a] = acc;
-        acc += (uint32_t)((lens[a] + (uint64_t)t.batch_tile - 1) / (uint64_t)t.batch_tile);
+        acc += lens[a];
     }
     pre[num_arrays] = acc;
     if (rebuild) {
@@ -550,16 +587,16 @@ int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
     if (e != hipSuccess)
         return fail(e);
     c->pending = true;
-    note_counters(dev, stream, c->ws.ctr);
+    note_counts(dev, stream, c->ws, c->grid_c, c->grid1);
     return ISP_OK;
 }
 
 size_t isp_workspace_bytes(size_t len)
 {
     size_t cap = 1 << 16;
-    while (cap < len)
+    while (cap < std::min(len, PLAIN_PIECE))
         cap <<= 1;
-    return sizeof(Counters) + 2 * cap * sizeof(Survivor);
+    return (2 * cap + 65 * (size_t)MAX_GRID) * sizeof(Survivor) + 2 * MAX_GRID * sizeof(uint32_t);
 }
 
 int isp_last_device_error(void) { return g_last_err.load(); }
@@ -600,15 +637,15 @@ int isp_set_config(const isp_config *cfg)
     if (!cfg)
         return ISP_EINVAL;
     isp_config c = *cfg;
-    const isp_config d = {256, 4, 24, 256, 1, 3, 8, 8192};
+    const isp_config &d = DEFAULT_CONFIG;
     if (!c.classify_block) c.classify_block = d.classify_block;
     if (!c.classify_ept) c.classify_ept = d.classify_ept;
+    if (!c.classify_blocks_per_cu) c.classify_blocks_per_cu = d.classify_blocks_per_cu;
     if (!c.filter_primes) c.filter_primes = d.filter_primes;
+    if (!c.sort_survivors) c.sort_survivors = d.sort_survivors;
     if (!c.mr_block) c.mr_block = d.mr_block;
-    if (!c.mr_bins) c.mr_bins = d.mr_bins;
-    if (!c.mr_window) c.mr_window = d.mr_window;
     if (!c.mr_blocks_per_cu) c.mr_blocks_per_cu = d.mr_blocks_per_cu;
-    if (!c.batch_tile) c.batch_tile = d.batch_tile;
+    if (!c.mr_window) c.mr_window = d.mr_window;
     if (!valid_config(c))
         return ISP_EINVAL;
     std::lock_guard<std::mutex> g(g_cfg_mu);
@@ -684,25 +721,26 @@ int isp_last_counts(void *stream, uint64_t *survivors, uint64_t *candidates)
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess)
         return fail(e);
-    Counters *c = nullptr;
+    LastCounts lc;
     {
         std::lock_guard<std::mutex> g(g_ws_mu);
-        auto it = g_last_ctr.find({dev, stream});
-        if (it != g_last_ctr.end())
-            c = it->second;
+        auto it = g_last.find({dev, stream});
+        if (it != g_last.end())
+            lc = it->second;
     }
-    if (!c) {
-        *survivors = *candidates = 0;
+    *survivors = *candidates = 0;
+    if (!lc.counts)
         return ISP_OK;
-    }
     e = hipStreamSynchronize((hipStream_t)stream);
-    Counters h;
+    std::vector<uint32_t> h(2 * (size_t)MAX_GRID);
     if (e == hipSuccess)
-        e = hipMemcpy(&h, c, sizeof(h), hipMemcpyDeviceToHost);
+        e = hipMemcpy(h.data(), lc.counts, h.size() * sizeof(uint32_t), hipMemcpyDeviceToHost);
     if (e != hipSuccess)
         return fail(e);
-    *survivors = h.survivors;
-    *candidates = h.candidates;
+    for (unsigned k = 0; k < lc.grid_c; ++k)
+        *survivors += h[k];
+    for (unsigned k = 0; k < lc.grid1; ++k)
+        *candidates += h[MAX_GRID + k];
     return ISP_OK;
 }
 

@@ -1,5 +1,5 @@
 // classify.hip -- dispatch, table lookup, trial filter and survivor
-// compaction in one streaming pass; then the magnitude-binning pass.
+// compaction in one streaming pass.
 //
 // Per element (paper: the input classes of section 1, the membership test of
 // section 6.1.3, the array shrinking of section 6.1.2):
@@ -12,17 +12,19 @@
 // Divisibility without division (Granlund and Montgomery, PLDI 1994):
 // p | n iff n * p^-1 mod 2^64 <= floor((2^64 - 1) / p), for odd p.
 //
-// Survivors (value, output address) are appended to a device list: a
-// wavefront ballot per element slot gives each lane its rank, the per-wave
-// totals are scanned in LDS, and one atomic per workgroup reserves the
-// block's range.  The order across workgroups is not deterministic; results
-// do not depend on it.  A per-block LDS histogram of survivor bit lengths
-// (33..64) feeds the binning pass.
+// Work split without global atomics: the grid is a fixed number of
+// workgroups; workgroup g owns the contiguous element range
+// [g * chunk, (g + 1) * chunk) of the (for batched calls, virtual
+// concatenated) input, writes its survivors to its own region
+// surv[g * chunk ...] and stores its survivor count in counts[g]; the
+// Miller-Rabin kernel scans those counts.  (A single hot device-scope
+// atomic sustains only about 1e8 operations per second on this part, far
+// too few to append survivors one workgroup at a time.)
 //
-// Binning (counting sort by bit length, longest first): each block counts
-// its chunk per bin in LDS, reserves per-bin ranges with one atomic per bin,
-// and scatters.  Wavefronts of the Miller-Rabin kernels then see values of
-// one bit length, so every lane runs the same number of squarings.
+// Within each pass of blockDim * EPT elements the survivors are ordered by
+// decreasing bit length with an LDS counting sort (32 keys, bit lengths 64
+// down to 33), so a wavefront of the Miller-Rabin kernels sees values of
+// (nearly) one bit length and its lanes run the same number of squarings.
 #include "internal.h"
 
 namespace isp {
@@ -30,11 +32,6 @@ namespace isp {
 namespace {
 
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(8)));
-
-__device__ __forceinline__ uint64_t lanemask_lt(int lane)
-{
-    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
 
 // 0 or 1: decided; 2: survivor of the filter.
 __device__ __forceinline__ int classify_one(uint64_t v, const uint32_t *__restrict__ table,
@@ -52,78 +49,26 @@ __device__ __forceinline__ int classify_one(uint64_t v, const uint32_t *__restri
     return 2;
 }
 
-__device__ __forceinline__ int bin_of(uint64_t v)
-{
-    return (64 - __clzll(v)) - 33;  // v >= 2^32: 0..31
-}
+// Sort key: 0 for bit length 64 ... 31 for bit length 33 (v >= 2^32).
+__device__ __forceinline__ int sort_key(uint64_t v) { return __clzll(v); }
 
-// Appends the survivors of a block to ws.surv: slot-major within a wave.
-template <int EPT>
-__device__ __forceinline__ void append_survivors(const uint64_t (&v)[EPT], const bool (&sv)[EPT],
-                                                 uint8_t *out_base, Survivor *__restrict__ surv,
-                                                 Counters *__restrict__ ctr, int binning,
-                                                 uint32_t *wave_off, uint32_t *hist,
-                                                 uint32_t *block_base)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    uint64_t masks[EPT];
-    uint32_t wave_total = 0;
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-        masks[j] = __ballot(sv[j]);
-        wave_total += __popcll(masks[j]);
-    }
-    if (lane == 0)
-        wave_off[wave] = wave_total;
-    if (binning) {
-#pragma unroll
-        for (int j = 0; j < EPT; ++j)
-            if (sv[j])
-                atomicAdd(&hist[bin_of(v[j])], 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int w = 0; w < nwaves; ++w) {
-            uint32_t t = wave_off[w];
-            wave_off[w] = run;
-            run += t;
-        }
-        *block_base = run ? atomicAdd(&ctr->survivors, run) : 0u;
-    }
-    if (binning && threadIdx.x < NUM_BINS) {
-        // hist is complete after the barrier above
-        uint32_t h = hist[threadIdx.x];
-        if (h)
-            atomicAdd(&ctr->bin_count[threadIdx.x], h);
-    }
-    __syncthreads();
-    uint32_t pos = *block_base + wave_off[wave];
-    const uint64_t lt = lanemask_lt(lane);
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-        if (sv[j]) {
-            Survivor s;
-            s.n = v[j];
-            s.out = out_base + j;
-            surv[pos + __popcll(masks[j] & lt)] = s;
-        }
-        pos += __popcll(masks[j]);
-    }
-}
+struct ClassifyShared {
+    uint32_t hist[NUM_BINS];
+    uint32_t off[NUM_BINS];
+    uint32_t wave_cnt[16];
+    uint32_t pass_total;
+};
 
-// Classifies elements [base, base + EPT) of one array (those below `end`),
-// writes their output bytes and appends the survivors.  Called by every
-// thread of the block (it contains barriers).
+// One pass: elements [base, base + EPT) of one array, those below `end`.
+// Writes the output bytes and appends the pass's survivors at
+// region[filled ...].  Called by every thread of the block.
 template <int EPT>
-__device__ __forceinline__ void classify_span(const uint64_t *__restrict__ n,
+__device__ __forceinline__ void classify_pass(const uint64_t *__restrict__ n,
                                               uint8_t *__restrict__ out, uint64_t base,
                                               uint64_t end, const uint32_t *__restrict__ table,
                                               const FilterPrime *__restrict__ filt, int nfilt,
-                                              Survivor *__restrict__ surv,
-                                              Counters *__restrict__ ctr, int binning,
-                                              uint32_t *wave_off, uint32_t *hist,
-                                              uint32_t *block_base)
+                                              Survivor *__restrict__ region, uint32_t &filled,
+                                              int sorted, ClassifyShared &sh)
 {
     uint64_t v[EPT];
     const bool full = base + EPT <= end;
@@ -131,7 +76,7 @@ __device__ __forceinline__ void classify_span(const uint64_t *__restrict__ n,
         if constexpr (EPT >= 2) {
 #pragma unroll
             for (int j = 0; j < EPT; j += 2) {
-                u64x2 t = *reinterpret_cast<const u64x2 *>(n + base + j);
+                const u64x2 t = *reinterpret_cast<const u64x2 *>(n + base + j);
                 v[j] = t.x;
                 v[j + 1] = t.y;
             }
@@ -147,7 +92,7 @@ __device__ __forceinline__ void classify_span(const uint64_t *__restrict__ n,
     uint8_t r[EPT];
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-        int c = classify_one(v[j], table, filt, nfilt);
+        const int c = classify_one(v[j], table, filt, nfilt);
         sv[j] = c == 2 && base + j < end;
         r[j] = (uint8_t)(c == 1);
     }
@@ -174,202 +119,161 @@ __device__ __forceinline__ void classify_span(const uint64_t *__restrict__ n,
             if (base + j < end)
                 out[base + j] = r[j];
     }
-    append_survivors<EPT>(v, sv, out + base, surv, ctr, binning, wave_off, hist, block_base);
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    if (sorted) {
+        // counting sort by bit length: rank within its key from an LDS atomic
+        uint32_t rank[EPT];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+            rank[j] = sv[j] ? atomicAdd(&sh.hist[sort_key(v[j])], 1u) : 0u;
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            // exclusive scan of the 32 key counts by the first wavefront
+            const uint32_t h = lane < NUM_BINS ? sh.hist[lane] : 0u;
+            uint32_t incl = h;
+#pragma unroll
+            for (int o = 1; o < NUM_BINS; o <<= 1) {
+                const uint32_t y = __shfl_up(incl, o, 64);
+                if (lane >= o)
+                    incl += y;
+            }
+            if (lane < NUM_BINS) {
+                sh.off[lane] = incl - h;
+                sh.hist[lane] = 0;  // ready for the next pass
+            }
+            if (lane == NUM_BINS - 1)
+                sh.pass_total = incl;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            if (sv[j]) {
+                Survivor s;
+                s.n = v[j];
+                s.out = out + base + j;
+                region[filled + sh.off[sort_key(v[j])] + rank[j]] = s;
+            }
+        }
+    } else {
+        // order-preserving compaction: ballot per slot, LDS scan over waves
+        uint64_t masks[EPT];
+        uint32_t wave_total = 0;
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            masks[j] = __ballot(sv[j]);
+            wave_total += __popcll(masks[j]);
+        }
+        if (lane == 0)
+            sh.wave_cnt[wave] = wave_total;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t run = 0;
+            for (int w = 0; w < nwaves; ++w) {
+                const uint32_t t = sh.wave_cnt[w];
+                sh.wave_cnt[w] = run;
+                run += t;
+            }
+            sh.pass_total = run;
+        }
+        __syncthreads();
+        uint32_t pos = filled + sh.wave_cnt[wave];
+        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            if (sv[j]) {
+                Survivor s;
+                s.n = v[j];
+                s.out = out + base + j;
+                region[pos + __popcll(masks[j] & lt)] = s;
+            }
+            pos += __popcll(masks[j]);
+        }
+    }
+    filled += sh.pass_total;
+    __syncthreads();  // sh is reused by the next pass
 }
 
-template <int EPT>
-__global__ void __launch_bounds__(1024) classify_kernel(const uint64_t *__restrict__ n,
-                                                        uint8_t *__restrict__ out, uint64_t len,
-                                                        const uint32_t *__restrict__ table,
-                                                        const FilterPrime *__restrict__ filt,
-                                                        int nfilt, Survivor *__restrict__ surv,
-                                                        Counters *__restrict__ ctr, int binning)
+// Workgroup g classifies the element range [g * chunk, (g + 1) * chunk) of
+// the input (plain) or of the virtual concatenation of the arrays (batched).
+template <int EPT, bool BATCHED>
+__global__ void __launch_bounds__(1024) classify_kernel(ClassifyArgs a)
 {
-    __shared__ uint32_t wave_off[16];
-    __shared__ uint32_t hist[NUM_BINS];
-    __shared__ uint32_t block_base;
-    if (binning && threadIdx.x < NUM_BINS)
-        hist[threadIdx.x] = 0;
+    __shared__ ClassifyShared sh;
+    if (threadIdx.x < NUM_BINS)
+        sh.hist[threadIdx.x] = 0;
     __syncthreads();
-    const uint64_t base = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * EPT;
-    classify_span<EPT>(n, out, base, len, table, filt, nfilt, surv, ctr, binning, wave_off, hist,
-                       &block_base);
-}
-
-// Batched form: a persistent grid walks tiles of many arrays.  Tile t of the
-// whole batch belongs to the array a with tile_prefix[a] <= t <
-// tile_prefix[a+1] (binary search) and covers elements
-// [(t - tile_prefix[a]) * tile, +tile) of it.
-template <int EPT>
-__global__ void __launch_bounds__(1024) classify_batched_kernel(
-    const BatchDesc *__restrict__ desc, const uint32_t *__restrict__ table,
-    const FilterPrime *__restrict__ filt, int nfilt, Survivor *__restrict__ surv,
-    Counters *__restrict__ ctr, int binning, uint32_t tile)
-{
-    __shared__ uint32_t wave_off[16];
-    __shared__ uint32_t hist[NUM_BINS];
-    __shared__ uint32_t block_base;
-    __shared__ uint32_t cur_tile;
-    const uint32_t num_arrays = desc->num_arrays;
-    const uint32_t num_tiles = desc->num_tiles;
-    const uint64_t *const *n_ptrs = desc->n_ptrs;
-    uint8_t *const *out_ptrs = desc->out_ptrs;
-    const uint64_t *lens = desc->lens;
-    const uint32_t *tile_prefix = desc->tile_prefix;
-    const uint32_t per_pass = blockDim.x * EPT;
-
-    for (;;) {
-        if (threadIdx.x == 0)
-            cur_tile = atomicAdd(&ctr->tile_cursor, 1u);
-        __syncthreads();
-        const uint32_t t = cur_tile;
-        __syncthreads();
-        if (t >= num_tiles)
-            break;
-        uint32_t lo = 0, hi = num_arrays;  // prefix[lo] <= t < prefix[hi]
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (tile_prefix[mid] <= t)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        const uint64_t len = lens[lo];
-        const uint64_t t0 = (uint64_t)(t - tile_prefix[lo]) * tile;
-        const uint64_t t1 = t0 + tile < len ? t0 + tile : len;
-        const uint64_t *nv = n_ptrs[lo];
-        uint8_t *ov = out_ptrs[lo];
-        for (uint64_t pass0 = t0; pass0 < t1; pass0 += per_pass) {
-            if (binning && threadIdx.x < NUM_BINS)
-                hist[threadIdx.x] = 0;
-            __syncthreads();
-            classify_span<EPT>(nv, ov, pass0 + (uint64_t)threadIdx.x * EPT, t1, table, filt, nfilt,
-                               surv, ctr, binning, wave_off, hist, &block_base);
-            __syncthreads();
+    const uint64_t g = blockIdx.x;
+    const uint64_t total = BATCHED ? a.desc->total : a.total;
+    const uint64_t chunk = classify_chunk(total, gridDim.x);
+    const uint64_t r0 = g * chunk;
+    const uint64_t r1 = r0 + chunk < total ? r0 + chunk : total;
+    Survivor *region = a.surv + r0;
+    uint32_t filled = 0;
+    const uint64_t per_pass = (uint64_t)blockDim.x * EPT;
+    if (r0 < r1) {
+        if constexpr (!BATCHED) {
+            for (uint64_t p0 = r0; p0 < r1; p0 += per_pass)
+                classify_pass<EPT>(a.n, a.out, p0 + (uint64_t)threadIdx.x * EPT, r1, a.table,
+                                   a.filter, a.nfilter, region, filled, a.sorted, sh);
+        } else {
+            const BatchDesc *d = a.desc;
+            // first array overlapping r0: prefix[lo] <= r0 < prefix[hi]
+            uint32_t lo = 0, hi = d->num_arrays;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (d->elem_prefix[mid] <= r0)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            for (uint32_t k = lo; k < d->num_arrays && d->elem_prefix[k] < r1; ++k) {
+                const uint64_t s0 = d->elem_prefix[k], s1 = d->elem_prefix[k + 1];
+                if (s1 <= r0)
+                    continue;  // an empty array at the start of the range
+                const uint64_t b0 = (r0 > s0 ? r0 : s0) - s0;  // local range in array k
+                const uint64_t b1 = (r1 < s1 ? r1 : s1) - s0;
+                const uint64_t *nv = d->n_ptrs[k];
+                uint8_t *ov = d->out_ptrs[k];
+                for (uint64_t p0 = b0; p0 < b1; p0 += per_pass)
+                    classify_pass<EPT>(nv, ov, p0 + (uint64_t)threadIdx.x * EPT, b1, a.table,
+                                       a.filter, a.nfilter, region, filled, a.sorted, sh);
+            }
         }
     }
+    if (threadIdx.x == 0)
+        a.counts[g] = filled;
 }
 
-__global__ void __launch_bounds__(256) bin_kernel(const Survivor *__restrict__ in,
-                                                  Survivor *__restrict__ outl,
-                                                  Counters *__restrict__ ctr)
+template <bool BATCHED>
+hipError_t launch_classify_t(const ClassifyArgs &a, unsigned grid, int block, int ept,
+                             hipStream_t s)
 {
-    __shared__ uint32_t start[NUM_BINS];
-    __shared__ uint32_t lcount[NUM_BINS];
-    __shared__ uint32_t lbase[NUM_BINS];
-    const uint32_t total = ctr->survivors;
-    const int tid = threadIdx.x;
-    if (tid < NUM_BINS) {
-        // longest values first: bin 31 (64-bit) starts at 0
-        uint32_t s = 0;
-        for (int b = NUM_BINS - 1; b > tid; --b)
-            s += ctr->bin_count[b];
-        start[tid] = s;
+    switch (ept) {
+    case 1:
+        classify_kernel<1, BATCHED><<<grid, block, 0, s>>>(a);
+        break;
+    case 2:
+        classify_kernel<2, BATCHED><<<grid, block, 0, s>>>(a);
+        break;
+    case 4:
+        classify_kernel<4, BATCHED><<<grid, block, 0, s>>>(a);
+        break;
+    case 8:
+        classify_kernel<8, BATCHED><<<grid, block, 0, s>>>(a);
+        break;
+    default:
+        return hipErrorInvalidValue;
     }
-    for (uint64_t chunk = (uint64_t)blockIdx.x * blockDim.x; chunk < total;
-         chunk += (uint64_t)gridDim.x * blockDim.x) {
-        if (tid < NUM_BINS)
-            lcount[tid] = 0;
-        __syncthreads();
-        const uint64_t i = chunk + tid;
-        const bool active = i < total;
-        Survivor s;
-        int b = 0;
-        uint32_t lpos = 0;
-        if (active) {
-            s = in[i];
-            b = bin_of(s.n);
-            lpos = atomicAdd(&lcount[b], 1u);
-        }
-        __syncthreads();
-        if (tid < NUM_BINS && lcount[tid])
-            lbase[tid] = start[tid] + atomicAdd(&ctr->bin_cursor[tid], lcount[tid]);
-        __syncthreads();
-        if (active)
-            outl[lbase[b] + lpos] = s;
-        __syncthreads();
-    }
-}
-
-__global__ void reset_kernel(Counters *ctr)
-{
-    uint32_t *w = reinterpret_cast<uint32_t *>(ctr);
-    for (unsigned k = threadIdx.x; k < sizeof(Counters) / 4; k += blockDim.x)
-        w[k] = 0;
+    return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_reset(Counters *ctr, hipStream_t s)
+hipError_t launch_classify(const ClassifyArgs &a, unsigned grid, int block, int ept, hipStream_t s)
 {
-    reset_kernel<<<1, 128, 0, s>>>(ctr);
-    return hipGetLastError();
-}
-
-hipError_t launch_classify(const uint64_t *n, uint8_t *out, uint64_t len, const DeviceState &ds,
-                           const Workspace &ws, const Tuning &t, hipStream_t s)
-{
-    const uint64_t per_block = (uint64_t)t.classify_block * t.classify_ept;
-    const uint64_t blocks = (len + per_block - 1) / per_block;
-    if (blocks > 0x7fffffffull)
-        return hipErrorInvalidValue;
-    const int bin = t.mr_bins > 0;
-    switch (t.classify_ept) {
-    case 1:
-        classify_kernel<1><<<(unsigned)blocks, t.classify_block, 0, s>>>(
-            n, out, len, ds.table, ds.filter, t.filter_primes, ws.surv, ws.ctr, bin);
-        break;
-    case 2:
-        classify_kernel<2><<<(unsigned)blocks, t.classify_block, 0, s>>>(
-            n, out, len, ds.table, ds.filter, t.filter_primes, ws.surv, ws.ctr, bin);
-        break;
-    case 4:
-        classify_kernel<4><<<(unsigned)blocks, t.classify_block, 0, s>>>(
-            n, out, len, ds.table, ds.filter, t.filter_primes, ws.surv, ws.ctr, bin);
-        break;
-    case 8:
-        classify_kernel<8><<<(unsigned)blocks, t.classify_block, 0, s>>>(
-            n, out, len, ds.table, ds.filter, t.filter_primes, ws.surv, ws.ctr, bin);
-        break;
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_classify_batched(const BatchDesc *desc, uint32_t grid, const DeviceState &ds,
-                                   const Workspace &ws, const Tuning &t, hipStream_t s)
-{
-    const int bin = t.mr_bins > 0;
-    const uint32_t tile = (uint32_t)t.batch_tile;
-    switch (t.classify_ept) {
-    case 1:
-        classify_batched_kernel<1><<<grid, t.classify_block, 0, s>>>(
-            desc, ds.table, ds.filter, t.filter_primes, ws.surv, ws.ctr, bin, tile);
-        break;
-    case 2:
-        classify_batched_kernel<2><<<grid, t.classify_block, 0, s>>>(
-            desc, ds.table, ds.filter, t.filter_primes, ws.surv, ws.ctr, bin, tile);
-        break;
-    case 4:
-        classify_batched_kernel<4><<<grid, t.classify_block, 0, s>>>(
-            desc, ds.table, ds.filter, t.filter_primes, ws.surv, ws.ctr, bin, tile);
-        break;
-    case 8:
-        classify_batched_kernel<8><<<grid, t.classify_block, 0, s>>>(
-            desc, ds.table, ds.filter, t.filter_primes, ws.surv, ws.ctr, bin, tile);
-        break;
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_bin(const Workspace &ws, const Tuning &t, int cus, hipStream_t s)
-{
-    (void)t;
-    bin_kernel<<<(unsigned)(cus * 4), 256, 0, s>>>(ws.surv, ws.sorted, ws.ctr);
-    return hipGetLastError();
+    return a.desc ? launch_classify_t<true>(a, grid, block, ept, s)
+                  : launch_classify_t<false>(a, grid, block, ept, s);
 }
 
 }  // namespace isp

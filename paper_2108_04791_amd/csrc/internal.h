@@ -31,38 +31,67 @@ struct FilterPrime {
     uint64_t lim;
 };
 
-// Device-side counters of one call, cleared by a kernel at its start.
-struct Counters {
-    uint32_t survivors;           // appended by classify
-    uint32_t candidates;          // base-2 passers appended by phase 1
-    uint32_t work1, work2;        // chunk cursors of the persistent MR kernels
-    uint32_t bin_count[NUM_BINS]; // survivors per bit-length bin
-    uint32_t bin_cursor[NUM_BINS];
-    uint32_t tile_cursor;         // batched classify tile cursor
-    uint32_t pad[7];
-};
+// Largest grid of the classify and Miller-Rabin kernels: their per-block
+// counts are scanned in LDS by the consumer.
+constexpr int MAX_GRID = 4096;
 
 // Device-resident descriptor of a batched call.  The arrays follow the
 // header in the same allocation; the pointers address them.
 struct BatchDesc {
     uint32_t num_arrays;
-    uint32_t num_tiles;
+    uint32_t pad;
+    uint64_t total;                 // elements over all arrays
     const uint64_t *const *n_ptrs;  // num_arrays device pointers
     uint8_t *const *out_ptrs;       // num_arrays device pointers
-    const uint64_t *lens;           // num_arrays lengths
-    const uint32_t *tile_prefix;    // num_arrays + 1 exclusive tile counts
+    const uint64_t *elem_prefix;    // num_arrays + 1 exclusive element offsets
+};
+
+// Region size of classify block g: its element range, a multiple of 64.
+__host__ __device__ inline uint64_t classify_chunk(uint64_t total, uint32_t grid)
+{
+    return ((total + grid - 1) / grid + 63) / 64 * 64;
+}
+
+// Region size of Miller-Rabin base-2 block g for its base-2 passers.
+__host__ __device__ inline uint64_t cand_chunk(uint64_t total, uint32_t grid)
+{
+    return (total + grid - 1) / grid;
+}
+
+struct ClassifyArgs {
+    const uint64_t *n;      // plain call: the input ...
+    uint8_t *out;           // ... and its output
+    const BatchDesc *desc;  // batched call (n, out unused); nullptr for plain
+    uint64_t total;         // plain call: elements (batched: desc->total)
+    const uint32_t *table;
+    const FilterPrime *filter;
+    int nfilter;
+    int sorted;             // order survivors by bit length within a pass
+    Survivor *surv;         // grid regions of classify_chunk() entries
+    uint32_t *counts;       // [grid] survivors per region
+};
+
+struct MrArgs {
+    uint64_t total;              // elements of the call ...
+    const uint64_t *total_dev;   // ... or where to read them (batched)
+    uint32_t grid_c;             // classify grid
+    const Survivor *surv;        // classify regions
+    const uint32_t *counts_c;    // [grid_c]
+    uint32_t grid1;              // base-2 grid
+    Survivor *cand;              // base-2 passer regions of cand_chunk() entries
+    uint32_t *counts1;           // [grid1]
 };
 
 // Resolved launch parameters (the public isp_config after defaults).
 struct Tuning {
     int classify_block;
     int classify_ept;
+    int classify_blocks_per_cu;
     int filter_primes;
+    int sort_survivors;
     int mr_block;
-    int mr_bins;     // 0 or 1: no binning pass
-    int mr_window;   // fixed window width of the phase-2 exponentiation
     int mr_blocks_per_cu;
-    int batch_tile;  // elements per batched classify tile
+    int mr_window;
 };
 
 struct DeviceState {
@@ -75,12 +104,12 @@ struct DeviceState {
     int num_base_primes = 0;
 };
 
-// Per-call workspace (one per stream).
+// Per-call workspace (one per stream, or per batched context).
 struct Workspace {
-    Counters *ctr = nullptr;
-    Survivor *surv = nullptr;    // classify output
-    Survivor *sorted = nullptr;  // binning output; phase-2 list reuses `surv`
-    size_t cap = 0;              // survivors each buffer holds
+    Survivor *surv = nullptr;   // classify regions (cap + 64 * MAX_GRID entries)
+    Survivor *cand = nullptr;   // base-2 passer regions (cap + MAX_GRID entries)
+    uint32_t *counts = nullptr; // 2 * MAX_GRID
+    size_t cap = 0;             // elements per call this workspace serves
 };
 
 // ---- launchers (each enqueues on `stream` and returns hipError_t) ----
@@ -88,14 +117,10 @@ hipError_t launch_base_primes(DeviceState &ds, hipStream_t s);
 hipError_t launch_sieve(DeviceState &ds, hipStream_t s);
 hipError_t launch_filter_consts(DeviceState &ds, hipStream_t s);
 
-hipError_t launch_reset(Counters *ctr, hipStream_t s);
-hipError_t launch_classify(const uint64_t *n, uint8_t *out, uint64_t len, const DeviceState &ds,
-                           const Workspace &ws, const Tuning &t, hipStream_t s);
-hipError_t launch_classify_batched(const BatchDesc *desc, uint32_t grid, const DeviceState &ds,
-                                   const Workspace &ws, const Tuning &t, hipStream_t s);
-hipError_t launch_bin(const Workspace &ws, const Tuning &t, int cus, hipStream_t s);
-hipError_t launch_mr1(const Workspace &ws, const Tuning &t, int cus, hipStream_t s);
-hipError_t launch_mr2(const Workspace &ws, const Tuning &t, int cus, hipStream_t s);
+hipError_t launch_classify(const ClassifyArgs &a, unsigned grid, int block, int ept,
+                           hipStream_t s);
+hipError_t launch_mr1(const MrArgs &a, int block, hipStream_t s);
+hipError_t launch_mr2(const MrArgs &a, unsigned grid2, int block, int window, hipStream_t s);
 
 hipError_t launch_montmul_test(const uint64_t *a, const uint64_t *b, const uint64_t *n,
                                uint64_t *out, uint64_t len, hipStream_t s);

@@ -73,19 +73,20 @@ def test_batched_growing_and_empty_arrays(isp):
         assert np.array_equal(got, exp), k
 
 
-def test_batched_tile_sizes(isp):
-    arrays = [W.c3_mixed(L, start=L) for L in (1, 255, 256, 257, 70000, 3)]
+def test_batched_grids(isp):
+    arrays = [W.c3_mixed(L, start=L) for L in (1, 255, 256, 257, 70000, 3, 0, 5)]
     exp = [oracle.isprime_array(a, nthreads=NTHREADS, use_table=False)[0] for a in arrays]
     dev = [to_dev(a) for a in arrays]
-    for tile in (256, 1000, 65536):
-        prev = isp.set_config(batch_tile=tile)
+    for cfg in (dict(classify_blocks_per_cu=1), dict(classify_blocks_per_cu=16, classify_ept=1),
+                dict(mr_blocks_per_cu=1, mr_block=64), dict(sort_survivors=-1)):
+        prev = isp.set_config(**cfg)
         try:
             outs = isp.isprime_batched(dev)
             torch.cuda.synchronize()
         finally:
             isp.set_config(**prev)
         for o, e in zip(outs, exp):
-            assert np.array_equal(o.cpu().numpy().astype(np.uint8), e), tile
+            assert np.array_equal(o.cpu().numpy().astype(np.uint8), e), cfg
 
 
 def test_batched_invalid(isp):

@@ -177,14 +177,14 @@ def test_counts_match_host_accounting(isp):
 
 @pytest.mark.parametrize("cfg", [
     dict(classify_ept=1, classify_block=64),
-    dict(classify_ept=2, classify_block=1024),
-    dict(classify_ept=8, classify_block=128),
+    dict(classify_ept=2, classify_block=1024, classify_blocks_per_cu=1),
+    dict(classify_ept=8, classify_block=128, classify_blocks_per_cu=16),
     dict(filter_primes=-1),
     dict(filter_primes=256),
-    dict(mr_bins=-1),
+    dict(sort_survivors=-1),
     dict(mr_window=1), dict(mr_window=2), dict(mr_window=4),
     dict(mr_block=64, mr_blocks_per_cu=1),
-    dict(mr_block=128, mr_blocks_per_cu=32),
+    dict(mr_block=128, mr_blocks_per_cu=16),
 ])
 def test_configs_do_not_change_bits(isp, cfg):
     a = np.concatenate([np.array(EDGES, dtype=np.uint64), W.c3_mixed(30011, start=99),
