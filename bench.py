@@ -28,12 +28,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "uint64 primality tests/sec (bit-exact) + p50/p99 latency at fixed QPS vs plain"
 HBM_PEAK_GBS = 8000.0
-# Integer VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, 32-bit lane-ops.
+# Integer VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, in
+# full-rate VALU lane-instructions per second (on gfx950 the 32-bit
+# multiplies v_mad_u64_u32, v_mul_lo_u32 and v_mul_hi_u32 issue at full rate).
 VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
-# 32-bit operations in one 64-bit Montgomery product (schoolbook 2x2-word
-# product, REDC in the subtractive form, final conditional add); the count
-# is derived operation by operation in the design notes.
-OPS_PER_MONTMUL = 40
+# VALU instructions of the shortest gfx950 sequence for one 64-bit
+# Montgomery product (4 v_mad_u64_u32 + 4 carry adds for a*b, 1 v_mad_u64_u32
+# + 2 v_mul_lo_u32 + 1 v_add3_u32 for m, 1 v_mul_hi_u32 + 3 v_mad_u64_u32 + 4
+# carry adds for the high half of m*n, 2 subtracts + 2 selects + 1 add for the
+# correction: 27) and for one modular doubling (add, two tests, subtract,
+# select: 6).
+OPS_PER_MONTMUL = 27
+OPS_PER_DOUBLING = 6
 MR_BASES_AFTER_2 = 6
 
 
@@ -57,37 +63,44 @@ def bit_length(a: np.ndarray) -> np.ndarray:
     return L + (x > 0)
 
 
-def mr_work(a: np.ndarray, prime: np.ndarray, filter_primes: int):
-    """Algorithmic Montgomery products of the two Miller-Rabin launches.
+def popcount(x: np.ndarray) -> np.ndarray:
+    c = np.zeros(x.size, dtype=np.int64)
+    x = x.copy()
+    while (x != 0).any():
+        c += (x & np.uint64(1)).astype(np.int64)
+        x >>= np.uint64(1)
+    return c
 
-    Base 2 (every filter survivor): L - 2 squarings for bit length L (the
-    doublings are additions and are not counted).  Remaining six bases
-    (every prime >= 2^32; base-2 pseudoprimes are negligible here): per base,
-    L - 2 squarings plus popcount(d) - 1 multiplications, d = (n - 1) / 2^s.
+
+def mr_work(a: np.ndarray, prime: np.ndarray, filter_primes: int):
+    """Algorithmic work (VALU instructions) of the two Miller-Rabin launches,
+    counted for left-to-right binary exponentiation.
+
+    Base 2 (every filter survivor): L - 2 Montgomery squarings for bit length
+    L and popcount(n - 1) - 1 modular doublings.  Remaining six bases (every
+    prime >= 2^32; base-2 pseudoprimes are negligible here): per base, L - 2
+    squarings plus popcount(d) - 1 multiplications, d = (n - 1) / 2^s.
+    Early exits of the squaring chain are not subtracted.
     """
     big = (a >= np.uint64(1 << 32)) & ((a & np.uint64(1)) == 1)
     keep = big.copy()
     for p in small_odd_primes(filter_primes):
         keep &= (a % np.uint64(p)) != 0
     L = bit_length(a)
-    base2 = int((L[keep] - 2).sum())
+    sq2 = int((L[keep] - 2).sum())
+    dbl2 = int((popcount(a[keep] - np.uint64(1)) - 1).sum())
+    base2_ops = sq2 * OPS_PER_MONTMUL + dbl2 * OPS_PER_DOUBLING
     pr = prime.astype(bool) & big
-    e = a[pr] - np.uint64(1)
-    s = np.zeros(e.size, dtype=np.int64)
-    d = e.copy()
+    d = a[pr] - np.uint64(1)
     while True:
         ev = (d & np.uint64(1)) == 0
         if not ev.any():
             break
         d[ev] >>= np.uint64(1)
-        s[ev] += 1
-    pc = np.zeros(d.size, dtype=np.int64)
-    dd = d.copy()
-    while (dd != 0).any():
-        pc += (dd & np.uint64(1)).astype(np.int64)
-        dd >>= np.uint64(1)
-    rest = int((MR_BASES_AFTER_2 * ((L[pr] - 2) + (pc - 1))).sum())
-    return base2, rest, int(keep.sum()), int(pr.sum())
+    mm_rest = int((MR_BASES_AFTER_2 * ((L[pr] - 2) + (popcount(d) - 1))).sum())
+    work = {"mr_base2": {"montmul": sq2, "doublings": dbl2, "ops": base2_ops},
+            "mr_rest": {"montmul": mm_rest, "doublings": 0, "ops": mm_rest * OPS_PER_MONTMUL}}
+    return work, int(keep.sum()), int(pr.sum())
 
 
 def main() -> int:
@@ -96,6 +109,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (the reference "
+                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path needs no exchange between devices, "
@@ -103,6 +119,14 @@ def main() -> int:
         return 2
 
     import torch
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.int64, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": src.numel() * 8, "copies": 5}))
+        return 0
     import paper_2108_04791_amd as isp
     import workloads as W
 
@@ -143,8 +167,7 @@ def main() -> int:
     calls = max(1, prof["calls"])
     stage_ms = {k: prof[k] / calls for k in isp.STAGES}
 
-    base2_mm, rest_mm, n_surv, n_prime = mr_work(a, got, cfg["filter_primes"])
-    work = {"mr_base2": base2_mm, "mr_rest": rest_mm}
+    work, n_surv, n_prime = mr_work(a, got, max(0, cfg["filter_primes"]))
     dom = max(("mr_base2", "mr_rest", "classify"), key=lambda k: stage_ms[k])
     if dom == "classify":
         bytes_per_launch = n * 9.0
@@ -152,11 +175,17 @@ def main() -> int:
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom}
     else:
-        ops = work[dom] * OPS_PER_MONTMUL
-        achieved = ops / (stage_ms[dom] * 1e-3) / 1e9
-        roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GOPS, "unit": "Gop/s",
-                    "frac": achieved / VALU_PEAK_GOPS, "traffic": None, "kernel": dom,
-                    "montmul_per_launch": work[dom], "ops_per_montmul": OPS_PER_MONTMUL}
+        achieved = work[dom]["ops"] / (stage_ms[dom] * 1e-3) / 1e9
+        roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GOPS,
+                    "unit": "Gop/s", "frac": achieved / VALU_PEAK_GOPS, "traffic": None,
+                    "kernel": dom, "op": "VALU lane-instruction",
+                    "montmul_per_launch": work[dom]["montmul"],
+                    "doublings_per_launch": work[dom]["doublings"],
+                    "ops_per_montmul": OPS_PER_MONTMUL, "ops_per_doubling": OPS_PER_DOUBLING}
+    other = {}
+    for k in ("mr_base2", "mr_rest"):
+        ach = work[k]["ops"] / (stage_ms[k] * 1e-3) / 1e9
+        other[k] = {"achieved": ach, "frac": ach / VALU_PEAK_GOPS}
 
     cpu = None
     bit_exact = None
@@ -190,6 +219,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "bit_exact_vs_oracle": bit_exact,
         "stage_ms": stage_ms,
+        "alu_frac_by_kernel": other,
         "survivors": n_surv,
         "primes": int(got.sum()),
         "sieve_build_ms": sieve_ms,

@@ -56,7 +56,7 @@ enum {
 
 /* Build the odd-only sieve table for n < 2^32 on `device` (bit i of the
  * table is 1 iff 2i+1 is prime; 2^31 bits = 256 MiB in HBM), together with
- * the base primes and filter constants.  Blocking; idempotent; thread-safe.
+ * and the base primes.  Blocking; idempotent; thread-safe.
  * Every other entry point calls it lazily for the current device.
  * Paper: section 1 (sieve of Eratosthenes), section 4 (odd numbers only). */
 int isp_init(int device);
@@ -104,7 +104,7 @@ typedef struct {
     int32_t classify_block;         /* threads per classify block: 64..1024, multiple of 64 */
     int32_t classify_ept;           /* elements per classify thread and pass: 1, 2, 4 or 8 */
     int32_t classify_blocks_per_cu; /* classify grid = CUs x this (at most 4096): 1..16 */
-    int32_t filter_primes;          /* odd primes in the trial filter: -1 (none) or 1..256 */
+    int32_t filter_primes;          /* odd primes in the trial filter: -1 (none), 8, 16, 24, 32, 48 or 64 */
     int32_t sort_survivors;         /* 1: order survivors by bit length; -1: keep input order */
     int32_t mr_block;               /* threads per Miller-Rabin block: 64..256, multiple of 64 */
     int32_t mr_blocks_per_cu;       /* Miller-Rabin grids = CUs x this (at most 4096): 1..16 */

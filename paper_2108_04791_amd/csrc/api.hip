@@ -54,7 +54,9 @@ bool valid_config(const isp_config &c)
            (c.classify_ept == 1 || c.classify_ept == 2 || c.classify_ept == 4 ||
             c.classify_ept == 8) &&
            c.classify_blocks_per_cu >= 1 && c.classify_blocks_per_cu <= 16 &&
-           (c.filter_primes == -1 || (c.filter_primes >= 1 && c.filter_primes <= MAX_FILTER_PRIMES)) &&
+           (c.filter_primes == -1 || c.filter_primes == 8 || c.filter_primes == 16 ||
+            c.filter_primes == 24 || c.filter_primes == 32 || c.filter_primes == 48 ||
+            c.filter_primes == 64) &&
            (c.sort_survivors == -1 || c.sort_survivors == 1) && blk(c.mr_block, MR_MAX_BLOCK) &&
            c.mr_blocks_per_cu >= 1 && c.mr_blocks_per_cu <= 16 && c.mr_window >= 1 &&
            c.mr_window <= 4;
@@ -163,7 +165,6 @@ void make_args(const DeviceState &ds, const Workspace &ws, const Tuning &t, Clas
     grid1 = grid_of(ds.cus, t.mr_blocks_per_cu);
     ca = ClassifyArgs();
     ca.table = ds.table;
-    ca.filter = ds.filter;
     ca.nfilter = t.filter_primes;
     ca.sorted = t.sort_survivors;
     ca.surv = ws.surv;
@@ -214,7 +215,7 @@ int run_plain(const uint64_t *n, uint8_t *out, size_t len, const DeviceState &ds
         e = launch_mr1(ma, t.mr_block, s);
     mark(2);
     if (e == hipSuccess)
-        e = launch_mr2(ma, grid1, t.mr_block, t.mr_window, s);
+        e = launch_mr2(ma, ds.cus, t.mr_blocks_per_cu, t.mr_block, t.mr_window, s);
     mark(3);
     if (prof && e == hipSuccess) {
         e = hipEventSynchronize(g_prof_ev[ISP_NUM_STAGES]);
@@ -315,7 +316,7 @@ int build_graph(BatchCtx &c, const DeviceState &ds, const Tuning &t)
     if (ee == hipSuccess)
         ee = launch_mr1(ma, t.mr_block, c.cap_stream);
     if (ee == hipSuccess)
-        ee = launch_mr2(ma, grid1, t.mr_block, t.mr_window, c.cap_stream);
+        ee = launch_mr2(ma, ds.cus, t.mr_blocks_per_cu, t.mr_block, t.mr_window, c.cap_stream);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(c.cap_stream, &g);
     if (ee != hipSuccess) {
@@ -377,15 +378,11 @@ int isp_init(int device)
     if (e == hipSuccess)
         e = hipMalloc(&st.base_count, sizeof(uint32_t));
     if (e == hipSuccess)
-        e = hipMalloc(&st.filter, MAX_FILTER_PRIMES * sizeof(FilterPrime));
-    if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (e == hipSuccess)
         e = launch_base_primes(st, s);
     if (e == hipSuccess)
         e = launch_sieve(st, s);
-    if (e == hipSuccess)
-        e = launch_filter_consts(st, s);
     uint32_t count = 0;
     if (e == hipSuccess)
         e = hipMemcpyAsync(&count, st.base_count, sizeof(count), hipMemcpyDeviceToHost, s);
@@ -399,7 +396,6 @@ int isp_init(int device)
         (void)hipFree(st.table);
         (void)hipFree(st.base_primes);
         (void)hipFree(st.base_count);
-        (void)hipFree(st.filter);
         (void)hipSetDevice(prev);
         return fail(e);
     }
@@ -435,7 +431,6 @@ void isp_shutdown(void)
         (void)hipFree(ds.table);
         (void)hipFree(ds.base_primes);
         (void)hipFree(ds.base_count);
-        (void)hipFree(ds.filter);
         ds = DeviceState();
     }
 }

@@ -33,9 +33,47 @@ namespace {
 
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(8)));
 
-// 0 or 1: decided; 2: survivor of the filter.
-__device__ __forceinline__ int classify_one(uint64_t v, const uint32_t *__restrict__ table,
-                                            const FilterPrime *__restrict__ filt, int nfilt)
+// Compile-time table of the first odd primes with their inverses modulo 2^64
+// and the bound floor((2^64 - 1) / p), so the unrolled filter below uses
+// immediate constants and issues no memory load.
+constexpr bool ce_is_prime(uint64_t p)
+{
+    for (uint64_t d = 3; d * d <= p; d += 2)
+        if (p % d == 0)
+            return false;
+    return true;
+}
+
+constexpr uint64_t ce_inv64(uint64_t p)
+{
+    uint64_t x = (3 * p) ^ 2;
+    for (int k = 0; k < 4; ++k)
+        x *= 2 - p * x;
+    return x;
+}
+
+struct FilterTable {
+    uint64_t inv[MAX_FILTER_PRIMES];
+    uint64_t lim[MAX_FILTER_PRIMES];
+    constexpr FilterTable() : inv(), lim()
+    {
+        int k = 0;
+        for (uint64_t p = 3; k < MAX_FILTER_PRIMES; p += 2) {
+            if (ce_is_prime(p)) {
+                inv[k] = ce_inv64(p);
+                lim[k] = ~(uint64_t)0 / p;
+                ++k;
+            }
+        }
+    }
+};
+constexpr FilterTable FILTER{};
+static_assert(FILTER.inv[0] * 3 == 1 && FILTER.lim[0] == 6148914691236517205ull, "p = 3");
+static_assert(FILTER.inv[MAX_FILTER_PRIMES - 1] * 727 == 1, "the 128th odd prime is 727");
+
+// 0 or 1: decided; 2: survivor of the filter (NF odd primes).
+template <int NF>
+__device__ __forceinline__ int classify_one(uint64_t v, const uint32_t *__restrict__ table)
 {
     if (v < 3)
         return v == 2 ? 1 : 0;
@@ -43,10 +81,11 @@ __device__ __forceinline__ int classify_one(uint64_t v, const uint32_t *__restri
         return 0;
     if (v < TABLE_BOUND)
         return (int)((table[v >> 6] >> ((v >> 1) & 31)) & 1u);
-    for (int k = 0; k < nfilt; ++k)
-        if (v * filt[k].inv <= filt[k].lim)
-            return 0;
-    return 2;
+    bool divisible = false;
+#pragma unroll
+    for (int k = 0; k < NF; ++k)
+        divisible |= v * FILTER.inv[k] <= FILTER.lim[k];
+    return divisible ? 0 : 2;
 }
 
 // Sort key: 0 for bit length 64 ... 31 for bit length 33 (v >= 2^32).
@@ -62,11 +101,10 @@ struct ClassifyShared {
 // One pass: elements [base, base + EPT) of one array, those below `end`.
 // Writes the output bytes and appends the pass's survivors at
 // region[filled ...].  Called by every thread of the block.
-template <int EPT>
+template <int EPT, int NF>
 __device__ __forceinline__ void classify_pass(const uint64_t *__restrict__ n,
                                               uint8_t *__restrict__ out, uint64_t base,
                                               uint64_t end, const uint32_t *__restrict__ table,
-                                              const FilterPrime *__restrict__ filt, int nfilt,
                                               Survivor *__restrict__ region, uint32_t &filled,
                                               int sorted, ClassifyShared &sh)
 {
@@ -92,7 +130,7 @@ __device__ __forceinline__ void classify_pass(const uint64_t *__restrict__ n,
     uint8_t r[EPT];
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-        const int c = classify_one(v[j], table, filt, nfilt);
+        const int c = classify_one<NF>(v[j], table);
         sv[j] = c == 2 && base + j < end;
         r[j] = (uint8_t)(c == 1);
     }
@@ -196,7 +234,7 @@ __device__ __forceinline__ void classify_pass(const uint64_t *__restrict__ n,
 
 // Workgroup g classifies the element range [g * chunk, (g + 1) * chunk) of
 // the input (plain) or of the virtual concatenation of the arrays (batched).
-template <int EPT, bool BATCHED>
+template <int EPT, bool BATCHED, int NF>
 __global__ void __launch_bounds__(1024) classify_kernel(ClassifyArgs a)
 {
     __shared__ ClassifyShared sh;
@@ -214,8 +252,8 @@ __global__ void __launch_bounds__(1024) classify_kernel(ClassifyArgs a)
     if (r0 < r1) {
         if constexpr (!BATCHED) {
             for (uint64_t p0 = r0; p0 < r1; p0 += per_pass)
-                classify_pass<EPT>(a.n, a.out, p0 + (uint64_t)threadIdx.x * EPT, r1, a.table,
-                                   a.filter, a.nfilter, region, filled, a.sorted, sh);
+                classify_pass<EPT, NF>(a.n, a.out, p0 + (uint64_t)threadIdx.x * EPT, r1, a.table,
+                                       region, filled, a.sorted, sh);
         } else {
             const BatchDesc *d = a.desc;
             // first array overlapping r0: prefix[lo] <= r0 < prefix[hi]
@@ -236,13 +274,44 @@ __global__ void __launch_bounds__(1024) classify_kernel(ClassifyArgs a)
                 const uint64_t *nv = d->n_ptrs[k];
                 uint8_t *ov = d->out_ptrs[k];
                 for (uint64_t p0 = b0; p0 < b1; p0 += per_pass)
-                    classify_pass<EPT>(nv, ov, p0 + (uint64_t)threadIdx.x * EPT, b1, a.table,
-                                       a.filter, a.nfilter, region, filled, a.sorted, sh);
+                    classify_pass<EPT, NF>(nv, ov, p0 + (uint64_t)threadIdx.x * EPT, b1, a.table,
+                                           region, filled, a.sorted, sh);
             }
         }
     }
     if (threadIdx.x == 0)
         a.counts[g] = filled;
+}
+
+template <int EPT, bool BATCHED>
+hipError_t launch_classify_nf(const ClassifyArgs &a, unsigned grid, int block, hipStream_t s)
+{
+    switch (a.nfilter) {
+    case 0:
+        classify_kernel<EPT, BATCHED, 0><<<grid, block, 0, s>>>(a);
+        break;
+    case 8:
+        classify_kernel<EPT, BATCHED, 8><<<grid, block, 0, s>>>(a);
+        break;
+    case 16:
+        classify_kernel<EPT, BATCHED, 16><<<grid, block, 0, s>>>(a);
+        break;
+    case 24:
+        classify_kernel<EPT, BATCHED, 24><<<grid, block, 0, s>>>(a);
+        break;
+    case 32:
+        classify_kernel<EPT, BATCHED, 32><<<grid, block, 0, s>>>(a);
+        break;
+    case 48:
+        classify_kernel<EPT, BATCHED, 48><<<grid, block, 0, s>>>(a);
+        break;
+    case 64:
+        classify_kernel<EPT, BATCHED, 64><<<grid, block, 0, s>>>(a);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <bool BATCHED>
@@ -251,21 +320,16 @@ hipError_t launch_classify_t(const ClassifyArgs &a, unsigned grid, int block, in
 {
     switch (ept) {
     case 1:
-        classify_kernel<1, BATCHED><<<grid, block, 0, s>>>(a);
-        break;
+        return launch_classify_nf<1, BATCHED>(a, grid, block, s);
     case 2:
-        classify_kernel<2, BATCHED><<<grid, block, 0, s>>>(a);
-        break;
+        return launch_classify_nf<2, BATCHED>(a, grid, block, s);
     case 4:
-        classify_kernel<4, BATCHED><<<grid, block, 0, s>>>(a);
-        break;
+        return launch_classify_nf<4, BATCHED>(a, grid, block, s);
     case 8:
-        classify_kernel<8, BATCHED><<<grid, block, 0, s>>>(a);
-        break;
+        return launch_classify_nf<8, BATCHED>(a, grid, block, s);
     default:
         return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace

@@ -13,7 +13,7 @@ namespace isp {
 constexpr uint64_t TABLE_BOUND = (uint64_t)1 << 32;
 constexpr uint64_t TABLE_WORDS = (uint64_t)1 << 26;  // 2^31 odd numbers / 32
 constexpr int MAX_BASE_PRIMES = 6542;                // odd primes below 2^16: 6541
-constexpr int MAX_FILTER_PRIMES = 256;
+constexpr int MAX_FILTER_PRIMES = 128;
 constexpr int NUM_BINS = 32;                         // bit lengths 33..64
 constexpr int MR_MAX_BLOCK = 256;                    // launch bound of the Miller-Rabin kernels
 
@@ -21,14 +21,6 @@ constexpr int MR_MAX_BLOCK = 256;                    // launch bound of the Mill
 struct Survivor {
     uint64_t n;
     uint8_t *out;
-};
-
-// Exact divisibility test by a small odd prime p without division
-// (Granlund and Montgomery, PLDI 1994): p | n iff n * p^-1 mod 2^64 <= lim,
-// with lim = floor((2^64 - 1) / p).
-struct FilterPrime {
-    uint64_t inv;
-    uint64_t lim;
 };
 
 // Largest grid of the classify and Miller-Rabin kernels: their per-block
@@ -64,8 +56,7 @@ struct ClassifyArgs {
     const BatchDesc *desc;  // batched call (n, out unused); nullptr for plain
     uint64_t total;         // plain call: elements (batched: desc->total)
     const uint32_t *table;
-    const FilterPrime *filter;
-    int nfilter;
+    int nfilter;            // odd primes in the trial filter: 0, 8, 16, 24, 32, 48 or 64
     int sorted;             // order survivors by bit length within a pass
     Survivor *surv;         // grid regions of classify_chunk() entries
     uint32_t *counts;       // [grid] survivors per region
@@ -100,7 +91,6 @@ struct DeviceState {
     uint32_t *table = nullptr;       // TABLE_WORDS words
     uint32_t *base_primes = nullptr; // odd primes < 2^16
     uint32_t *base_count = nullptr;  // device word: how many
-    FilterPrime *filter = nullptr;   // first MAX_FILTER_PRIMES odd primes
     int num_base_primes = 0;
 };
 
@@ -115,12 +105,12 @@ struct Workspace {
 // ---- launchers (each enqueues on `stream` and returns hipError_t) ----
 hipError_t launch_base_primes(DeviceState &ds, hipStream_t s);
 hipError_t launch_sieve(DeviceState &ds, hipStream_t s);
-hipError_t launch_filter_consts(DeviceState &ds, hipStream_t s);
 
 hipError_t launch_classify(const ClassifyArgs &a, unsigned grid, int block, int ept,
                            hipStream_t s);
 hipError_t launch_mr1(const MrArgs &a, int block, hipStream_t s);
-hipError_t launch_mr2(const MrArgs &a, unsigned grid2, int block, int window, hipStream_t s);
+hipError_t launch_mr2(const MrArgs &a, int cus, int per_cu, int block, int window,
+                      hipStream_t s);
 
 hipError_t launch_montmul_test(const uint64_t *a, const uint64_t *b, const uint64_t *n,
                                uint64_t *out, uint64_t len, hipStream_t s);

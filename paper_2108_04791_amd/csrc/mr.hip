@@ -28,6 +28,11 @@
 // workgroup scans the producer's per-workgroup counts in LDS, takes an
 // equal slice of the resulting dense index space, and finds each element's
 // producer region by binary search in LDS.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "internal.h"
 #include "mont.h"
 
@@ -35,65 +40,64 @@ namespace isp {
 
 namespace {
 
-// Strong probable-prime test to base 2 for odd n >= 2^32.
+// Strong probable-prime test to base 2 for odd n >= 2^32, n - 1 = 2^s d.
+//
+// x runs over 2^(floor((n-1) / 2^t)) (Montgomery form) for t = L-1 down to
+// s: one squaring per bit and a modular doubling when the bit is set.
+// `rest` holds the bits of n - 1 below t shifted to the top, so the next
+// bit is its sign bit and rest == 0 right after bit s, the lowest set bit,
+// is consumed: then x = 2^d.  The chain 2^(2^r d), r = 1 .. s-1, follows
+// and stops as soon as -1 shows up.  A wavefront of one bit length runs
+// L - 2 steps plus the spread of s between its lanes.
 __device__ __forceinline__ bool sprp_base2(uint64_t n)
 {
     const int L = 64 - __clzll(n);
     const MontCtx c = make_ctx(n, L);
-    const uint64_t e = n - 1;
-    const int s = __ffsll((long long)e) - 1;
-    uint64_t x = dbl_mod(c.one, n);  // top bit of e (bit L-1): x = 2
-    bool pass = (s == L - 1) && (x == c.one || x == c.mone);
-    for (int t = L - 2; t >= 1; --t) {
+    uint64_t rest = (n - 1) << (65 - L);  // bits L-2 .. 0 of n - 1, at the top
+    uint64_t x = dbl_mod(c.one, n);        // bit L-1 (the leading one): x = 2
+    while (rest != 0) {
+        const bool bit = (int64_t)rest < 0;
+        rest <<= 1;
         x = montsqr(x, n, c.ninv);
-        const uint64_t x2 = dbl_mod(x, n);
-        x = ((e >> t) & 1) ? x2 : x;
-        pass |= (t == s) & ((x == c.one) | (x == c.mone));
-        pass |= (t < s) & (x == c.mone);
+        const uint64_t y = x + x;
+        const bool wrap = (int64_t)x < 0 || y >= n;  // 2x >= n, with the carry of x + x
+        x = bit ? (wrap ? y - n : y) : x;
+    }
+    bool pass = x == c.one || x == c.mone;
+    const int s = __ffsll((long long)(n - 1)) - 1;
+    for (int r = 1; r < s && !pass; ++r) {
+        x = montsqr(x, n, c.ninv);
+        pass = x == c.mone;
     }
     return pass;
 }
 
-// T[w] for a per-lane w < 2^W, as a tree of selects on the bits of w with
-// constant register indices (dynamic indexing would go through scratch).
+// Strong test for one base (am: its Montgomery form) with n - 1 = 2^s d.
+// a^d by a fixed window of W bits: the lane's table a^0 .. a^(2^W - 1) sits
+// in LDS, column threadIdx.x of tbl[2^W][blockDim] (each lane reads only
+// its own column, so no barrier is needed and the rows are bank-aligned).
 template <int W>
-__device__ __forceinline__ uint64_t select_pow(const uint64_t (&T)[1 << W], unsigned w)
-{
-    uint64_t v[1 << W];
-#pragma unroll
-    for (int k = 0; k < (1 << W); ++k)
-        v[k] = T[k];
-#pragma unroll
-    for (int level = 0; level < W; ++level) {
-        const bool bit = (w >> level) & 1;
-        const int step = 1 << level;
-#pragma unroll
-        for (int k = 0; k < (1 << W); k += 2 * step)
-            v[k] = bit ? v[k + step] : v[k];
-    }
-    return v[0];
-}
-
-// Strong test for one base a (in Montgomery form am) given d, s.
-template <int W>
-__device__ __forceinline__ bool sprp_window(uint64_t am, uint64_t d, int s, const MontCtx &c)
+__device__ __forceinline__ bool sprp_window(uint64_t am, uint64_t d, int s, const MontCtx &c,
+                                            uint64_t *tbl)
 {
     constexpr int TS = 1 << W;
-    uint64_t T[TS];
-    T[0] = c.one;
-    T[1] = am;
+    const unsigned col = threadIdx.x, stride = blockDim.x;
+    uint64_t p = c.one;
+    tbl[col] = p;
 #pragma unroll
-    for (int k = 2; k < TS; ++k)
-        T[k] = montmul(T[k - 1], am, c.n, c.ninv);
+    for (int k = 1; k < TS; ++k) {
+        p = k == 1 ? am : montmul(p, am, c.n, c.ninv);
+        tbl[k * stride + col] = p;
+    }
     const int Ld = 64 - __clzll(d);
     const int nwin = (Ld + W - 1) / W;
     int pos = (nwin - 1) * W;
-    uint64_t x = select_pow<W>(T, (unsigned)(d >> pos) & (TS - 1));
+    uint64_t x = tbl[((unsigned)(d >> pos) & (TS - 1)) * stride + col];
     for (pos -= W; pos >= 0; pos -= W) {
 #pragma unroll
         for (int k = 0; k < W; ++k)
             x = montsqr(x, c.n, c.ninv);
-        x = montmul(x, select_pow<W>(T, (unsigned)(d >> pos) & (TS - 1)), c.n, c.ninv);
+        x = montmul(x, tbl[((unsigned)(d >> pos) & (TS - 1)) * stride + col], c.n, c.ninv);
     }
     if (x == c.one || x == c.mone)
         return true;
@@ -107,14 +111,14 @@ __device__ __forceinline__ bool sprp_window(uint64_t am, uint64_t d, int s, cons
 
 // Strong test of odd n >= 2^32 to one base a < 2^32.
 template <int W>
-__device__ __forceinline__ bool sprp_one_base(uint64_t n, uint32_t a)
+__device__ __forceinline__ bool sprp_one_base(uint64_t n, uint32_t a, uint64_t *tbl)
 {
     const int L = 64 - __clzll(n);
     const MontCtx c = make_ctx(n, L);
     const uint64_t r2 = r2_mod_n(c);
     const uint64_t e = n - 1;
     const int s = __ffsll((long long)e) - 1;
-    return sprp_window<W>(to_mont(a, r2, c), e >> s, s, c);
+    return sprp_window<W>(to_mont(a, r2, c), e >> s, s, c, tbl);
 }
 
 // Exclusive prefix of counts[0..nc) into pre[0..nc] (pre[nc] = total), in
@@ -179,7 +183,8 @@ __device__ __forceinline__ uint64_t call_total(const MrArgs &a)
 
 __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
 {
-    __shared__ uint32_t pre[MAX_GRID + 1];
+    extern __shared__ uint64_t dyn[];
+    uint32_t *pre = reinterpret_cast<uint32_t *>(dyn);  // grid_c + 1 entries
     __shared__ uint32_t wsum[MR_MAX_BLOCK / 64];
     __shared__ uint32_t wave_cnt[MR_MAX_BLOCK / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
@@ -227,7 +232,11 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
 template <int W>
 __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase2_kernel(MrArgs a)
 {
-    __shared__ uint32_t pre[MAX_GRID + 1];
+    // dynamic LDS: the window tables (2^W x blockDim values), then the
+    // prefix of the base-2 counts (grid1 + 1 entries)
+    extern __shared__ uint64_t dyn[];
+    uint64_t *tbl = dyn;
+    uint32_t *pre = reinterpret_cast<uint32_t *>(dyn + (1u << W) * blockDim.x);
     __shared__ uint32_t wsum[MR_MAX_BLOCK / 64];
     constexpr uint32_t BASES[6] = {325u, 9375u, 28178u, 450775u, 9780504u, 1795265022u};
     constexpr int PER_WAVE = 10;  // candidates per wavefront, 6 lanes each
@@ -250,7 +259,7 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase2_kernel(MrArgs a)
             const uint32_t k = find_region(pre, a.grid1, j);
             const Survivor sv = a.cand[(uint64_t)k * chunk_1 + (j - pre[k])];
             out = sv.out;
-            ok = sprp_one_base<W>(sv.n, BASES[b]);
+            ok = sprp_one_base<W>(sv.n, BASES[b], tbl);
         }
         const uint64_t m = __ballot(ok);
         if (active && b == 0 && ((m >> lane) & 0x3full) == 0x3full)
@@ -276,26 +285,71 @@ __global__ void montmul_test_kernel(const uint64_t *__restrict__ a, const uint64
 
 }  // namespace
 
+size_t mr1_lds(const MrArgs &a) { return ((size_t)a.grid_c + 1) * sizeof(uint32_t); }
+
+size_t mr2_lds(const MrArgs &a, int block, int window)
+{
+    return ((size_t)block << window) * sizeof(uint64_t) + ((size_t)a.grid1 + 1) * sizeof(uint32_t);
+}
+
 hipError_t launch_mr1(const MrArgs &a, int block, hipStream_t s)
 {
-    mr_phase1_kernel<<<a.grid1, block, 0, s>>>(a);
+    mr_phase1_kernel<<<a.grid1, block, mr1_lds(a), s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_mr2(const MrArgs &a, unsigned grid2, int block, int window, hipStream_t s)
+// Workgroups of phase 2 that fit on one CU at once (LDS or registers
+// permitting): its grid is all resident, since each workgroup takes one
+// static slice.
+int mr2_resident_per_cu(int block, int window, size_t lds)
 {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, size_t>, int> cache;
+    std::lock_guard<std::mutex> g(mu);
+    auto key = std::make_tuple(block, window, lds);
+    auto it = cache.find(key);
+    if (it != cache.end())
+        return it->second;
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
     switch (window) {
     case 1:
-        mr_phase2_kernel<1><<<grid2, block, 0, s>>>(a);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mr_phase2_kernel<1>, block, lds);
         break;
     case 2:
-        mr_phase2_kernel<2><<<grid2, block, 0, s>>>(a);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mr_phase2_kernel<2>, block, lds);
         break;
     case 3:
-        mr_phase2_kernel<3><<<grid2, block, 0, s>>>(a);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mr_phase2_kernel<3>, block, lds);
         break;
     case 4:
-        mr_phase2_kernel<4><<<grid2, block, 0, s>>>(a);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mr_phase2_kernel<4>, block, lds);
+        break;
+    }
+    if (e != hipSuccess || nb < 1)
+        nb = 1;
+    cache[key] = nb;
+    return nb;
+}
+
+hipError_t launch_mr2(const MrArgs &a, int cus, int per_cu, int block, int window,
+                      hipStream_t s)
+{
+    const size_t lds = mr2_lds(a, block, window);
+    const int fit = mr2_resident_per_cu(block, window, lds);
+    const unsigned grid = (unsigned)std::max(1, std::min(MAX_GRID, cus * std::min(per_cu, fit)));
+    switch (window) {
+    case 1:
+        mr_phase2_kernel<1><<<grid, block, lds, s>>>(a);
+        break;
+    case 2:
+        mr_phase2_kernel<2><<<grid, block, lds, s>>>(a);
+        break;
+    case 3:
+        mr_phase2_kernel<3><<<grid, block, lds, s>>>(a);
+        break;
+    case 4:
+        mr_phase2_kernel<4><<<grid, block, lds, s>>>(a);
         break;
     default:
         return hipErrorInvalidValue;

@@ -19,8 +19,6 @@
 //                       from max(p^2, segment start) by a whole wavefront,
 //                       lane l taking the multiples l, l+64, l+128, ... of
 //                       the stride p (in bit units), with LDS atomic ANDs.
-//   filter_consts_kernel  inverse mod 2^64 and floor((2^64-1)/p) of the first
-//                       odd primes, for the division-free divisibility test.
 #include "internal.h"
 #include "mont.h"
 
@@ -137,16 +135,6 @@ __global__ void __launch_bounds__(SIEVE_THREADS) sieve_kernel(uint32_t *__restri
         table[w0 + k] = seg[k];
 }
 
-__global__ void filter_consts_kernel(const uint32_t *__restrict__ primes, FilterPrime *__restrict__ f)
-{
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= MAX_FILTER_PRIMES)
-        return;
-    const uint64_t p = primes[k];
-    f[k].inv = inv64(p);
-    f[k].lim = ~(uint64_t)0 / p;
-}
-
 }  // namespace
 
 hipError_t launch_base_primes(DeviceState &ds, hipStream_t s)
@@ -160,12 +148,6 @@ hipError_t launch_sieve(DeviceState &ds, hipStream_t s)
     static_assert(TABLE_WORDS % SEG_WORDS == 0, "segments tile the table");
     sieve_kernel<<<(unsigned)(TABLE_WORDS / SEG_WORDS), SIEVE_THREADS, 0, s>>>(
         ds.table, ds.base_primes, ds.base_count);
-    return hipGetLastError();
-}
-
-hipError_t launch_filter_consts(DeviceState &ds, hipStream_t s)
-{
-    filter_consts_kernel<<<(MAX_FILTER_PRIMES + 255) / 256, 256, 0, s>>>(ds.base_primes, ds.filter);
     return hipGetLastError();
 }
 

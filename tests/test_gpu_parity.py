@@ -180,7 +180,7 @@ def test_counts_match_host_accounting(isp):
     dict(classify_ept=2, classify_block=1024, classify_blocks_per_cu=1),
     dict(classify_ept=8, classify_block=128, classify_blocks_per_cu=16),
     dict(filter_primes=-1),
-    dict(filter_primes=256),
+    dict(filter_primes=64), dict(filter_primes=8),
     dict(sort_survivors=-1),
     dict(mr_window=1), dict(mr_window=2), dict(mr_window=4),
     dict(mr_block=64, mr_blocks_per_cu=1),
