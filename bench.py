@@ -103,12 +103,130 @@ def mr_work(a: np.ndarray, prime: np.ndarray, filter_primes: int):
     return work, int(keep.sum()), int(pr.sum())
 
 
+def bench_batched(isp, W, torch, reps: int = 5) -> dict:
+    """4096 arrays of log-uniform length in [1, 2^16], magnitude class per
+    array: one isprime_u64_batched call (graph replay) vs one isprime_u64
+    call per array on the same stream."""
+    arrays = W.c4_batched()
+    total = sum(a.size for a, _ in arrays)
+    dev = [torch.from_numpy(a.view(np.int64)).cuda() for a, _ in arrays]
+    outs = [torch.empty(a.size, dtype=torch.uint8, device="cuda") for a, _ in arrays]
+    stream = torch.cuda.current_stream()
+
+    def batched():
+        isp.isprime_batched(dev, outs, stream)
+
+    def plain():
+        for d, o in zip(dev, outs):
+            isp.isprime_into(d, o, stream)
+
+    res = {}
+    for name, fn in (("batched", batched), ("plain_per_array", plain)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = {"ms": ms, "tests_per_s": total / (ms * 1e-3)}
+    res["arrays"] = len(arrays)
+    res["elements"] = total
+    res["speedup"] = res["plain_per_array"]["ms"] / res["batched"]["ms"]
+    return res
+
+
+def bench_served(isp, W, torch, num: int = 2100, warm: int = 100) -> dict:
+    """Poisson request stream (lengths log-uniform in [1, 2^20], magnitude
+    class per request) served by the continuous-batching server, against the
+    same stream served FIFO by serial plain calls (copy in, isprime_u64, copy
+    out, synchronise).  Arrival rate: 0.7 x the server's measured capacity.
+    Latency = arrival to result in the caller's host array."""
+    import threading
+    reqs = W.c5_requests(num, qps=1.0)  # arrival times for rate 1; rescaled below
+    arrays = [r for _, r, _ in reqs]
+    unit_t = np.array([t for t, _, _ in reqs])
+    elems = sum(a.size for a in arrays[warm:])
+
+    srv = isp.Server(max_inflight=3, max_batch_elems=1 << 22)
+    try:
+        # capacity: everything submitted at once
+        outs = [np.zeros(a.size, np.uint8) for a in arrays]
+        t0 = time.perf_counter()
+        tk = [srv.submit(a, o) for a, o in zip(arrays, outs)]
+        for t in tk:
+            srv.wait(t)
+        cap_s = time.perf_counter() - t0
+        capacity = num / cap_s
+        qps = 0.7 * capacity
+        arrive = unit_t / qps
+
+        def run_served():
+            lat = np.zeros(num)
+            done_t = np.zeros(num)
+            tickets = [None] * num
+            ready = threading.Semaphore(0)
+            base = time.perf_counter() + 0.01
+
+            def waiter():
+                for i in range(num):
+                    ready.acquire()
+                    srv.wait(tickets[i])
+                    done_t[i] = time.perf_counter() - base
+
+            th = threading.Thread(target=waiter)
+            th.start()
+            for i in range(num):
+                d = base + arrive[i] - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(arrays[i], outs[i])
+                ready.release()
+            th.join()
+            lat[:] = done_t - arrive
+            return lat, done_t[-1] - arrive[warm]
+
+        lat_s, span_s = run_served()
+    finally:
+        srv.close()
+
+    # baseline: serial plain calls in arrival order
+    stream = torch.cuda.current_stream()
+    lat_p = np.zeros(num)
+    base = time.perf_counter() + 0.01
+    t_free = 0.0
+    for i, a in enumerate(arrays):
+        now = time.perf_counter() - base
+        if now < arrive[i]:
+            time.sleep(arrive[i] - now)
+        d = torch.from_numpy(a.view(np.int64)).cuda()
+        o = torch.empty(a.size, dtype=torch.uint8, device="cuda")
+        isp.isprime_into(d, o, stream)
+        o.cpu()
+        t_free = time.perf_counter() - base
+        lat_p[i] = t_free - arrive[i]
+    span_p = t_free - arrive[warm]
+
+    def stats(lat, span):
+        m = lat[warm:] * 1e3
+        return {"p50_ms": float(np.percentile(m, 50)), "p99_ms": float(np.percentile(m, 99)),
+                "mean_ms": float(m.mean()), "tests_per_s": elems / span}
+
+    return {"requests": num - warm, "warmup_requests": warm, "elements": int(elems),
+            "capacity_req_per_s": capacity, "qps": qps,
+            "served": stats(lat_s, span_s), "serial_plain": stats(lat_p, span_p)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched and served measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters)")
@@ -187,6 +305,11 @@ def main() -> int:
         ach = work[k]["ops"] / (stage_ms[k] * 1e-3) / 1e9
         other[k] = {"achieved": ach, "frac": ach / VALU_PEAK_GOPS}
 
+    forms = {}
+    if not args.no_forms:
+        forms["batched"] = bench_batched(isp, W, torch)
+        forms["served"] = bench_served(isp, W, torch)
+
     cpu = None
     bit_exact = None
     if not args.no_cpu_baseline:
@@ -224,6 +347,7 @@ def main() -> int:
         "primes": int(got.sum()),
         "sieve_build_ms": sieve_ms,
     }
+    line.update(forms)
     print(json.dumps(line), flush=True)
     return 0 if bit_exact in (None, True) else 1
 

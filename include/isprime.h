@@ -162,15 +162,22 @@ typedef struct isp_server isp_server;
 typedef struct {
     int32_t device;            /* HIP device ordinal */
     int32_t max_inflight;      /* batches on the device at once: 1..8 (0 = 3) */
-    uint64_t mem_budget_bytes; /* device bytes for request data (0 = 1 GiB) */
-    uint64_t max_batch_elems;  /* elements per batch (0 = 4,194,304) */
-    int32_t max_batch_reqs;    /* requests per batch (0 = 1024) */
-    int32_t block_on_full;     /* 1: isp_submit waits for capacity; 0: ISP_EBUSY */
+    uint64_t mem_budget_bytes; /* bytes of admitted requests, 9 per element (0 = 1 GiB) */
+    uint64_t max_batch_elems;  /* elements per batch, at most 2^28 (0 = 4,194,304) */
+    int32_t max_batch_reqs;    /* request pieces per batch (0 = 1024) */
+    int32_t block_on_full;     /* 1: isp_submit waits for budget; 0: ISP_EBUSY */
+    int32_t test_mode;         /* 0: the device; 1: a host stand-in that writes n & 1, for
+                                  testing the queueing without a GPU (no HIP call at all) */
+    int32_t test_fail_every;   /* test mode: every k-th batch fails with ISP_EDEVICE (0: never) */
+    int32_t test_delay_us;     /* test mode: time each batch takes */
+    int32_t reserved;
 } isp_server_config;
 
 int isp_server_create(const isp_server_config *cfg, isp_server **srv);
-/* Queue one request; `ticket` receives its id.  len may be 0.  A request
- * larger than the memory budget is split into pieces internally. */
+/* Queue one request; `ticket` receives its id.  len may be 0.  The request
+ * holds 9 * len bytes of the budget until it completes; one larger than the
+ * whole budget is admitted when nothing else holds any.  Requests are split
+ * into pieces of at most max_batch_elems. */
 int isp_submit(isp_server *srv, const uint64_t *host_n, uint8_t *host_out, size_t len,
                uint64_t *ticket);
 /* 1 done, 0 pending, <0 error (ISP_ENOENT for an unknown or consumed ticket). */
@@ -178,7 +185,8 @@ int isp_poll(isp_server *srv, uint64_t ticket);
 /* Block until the request is done (timeout_us < 0: no limit).  Consumes the
  * ticket on success. */
 int isp_wait(isp_server *srv, uint64_t ticket, int64_t timeout_us);
-/* Drain every request, stop the worker threads, free the server. */
+/* Finish every queued request, stop the worker threads, free the server.
+ * No other call on this server may be in progress or follow. */
 int isp_server_destroy(isp_server *srv);
 
 #ifdef __cplusplus

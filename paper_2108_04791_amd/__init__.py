@@ -69,6 +69,10 @@ class ServerConfig(ctypes.Structure):
         ("max_batch_elems", ctypes.c_uint64),
         ("max_batch_reqs", ctypes.c_int32),
         ("block_on_full", ctypes.c_int32),
+        ("test_mode", ctypes.c_int32),
+        ("test_fail_every", ctypes.c_int32),
+        ("test_delay_us", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -97,9 +101,6 @@ SIGNATURES = {
 }
 
 
-_SERVING = {"isp_server_create", "isp_submit", "isp_poll", "isp_wait", "isp_server_destroy"}
-
-
 def lib() -> ctypes.CDLL:
     """The loaded library; raises if it has not been built."""
     global _lib
@@ -111,8 +112,6 @@ def lib() -> ctypes.CDLL:
                     "this package has no CPU fallback")
             L = ctypes.CDLL(LIB_PATH)
             for name, (res, args) in SIGNATURES.items():
-                if name in _SERVING and not hasattr(L, name):
-                    continue  # serving entry points not built yet
                 fn = getattr(L, name)
                 fn.restype = res
                 fn.argtypes = args
@@ -281,21 +280,26 @@ class Server:
     """Continuous-batching request server over host buffers (isp_server_*)."""
 
     def __init__(self, device: int = 0, max_inflight: int = 0, mem_budget_bytes: int = 0,
-                 max_batch_elems: int = 0, max_batch_reqs: int = 0, block_on_full: bool = True):
+                 max_batch_elems: int = 0, max_batch_reqs: int = 0, block_on_full: bool = True,
+                 test_mode: int = 0, test_fail_every: int = 0, test_delay_us: int = 0):
         cfg = ServerConfig(device, max_inflight, mem_budget_bytes, max_batch_elems,
-                           max_batch_reqs, 1 if block_on_full else 0)
+                           max_batch_reqs, 1 if block_on_full else 0, test_mode,
+                           test_fail_every, test_delay_us, 0)
         h = _P()
         _check(lib().isp_server_create(ctypes.byref(cfg), ctypes.byref(h)), "isp_server_create")
         self._h = h
         self._keep = {}
 
     def submit(self, n, out) -> int:
-        """Queue host arrays n (uint64) -> out (uint8); both must stay alive."""
+        """Queue host arrays n (uint64) -> out (uint8); kept alive until waited on."""
         import numpy as np
-        assert n.dtype == np.uint64 and out.dtype == np.uint8 and n.size == out.size
-        assert n.flags["C_CONTIGUOUS"] and out.flags["C_CONTIGUOUS"]
+        if n.dtype != np.uint64 or out.dtype != np.uint8 or n.size != out.size:
+            raise TypeError("submit needs uint64 n and uint8 out of the same size")
+        if not (n.flags["C_CONTIGUOUS"] and out.flags["C_CONTIGUOUS"]):
+            raise ValueError("submit needs contiguous arrays")
         t = _U64()
-        _check(lib().isp_submit(self._h, n.ctypes.data, out.ctypes.data, n.size, ctypes.byref(t)),
+        _check(lib().isp_submit(self._h, n.ctypes.data if n.size else None,
+                                out.ctypes.data if out.size else None, n.size, ctypes.byref(t)),
                "isp_submit")
         self._keep[t.value] = (n, out)
         return t.value

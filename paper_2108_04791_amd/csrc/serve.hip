@@ -1,0 +1,428 @@
+// serve.hip -- request server with continuous batching (host code).
+//
+// A client submits a request (host arrays n[len] -> out[len]) and gets a
+// ticket.  Admission reserves 9 bytes per element (8 in, 1 out) from the
+// memory budget; a request that does not fit waits (or is refused with
+// ISP_EBUSY) until earlier requests complete.  Admitted requests are split
+// into pieces of at most max_batch_elems and queued.
+//
+// The dispatcher thread keeps up to max_inflight batches on the device: as
+// soon as a slot is free it packs the queued pieces (in arrival order) into
+// that slot's pinned staging buffer, and enqueues on the slot's own stream
+// the host-to-device copy, the isprime_u64 kernels over the whole packed
+// buffer (elements are independent, so one call classifies every piece),
+// the device-to-host copy and an event.  Requests that arrive while other
+// batches run are therefore packed into the next batch as capacity frees
+// up, and batches on different streams overlap on the device.
+//
+// The completer thread waits for the oldest in-flight batch, scatters its
+// results to the requests' output arrays, and completes each request whose
+// last piece has arrived.  A failed batch fails exactly the requests that
+// had pieces in it.
+//
+// Test mode (cfg.test_mode = 1): no device at all; a batch "runs" on the
+// completer thread and writes n & 1 for every element, optionally after a
+// delay and with every k-th batch failing, so the queueing, admission,
+// splitting and error paths can be checked on a machine without a GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    uint64_t ticket = 0;
+    const uint64_t *n = nullptr;
+    uint8_t *out = nullptr;
+    size_t len = 0;
+    size_t pieces_left = 0;
+    size_t bytes = 0;
+    int status = ISP_OK;
+    bool done = false;
+};
+
+struct Piece {
+    Request *req;
+    size_t off;  // in the request
+    size_t len;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    uint64_t *d_n = nullptr;
+    uint8_t *d_out = nullptr;
+    uint64_t *h_n = nullptr;  // pinned (plain heap in test mode)
+    uint8_t *h_out = nullptr;
+    std::vector<Piece> pieces;
+    size_t elems = 0;
+    int status = ISP_OK;
+    bool busy = false;
+};
+
+}  // namespace
+
+struct isp_server {
+    isp_server_config cfg{};
+    std::mutex mu;
+    std::condition_variable cv_dispatch;  // queued work or a free slot
+    std::condition_variable cv_complete;  // a batch in flight
+    std::condition_variable cv_space;     // budget freed
+    std::condition_variable cv_done;      // a request completed
+    std::deque<Piece> queue;
+    std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
+    std::deque<Slot *> inflight;
+    std::vector<std::unique_ptr<Slot>> slots;
+    uint64_t next_ticket = 1;
+    uint64_t bytes_in_use = 0;
+    uint64_t batches = 0;
+    bool stop = false;
+    bool dispatcher_done = false;
+    std::thread dispatcher, completer;
+};
+
+namespace {
+
+constexpr size_t BYTES_PER_ELEM = sizeof(uint64_t) + sizeof(uint8_t);
+
+void free_slot_resources(isp_server *s, Slot &sl)
+{
+    if (s->cfg.test_mode) {
+        delete[] sl.h_n;
+        delete[] sl.h_out;
+    } else {
+        if (sl.d_n)
+            (void)hipFree(sl.d_n);
+        if (sl.d_out)
+            (void)hipFree(sl.d_out);
+        if (sl.h_n)
+            (void)hipHostFree(sl.h_n);
+        if (sl.h_out)
+            (void)hipHostFree(sl.h_out);
+        if (sl.done)
+            (void)hipEventDestroy(sl.done);
+        if (sl.stream)
+            (void)hipStreamDestroy(sl.stream);
+    }
+    sl = Slot();
+}
+
+// Caller holds s->mu.  Marks the pieces of a finished batch.
+void finish_batch(isp_server *s, Slot &sl)
+{
+    for (const Piece &p : sl.pieces) {
+        Request *r = p.req;
+        if (sl.status != ISP_OK && r->status == ISP_OK)
+            r->status = sl.status;
+        if (--r->pieces_left == 0) {
+            r->done = true;
+            s->bytes_in_use -= r->bytes;
+        }
+    }
+    sl.pieces.clear();
+    sl.elems = 0;
+    sl.status = ISP_OK;
+    sl.busy = false;
+}
+
+void dispatcher_main(isp_server *s)
+{
+    if (!s->cfg.test_mode)
+        (void)hipSetDevice(s->cfg.device);
+    const size_t cap = s->cfg.max_batch_elems;
+    for (;;) {
+        Slot *sl = nullptr;
+        {
+            std::unique_lock<std::mutex> g(s->mu);
+            s->cv_dispatch.wait(g, [&] {
+                if (s->stop && s->queue.empty())
+                    return true;
+                if (s->queue.empty())
+                    return false;
+                for (auto &x : s->slots)
+                    if (!x->busy)
+                        return true;
+                return false;
+            });
+            if (s->queue.empty()) {  // stopping and drained
+                s->dispatcher_done = true;
+                s->cv_complete.notify_all();
+                return;
+            }
+            for (auto &x : s->slots)
+                if (!x->busy) {
+                    sl = x.get();
+                    break;
+                }
+            // pack queued pieces in arrival order
+            while (!s->queue.empty() && (int)sl->pieces.size() < s->cfg.max_batch_reqs &&
+                   sl->elems + s->queue.front().len <= cap) {
+                sl->pieces.push_back(s->queue.front());
+                sl->elems += s->queue.front().len;
+                s->queue.pop_front();
+            }
+            sl->busy = true;
+        }
+        // stage the inputs (outside the lock: the host arrays belong to the
+        // requests until they complete)
+        size_t off = 0;
+        for (const Piece &p : sl->pieces) {
+            std::memcpy(sl->h_n + off, p.req->n + p.off, p.len * sizeof(uint64_t));
+            off += p.len;
+        }
+        int st = ISP_OK;
+        if (!s->cfg.test_mode) {
+            hipError_t e = hipMemcpyAsync(sl->d_n, sl->h_n, sl->elems * sizeof(uint64_t),
+                                          hipMemcpyHostToDevice, sl->stream);
+            if (e == hipSuccess) {
+                st = isprime_u64(sl->d_n, sl->d_out, sl->elems, sl->stream);
+                if (st == ISP_OK)
+                    e = hipMemcpyAsync(sl->h_out, sl->d_out, sl->elems, hipMemcpyDeviceToHost,
+                                       sl->stream);
+            }
+            if (e == hipSuccess && st == ISP_OK)
+                e = hipEventRecord(sl->done, sl->stream);
+            if (e != hipSuccess && st == ISP_OK)
+                st = ISP_EDEVICE;
+        }
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            sl->status = st;
+            ++s->batches;
+            s->inflight.push_back(sl);
+        }
+        s->cv_complete.notify_one();
+    }
+}
+
+void completer_main(isp_server *s)
+{
+    if (!s->cfg.test_mode)
+        (void)hipSetDevice(s->cfg.device);
+    uint64_t seen = 0;
+    for (;;) {
+        Slot *sl = nullptr;
+        {
+            std::unique_lock<std::mutex> g(s->mu);
+            s->cv_complete.wait(g, [&] { return !s->inflight.empty() || s->dispatcher_done; });
+            if (s->inflight.empty())
+                return;  // dispatcher finished and nothing in flight
+            sl = s->inflight.front();
+            s->inflight.pop_front();
+        }
+        ++seen;
+        int st = sl->status;
+        if (s->cfg.test_mode) {
+            if (s->cfg.test_delay_us > 0)
+                std::this_thread::sleep_for(std::chrono::microseconds(s->cfg.test_delay_us));
+            if (s->cfg.test_fail_every > 0 && seen % (uint64_t)s->cfg.test_fail_every == 0)
+                st = ISP_EDEVICE;
+            else
+                for (size_t i = 0; i < sl->elems; ++i)
+                    sl->h_out[i] = (uint8_t)(sl->h_n[i] & 1);
+        } else if (st == ISP_OK) {
+            hipError_t e = hipEventSynchronize(sl->done);
+            if (e != hipSuccess)
+                st = ISP_EDEVICE;
+        } else {
+            // a failed enqueue may have left the copy of h_n in flight
+            (void)hipStreamSynchronize(sl->stream);
+        }
+        if (st == ISP_OK) {
+            size_t off = 0;
+            for (const Piece &p : sl->pieces) {
+                std::memcpy(p.req->out + p.off, sl->h_out + off, p.len);
+                off += p.len;
+            }
+        }
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            sl->status = st;
+            finish_batch(s, *sl);
+        }
+        s->cv_done.notify_all();
+        s->cv_space.notify_all();
+        s->cv_dispatch.notify_one();
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int isp_server_create(const isp_server_config *cfg, isp_server **srv)
+{
+    if (!cfg || !srv)
+        return ISP_EINVAL;
+    std::unique_ptr<isp_server> s(new isp_server());
+    s->cfg = *cfg;
+    isp_server_config &c = s->cfg;
+    if (!c.max_inflight)
+        c.max_inflight = 3;
+    if (!c.mem_budget_bytes)
+        c.mem_budget_bytes = (uint64_t)1 << 30;
+    if (!c.max_batch_elems)
+        c.max_batch_elems = (uint64_t)1 << 22;
+    if (!c.max_batch_reqs)
+        c.max_batch_reqs = 1024;
+    if (c.max_inflight < 1 || c.max_inflight > 8 || c.max_batch_reqs < 1 ||
+        c.max_batch_elems > ((uint64_t)1 << 28) || c.test_mode < 0 || c.test_mode > 1)
+        return ISP_EINVAL;
+    if (!c.test_mode) {
+        int st = isp_init(c.device);
+        if (st != ISP_OK)
+            return st;
+    }
+    int prev = 0;
+    if (!c.test_mode && hipGetDevice(&prev) != hipSuccess)
+        return ISP_EDEVICE;
+    if (!c.test_mode && hipSetDevice(c.device) != hipSuccess)
+        return ISP_EDEVICE;
+    int st = ISP_OK;
+    for (int k = 0; k < c.max_inflight && st == ISP_OK; ++k) {
+        std::unique_ptr<Slot> sl(new Slot());
+        const size_t cap = c.max_batch_elems;
+        if (c.test_mode) {
+            sl->h_n = new uint64_t[cap];
+            sl->h_out = new uint8_t[cap];
+        } else {
+            hipError_t e = hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking);
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(&sl->done, hipEventDisableTiming);
+            if (e == hipSuccess)
+                e = hipMalloc(&sl->d_n, cap * sizeof(uint64_t));
+            if (e == hipSuccess)
+                e = hipMalloc(&sl->d_out, cap);
+            if (e == hipSuccess)
+                e = hipHostMalloc(&sl->h_n, cap * sizeof(uint64_t), hipHostMallocDefault);
+            if (e == hipSuccess)
+                e = hipHostMalloc(&sl->h_out, cap, hipHostMallocDefault);
+            if (e != hipSuccess)
+                st = e == hipErrorOutOfMemory ? ISP_ENOMEM : ISP_EDEVICE;
+        }
+        s->slots.push_back(std::move(sl));
+    }
+    if (!c.test_mode)
+        (void)hipSetDevice(prev);
+    if (st != ISP_OK) {
+        for (auto &sl : s->slots)
+            free_slot_resources(s.get(), *sl);
+        return st;
+    }
+    isp_server *raw = s.release();
+    raw->dispatcher = std::thread(dispatcher_main, raw);
+    raw->completer = std::thread(completer_main, raw);
+    *srv = raw;
+    return ISP_OK;
+}
+
+int isp_submit(isp_server *s, const uint64_t *host_n, uint8_t *host_out, size_t len,
+               uint64_t *ticket)
+{
+    if (!s || !ticket || (len && (!host_n || !host_out)))
+        return ISP_EINVAL;
+    const uint64_t bytes = (uint64_t)len * BYTES_PER_ELEM;
+    std::unique_lock<std::mutex> g(s->mu);
+    if (s->stop)
+        return ISP_EINVAL;
+    // admit when it fits the budget, or when nothing else holds any of it
+    auto fits = [&] { return s->bytes_in_use == 0 || s->bytes_in_use + bytes <= s->cfg.mem_budget_bytes; };
+    if (!fits()) {
+        if (!s->cfg.block_on_full)
+            return ISP_EBUSY;
+        s->cv_space.wait(g, fits);
+    }
+    std::unique_ptr<Request> r(new Request());
+    r->ticket = s->next_ticket++;
+    r->n = host_n;
+    r->out = host_out;
+    r->len = len;
+    r->bytes = bytes;
+    const size_t cap = s->cfg.max_batch_elems;
+    r->pieces_left = len ? (len + cap - 1) / cap : 0;
+    if (len == 0) {
+        r->done = true;
+    } else {
+        s->bytes_in_use += bytes;
+        for (size_t off = 0; off < len; off += cap)
+            s->queue.push_back(Piece{r.get(), off, std::min(cap, len - off)});
+    }
+    *ticket = r->ticket;
+    s->reqs[r->ticket] = std::move(r);
+    g.unlock();
+    s->cv_dispatch.notify_one();
+    if (len == 0)
+        s->cv_done.notify_all();
+    return ISP_OK;
+}
+
+int isp_poll(isp_server *s, uint64_t ticket)
+{
+    if (!s)
+        return ISP_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end())
+        return ISP_ENOENT;
+    if (!it->second->done)
+        return 0;
+    return it->second->status == ISP_OK ? 1 : it->second->status;
+}
+
+int isp_wait(isp_server *s, uint64_t ticket, int64_t timeout_us)
+{
+    if (!s)
+        return ISP_EINVAL;
+    std::unique_lock<std::mutex> g(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end())
+        return ISP_ENOENT;
+    Request *r = it->second.get();
+    if (timeout_us < 0) {
+        s->cv_done.wait(g, [&] { return r->done; });
+    } else if (!s->cv_done.wait_for(g, std::chrono::microseconds(timeout_us),
+                                    [&] { return r->done; })) {
+        return ISP_ETIMEDOUT;
+    }
+    const int st = r->status;
+    s->reqs.erase(ticket);
+    return st;
+}
+
+int isp_server_destroy(isp_server *s)
+{
+    if (!s)
+        return ISP_EINVAL;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+    }
+    s->cv_dispatch.notify_all();
+    s->cv_complete.notify_all();
+    if (s->dispatcher.joinable())
+        s->dispatcher.join();
+    if (s->completer.joinable())
+        s->completer.join();
+    if (!s->cfg.test_mode)
+        (void)hipSetDevice(s->cfg.device);
+    for (auto &sl : s->slots)
+        free_slot_resources(s, *sl);
+    delete s;
+    return ISP_OK;
+}
+
+}  // extern "C"
