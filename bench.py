@@ -103,6 +103,24 @@ def mr_work(a: np.ndarray, prime: np.ndarray, filter_primes: int):
     return work, int(keep.sum()), int(pr.sum())
 
 
+def bench_plain(isp, torch, a: np.ndarray, reps: int = 10) -> dict:
+    """Plain isprime_u64 throughput on one resident array (HIP events)."""
+    dev = torch.from_numpy(a.view(np.int64)).cuda()
+    out = torch.empty(a.size, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    isp.isprime_into(dev, out, stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        isp.isprime_into(dev, out, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"len": int(a.size), "ms": ms, "tests_per_s": a.size / (ms * 1e-3),
+            "primes": int(out.sum().item())}
+
+
 def bench_batched(isp, W, torch, reps: int = 5) -> dict:
     """4096 arrays of log-uniform length in [1, 2^16], magnitude class per
     array: one isprime_u64_batched call (graph replay) vs one isprime_u64
@@ -307,6 +325,10 @@ def main() -> int:
 
     forms = {}
     if not args.no_forms:
+        forms["other_workloads"] = {
+            "c1_uniform20": bench_plain(isp, torch, W.c1_uniform20()),
+            "c3_mixed": bench_plain(isp, torch, W.c3_mixed(), reps=5),
+        }
         forms["batched"] = bench_batched(isp, W, torch)
         forms["served"] = bench_served(isp, W, torch)
 

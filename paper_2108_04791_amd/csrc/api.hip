@@ -32,6 +32,9 @@ constexpr int MAX_DEVICES = 64;
 constexpr size_t PLAIN_PIECE = (size_t)1 << 28;
 // Elements per batched call (its survivors share one 32-bit counter).
 constexpr uint64_t BATCH_MAX_ELEMS = (uint64_t)1 << 30;
+// A plain call over len elements uses at most ceil(len / this) Miller-Rabin
+// workgroups.
+constexpr size_t SMALL_CALL_PER_BLOCK = 1024;
 
 std::mutex g_init_mu;
 DeviceState g_dev[MAX_DEVICES];
@@ -157,12 +160,19 @@ void note_counts(int dev, void *stream, const Workspace &ws, unsigned grid_c, un
     g_last[{dev, stream}] = LastCounts{ws.counts, grid_c, grid1};
 }
 
-// Arguments of the three kernels for one call.
-void make_args(const DeviceState &ds, const Workspace &ws, const Tuning &t, ClassifyArgs &ca,
-               MrArgs &ma, unsigned &grid_c, unsigned &grid1)
+// Arguments of the three kernels for one call.  `len` (0: unknown, as for a
+// recorded graph) trims the grids for small inputs, so a short call does not
+// pay for thousands of idle workgroups.
+void make_args(const DeviceState &ds, const Workspace &ws, const Tuning &t, size_t len,
+               ClassifyArgs &ca, MrArgs &ma, unsigned &grid_c, unsigned &grid1)
 {
     grid_c = grid_of(ds.cus, t.classify_blocks_per_cu);
     grid1 = grid_of(ds.cus, t.mr_blocks_per_cu);
+    if (len) {
+        const size_t per_pass = (size_t)t.classify_block * t.classify_ept;
+        grid_c = (unsigned)std::min<size_t>(grid_c, (len + per_pass - 1) / per_pass);
+        grid1 = (unsigned)std::min<size_t>(grid1, (len + SMALL_CALL_PER_BLOCK - 1) / SMALL_CALL_PER_BLOCK);
+    }
     ca = ClassifyArgs();
     ca.table = ds.table;
     ca.nfilter = t.filter_primes;
@@ -197,7 +207,7 @@ int run_plain(const uint64_t *n, uint8_t *out, size_t len, const DeviceState &ds
     ClassifyArgs ca;
     MrArgs ma;
     unsigned grid_c, grid1;
-    make_args(ds, ws, t, ca, ma, grid_c, grid1);
+    make_args(ds, ws, t, len, ca, ma, grid_c, grid1);
     ca.n = n;
     ca.out = out;
     ca.total = len;
@@ -215,7 +225,7 @@ int run_plain(const uint64_t *n, uint8_t *out, size_t len, const DeviceState &ds
         e = launch_mr1(ma, t.mr_block, s);
     mark(2);
     if (e == hipSuccess)
-        e = launch_mr2(ma, ds.cus, t.mr_blocks_per_cu, t.mr_block, t.mr_window, s);
+        e = launch_mr2(ma, ds.cus, t.mr_blocks_per_cu, grid1, t.mr_block, t.mr_window, s);
     mark(3);
     if (prof && e == hipSuccess) {
         e = hipEventSynchronize(g_prof_ev[ISP_NUM_STAGES]);
@@ -302,7 +312,7 @@ int build_graph(BatchCtx &c, const DeviceState &ds, const Tuning &t)
     ClassifyArgs ca;
     MrArgs ma;
     unsigned grid_c, grid1;
-    make_args(ds, c.ws, t, ca, ma, grid_c, grid1);
+    make_args(ds, c.ws, t, 0, ca, ma, grid_c, grid1);
     const BatchDesc *d = reinterpret_cast<const BatchDesc *>(c.d_desc);
     ca.desc = d;
     ma.total_dev = &d->total;
@@ -316,7 +326,8 @@ int build_graph(BatchCtx &c, const DeviceState &ds, const Tuning &t)
     if (ee == hipSuccess)
         ee = launch_mr1(ma, t.mr_block, c.cap_stream);
     if (ee == hipSuccess)
-        ee = launch_mr2(ma, ds.cus, t.mr_blocks_per_cu, t.mr_block, t.mr_window, c.cap_stream);
+        ee = launch_mr2(ma, ds.cus, t.mr_blocks_per_cu, MAX_GRID, t.mr_block, t.mr_window,
+                        c.cap_stream);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(c.cap_stream, &g);
     if (ee != hipSuccess) {
@@ -455,8 +466,13 @@ int isprime_u64(const uint64_t *n, uint8_t *out, size_t len, void *stream)
     for (size_t off = 0; off < len && st == ISP_OK; off += PLAIN_PIECE)
         st = run_plain(n + off, out + off, std::min(PLAIN_PIECE, len - off), g_dev[dev], sw->ws,
                        t, s);
-    note_counts(dev, stream, sw->ws, grid_of(g_dev[dev].cus, t.classify_blocks_per_cu),
-                grid_of(g_dev[dev].cus, t.mr_blocks_per_cu));
+    {
+        ClassifyArgs ca;
+        MrArgs ma;
+        unsigned gc, g1;
+        make_args(g_dev[dev], sw->ws, t, std::min(len, PLAIN_PIECE), ca, ma, gc, g1);
+        note_counts(dev, stream, sw->ws, gc, g1);
+    }
     return st;
 }
 

@@ -109,8 +109,8 @@ hipError_t launch_sieve(DeviceState &ds, hipStream_t s);
 hipError_t launch_classify(const ClassifyArgs &a, unsigned grid, int block, int ept,
                            hipStream_t s);
 hipError_t launch_mr1(const MrArgs &a, int block, hipStream_t s);
-hipError_t launch_mr2(const MrArgs &a, int cus, int per_cu, int block, int window,
-                      hipStream_t s);
+hipError_t launch_mr2(const MrArgs &a, int cus, int per_cu, unsigned max_grid, int block,
+                      int window, hipStream_t s);
 
 hipError_t launch_montmul_test(const uint64_t *a, const uint64_t *b, const uint64_t *n,
                                uint64_t *out, uint64_t len, hipStream_t s);

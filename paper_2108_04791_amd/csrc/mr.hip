@@ -15,13 +15,15 @@
 // ModAdd of section 2.2) selected without a branch.  About 4 in 5 survivors
 // of random inputs fail here.  Passers go to the workgroup's own region.
 //
-// Phase 2 (base-2 passers, almost all prime): the six remaining bases, one
-// base per lane: a wavefront takes 10 candidates on 60 lanes (lanes 6c ..
-// 6c+5 hold the six bases of candidate c) and a ballot ANDs the six
-// verdicts.  a^d uses a fixed window of W bits with a per-lane table of
-// a^0..a^(2^W - 1) selected by a tree of selects (no dynamic register
-// indexing), so all lanes multiply at the same steps; then up to s - 1
-// squarings look for -1.  A prime stores out = 1 (classify wrote 0).
+// Phase 1 stores out = 1 for every base-2 passer.
+//
+// Phase 2 (base-2 passers, almost all prime): the six remaining bases as
+// six independent tasks per candidate, laid out densely over the lanes
+// (task 6j + b is base b of candidate j); a lane whose base fails stores
+// out = 0, so the verdict is the AND of the six without any cross-lane
+// step (several lanes may store the same 0).  a^d uses a fixed window of W
+// bits with the lane's table of a^0..a^(2^W - 1) in LDS, so all lanes
+// multiply at the same steps; then up to s - 1 squarings look for -1.
 //
 // Work split without global atomics (a single hot device-scope atomic
 // sustains only about 1e8 operations per second on this part): each
@@ -220,8 +222,10 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
             before += w < wave ? c : 0u;
             all += c;
         }
-        if (pass)
+        if (pass) {
             region[filled + before + __popcll(m & lt)] = sv;
+            *sv.out = 1;  // provisional: a failing later base clears it
+        }
         filled += all;
         __syncthreads();  // wave_cnt is rewritten next round
     }
@@ -239,31 +243,21 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase2_kernel(MrArgs a)
     uint32_t *pre = reinterpret_cast<uint32_t *>(dyn + (1u << W) * blockDim.x);
     __shared__ uint32_t wsum[MR_MAX_BLOCK / 64];
     constexpr uint32_t BASES[6] = {325u, 9375u, 28178u, 450775u, 9780504u, 1795265022u};
-    constexpr int PER_WAVE = 10;  // candidates per wavefront, 6 lanes each
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const uint64_t total = call_total(a);
     const uint64_t chunk_1 = cand_chunk(total, a.grid1);
     lds_prefix(a.counts1, a.grid1, pre, wsum);
-    const uint32_t n2 = pre[a.grid1];
-    const uint32_t g = blockIdx.x;
-    const uint32_t s0 = (uint32_t)((uint64_t)n2 * g / gridDim.x);
-    const uint32_t s1 = (uint32_t)((uint64_t)n2 * (g + 1) / gridDim.x);
-    const uint32_t per_round = PER_WAVE * nwaves;
-    const int c_in_wave = lane / 6, b = lane - 6 * (lane / 6);
-    for (uint32_t r0 = s0; r0 < s1; r0 += per_round) {
-        const uint32_t j = r0 + wave * PER_WAVE + c_in_wave;
-        const bool active = lane < 6 * PER_WAVE && j < s1;
-        bool ok = false;
-        uint8_t *out = nullptr;
-        if (active) {
-            const uint32_t k = find_region(pre, a.grid1, j);
-            const Survivor sv = a.cand[(uint64_t)k * chunk_1 + (j - pre[k])];
-            out = sv.out;
-            ok = sprp_one_base<W>(sv.n, BASES[b], tbl);
-        }
-        const uint64_t m = __ballot(ok);
-        if (active && b == 0 && ((m >> lane) & 0x3full) == 0x3full)
-            *out = 1;
+    // one task per (candidate, base): 6 per candidate, dense over all lanes
+    const uint64_t tasks = 6ull * pre[a.grid1];
+    const uint64_t g = blockIdx.x;
+    const uint64_t s0 = tasks * g / gridDim.x;
+    const uint64_t s1 = tasks * (g + 1) / gridDim.x;
+    for (uint64_t t = s0 + threadIdx.x; t < s1; t += blockDim.x) {
+        const uint32_t j = (uint32_t)(t / 6);
+        const uint32_t b = (uint32_t)(t - 6ull * j);
+        const uint32_t k = find_region(pre, a.grid1, j);
+        const Survivor sv = a.cand[(uint64_t)k * chunk_1 + (j - pre[k])];
+        if (!sprp_one_base<W>(sv.n, BASES[b], tbl))
+            *sv.out = 0;  // composite; the base-2 round had written 1
     }
 }
 
@@ -332,12 +326,13 @@ int mr2_resident_per_cu(int block, int window, size_t lds)
     return nb;
 }
 
-hipError_t launch_mr2(const MrArgs &a, int cus, int per_cu, int block, int window,
-                      hipStream_t s)
+hipError_t launch_mr2(const MrArgs &a, int cus, int per_cu, unsigned max_grid, int block,
+                      int window, hipStream_t s)
 {
     const size_t lds = mr2_lds(a, block, window);
     const int fit = mr2_resident_per_cu(block, window, lds);
-    const unsigned grid = (unsigned)std::max(1, std::min(MAX_GRID, cus * std::min(per_cu, fit)));
+    const unsigned grid = std::max(
+        1u, std::min({(unsigned)MAX_GRID, max_grid, (unsigned)(cus * std::min(per_cu, fit))}));
     switch (window) {
     case 1:
         mr_phase2_kernel<1><<<grid, block, lds, s>>>(a);
