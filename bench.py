@@ -43,6 +43,34 @@ OPS_PER_DOUBLING = 6
 MR_BASES_AFTER_2 = 6
 
 
+def kernel_source_hash() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(ROOT, "paper_2108_04791_amd", "csrc", "*"))):
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes scaled by the copy calibration), or
+    None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "pmc_c2_mr64.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and (line.startswith("source_sha256_16") or line.startswith("traffic_")):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256_16") != kernel_source_hash():
+        return None
+    v = vals.get("traffic_bytes_per_launch." + kernel)
+    return int(v) if v else None
+
+
 def small_odd_primes(count: int) -> list:
     out, p = [], 3
     while len(out) < count:
@@ -272,8 +300,11 @@ def main() -> int:
     torch.cuda.synchronize()
     sieve_ms = (time.perf_counter() - t0) * 1e3
 
+    from paper_2108_04791_amd import tune
+    defaults = isp.get_config()
     a = W.c2_mr64()
     n = a.size
+    tuned = tune.apply("c2_mr64", n) is not None  # autotuned launch parameters, if recorded
     dev = torch.from_numpy(a.view(np.int64)).cuda()
     out = torch.empty(n, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
@@ -309,11 +340,12 @@ def main() -> int:
         bytes_per_launch = n * 9.0
         achieved = bytes_per_launch / (stage_ms[dom] * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom}
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(dom), "kernel": dom}
     else:
         achieved = work[dom]["ops"] / (stage_ms[dom] * 1e-3) / 1e9
         roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GOPS,
-                    "unit": "Gop/s", "frac": achieved / VALU_PEAK_GOPS, "traffic": None,
+                    "unit": "Gop/s", "frac": achieved / VALU_PEAK_GOPS,
+                    "traffic": counter_traffic(dom),
                     "kernel": dom, "op": "VALU lane-instruction",
                     "montmul_per_launch": work[dom]["montmul"],
                     "doublings_per_launch": work[dom]["doublings"],
@@ -325,11 +357,21 @@ def main() -> int:
 
     forms = {}
     if not args.no_forms:
+        def with_tuning(key, length, fn):
+            isp.set_config(**defaults)
+            tune.apply(key, length)
+            res = fn()
+            res["tuning"] = isp.get_config()
+            isp.set_config(**defaults)
+            return res
+
+        c1, c3 = W.c1_uniform20(), W.c3_mixed()
         forms["other_workloads"] = {
-            "c1_uniform20": bench_plain(isp, torch, W.c1_uniform20()),
-            "c3_mixed": bench_plain(isp, torch, W.c3_mixed(), reps=5),
+            "c1_uniform20": with_tuning("c1_uniform20", c1.size, lambda: bench_plain(isp, torch, c1)),
+            "c3_mixed": with_tuning("c3_mixed", c3.size, lambda: bench_plain(isp, torch, c3, reps=5)),
         }
-        forms["batched"] = bench_batched(isp, W, torch)
+        del c3
+        forms["batched"] = with_tuning("c4_batched", 25341952, lambda: bench_batched(isp, W, torch))
         forms["served"] = bench_served(isp, W, torch)
 
     cpu = None
@@ -359,7 +401,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "c2_mr64: 2^24 uint64 rejection-uniform in [2^49, 2^64), half "
                                "forced odd, splitmix64 seed 0x2108047900000002",
-                   "len": n, "input_sha256_16": W.digest(a), "tuning": cfg},
+                   "len": n, "input_sha256_16": W.digest(a), "tuning": cfg,
+                   "tuning_source": "autotuner database" if tuned else "library defaults"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "bit_exact_vs_oracle": bit_exact,
