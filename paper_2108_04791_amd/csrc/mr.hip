@@ -42,6 +42,16 @@ namespace isp {
 
 namespace {
 
+// (x << 1) + a modulo 2^64 as the single gfx950 instruction v_lshl_add_u64
+// (the compiler otherwise turns x*2 + (2^64 - n) into a select of n and a
+// two-instruction 64-bit subtract).  Pure VALU arithmetic, no memory access.
+__device__ __forceinline__ uint64_t shl1_add(uint64_t x, uint64_t a)
+{
+    uint64_t r;
+    asm("v_lshl_add_u64 %0, %1, 1, %2" : "=v"(r) : "v"(x), "v"(a));
+    return r;
+}
+
 // Strong probable-prime test to base 2 for odd n >= 2^32, n - 1 = 2^s d.
 //
 // x runs over 2^(floor((n-1) / 2^t)) (Montgomery form) for t = L-1 down to
@@ -57,13 +67,17 @@ __device__ __forceinline__ bool sprp_base2(uint64_t n)
     const MontCtx c = make_ctx(n, L);
     uint64_t rest = (n - 1) << (65 - L);  // bits L-2 .. 0 of n - 1, at the top
     uint64_t x = dbl_mod(c.one, n);        // bit L-1 (the leading one): x = 2
+    // 2x mod n for x < n: 2x >= n exactly when x >= (n + 1) / 2 (n is odd),
+    // and then 2x - n = 2x + (2^64 - n) modulo 2^64, carry or not.
+    const uint64_t half = (n >> 1) + 1, neg_n = 0 - n;
     while (rest != 0) {
         const bool bit = (int64_t)rest < 0;
         rest <<= 1;
         x = montsqr(x, n, c.ninv);
-        const uint64_t y = x + x;
-        const bool wrap = (int64_t)x < 0 || y >= n;  // 2x >= n, with the carry of x + x
-        x = bit ? (wrap ? y - n : y) : x;
+        const uint64_t y = x << 1;
+        const uint64_t z = shl1_add(x, neg_n);  // both computed: selects, no branch
+        const bool wrap = x >= half;
+        x = bit ? (wrap ? z : y) : x;
     }
     bool pass = x == c.one || x == c.mone;
     const int s = __ffsll((long long)(n - 1)) - 1;
