@@ -334,6 +334,24 @@ def main() -> int:
     calls = max(1, prof["calls"])
     stage_ms = {k: prof[k] / calls for k in isp.STAGES}
 
+    # the Baillie-PSW alternative on the same input (base 2, then a strong
+    # Lucas test instead of the six remaining bases): same bytes, timed alike
+    alt = {}
+    isp.set_config(rest_test=1)
+    isp.profile(True)
+    for _ in range(args.steps):
+        isp.isprime_into(dev, out, stream)
+    p2 = isp.profile_read()
+    isp.profile(False)
+    isp.set_config(rest_test=-1)
+    c2 = max(1, p2["calls"])
+    alt_ms = {k: p2[k] / c2 for k in isp.STAGES}
+    alt["bpsw"] = {"stage_ms": alt_ms, "ms_per_step_events": sum(alt_ms.values()),
+                   "tests_per_s": n / (sum(alt_ms.values()) * 1e-3),
+                   "same_bytes": bool(np.array_equal(out.cpu().numpy(), got))}
+    isp.isprime_into(dev, out, stream)
+    torch.cuda.synchronize()
+
     work, n_surv, n_prime = mr_work(a, got, max(0, cfg["filter_primes"]))
     dom = max(("mr_base2", "mr_rest", "classify"), key=lambda k: stage_ms[k])
     if dom == "classify":
@@ -408,6 +426,7 @@ def main() -> int:
         "bit_exact_vs_oracle": bit_exact,
         "stage_ms": stage_ms,
         "alu_frac_by_kernel": other,
+        "alternatives": alt,
         "survivors": n_surv,
         "primes": int(got.sum()),
         "sieve_build_ms": sieve_ms,

@@ -98,8 +98,8 @@ int isp_last_device_error(void);
 const char *isp_strerror(int status);
 
 /* Launch and algorithm parameters.  None of them changes any output bit;
- * the autotuner picks them per workload class.  A zero field means
- * "library default". */
+ * the autotuner picks the launch shapes per workload class.  A zero field
+ * means "library default". */
 typedef struct {
     int32_t classify_block;         /* threads per classify block: 64..1024, multiple of 64 */
     int32_t classify_ept;           /* elements per classify thread and pass: 1, 2, 4 or 8 */
@@ -109,6 +109,10 @@ typedef struct {
     int32_t mr_block;               /* threads per Miller-Rabin block: 64..256, multiple of 64 */
     int32_t mr_blocks_per_cu;       /* Miller-Rabin grids = CUs x this (at most 4096): 1..16 */
     int32_t mr_window;              /* fixed window width for bases other than 2: 1..4 */
+    int32_t rest_test;              /* after base 2: -1 the six remaining Miller-Rabin bases of
+                                       the paper (default); 1 the strong Lucas test with
+                                       Selfridge's parameters (Baillie-PSW, the paper's future
+                                       work, section 10.1) -- the same verdicts below 2^64 */
 } isp_config;
 
 /* Read / replace the process-wide configuration (ISP_EINVAL if out of range). */

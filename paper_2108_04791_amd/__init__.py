@@ -55,6 +55,7 @@ class Config(ctypes.Structure):
         ("mr_block", ctypes.c_int32),
         ("mr_blocks_per_cu", ctypes.c_int32),
         ("mr_window", ctypes.c_int32),
+        ("rest_test", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:

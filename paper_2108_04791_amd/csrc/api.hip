@@ -43,7 +43,7 @@ std::atomic<int> g_last_err{0};
 std::mutex g_cfg_mu;
 // The autotuner's choice for 2^24 64-bit values; other classes are in the
 // tuning database that paper_2108_04791_amd/tune.py writes.
-constexpr isp_config DEFAULT_CONFIG = {512, 8, 4, 24, 1, 256, 12, 3};
+constexpr isp_config DEFAULT_CONFIG = {512, 8, 4, 24, 1, 256, 12, 3, -1};
 isp_config g_cfg = DEFAULT_CONFIG;
 
 int fail(hipError_t e)
@@ -64,7 +64,7 @@ bool valid_config(const isp_config &c)
             c.filter_primes == 64) &&
            (c.sort_survivors == -1 || c.sort_survivors == 1) && blk(c.mr_block, MR_MAX_BLOCK) &&
            c.mr_blocks_per_cu >= 1 && c.mr_blocks_per_cu <= 16 && c.mr_window >= 1 &&
-           c.mr_window <= 4;
+           c.mr_window <= 4 && (c.rest_test == -1 || c.rest_test == 1);
 }
 
 Tuning tuning_snapshot()
@@ -79,6 +79,7 @@ Tuning tuning_snapshot()
     t.mr_block = g_cfg.mr_block;
     t.mr_blocks_per_cu = g_cfg.mr_blocks_per_cu;
     t.mr_window = g_cfg.mr_window;
+    t.rest_test = g_cfg.rest_test > 0;
     return t;
 }
 
@@ -227,7 +228,9 @@ int run_plain(const uint64_t *n, uint8_t *out, size_t len, const DeviceState &ds
         e = launch_mr1(ma, t.mr_block, s);
     mark(2);
     if (e == hipSuccess)
-        e = launch_mr2(ma, ds.cus, t.mr_blocks_per_cu, grid1, t.mr_block, t.mr_window, s);
+        e = t.rest_test ? launch_lucas(ma, ds.cus, t.mr_blocks_per_cu, grid1, t.mr_block, s)
+                        : launch_mr2(ma, ds.cus, t.mr_blocks_per_cu, grid1, t.mr_block,
+                                     t.mr_window, s);
     mark(3);
     if (prof && e == hipSuccess) {
         e = hipEventSynchronize(g_prof_ev[ISP_NUM_STAGES]);
@@ -328,8 +331,10 @@ int build_graph(BatchCtx &c, const DeviceState &ds, const Tuning &t)
     if (ee == hipSuccess)
         ee = launch_mr1(ma, t.mr_block, c.cap_stream);
     if (ee == hipSuccess)
-        ee = launch_mr2(ma, ds.cus, t.mr_blocks_per_cu, MAX_GRID, t.mr_block, t.mr_window,
-                        c.cap_stream);
+        ee = t.rest_test ? launch_lucas(ma, ds.cus, t.mr_blocks_per_cu, MAX_GRID, t.mr_block,
+                                        c.cap_stream)
+                         : launch_mr2(ma, ds.cus, t.mr_blocks_per_cu, MAX_GRID, t.mr_block,
+                                      t.mr_window, c.cap_stream);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(c.cap_stream, &g);
     if (ee != hipSuccess) {
@@ -659,6 +664,7 @@ int isp_set_config(const isp_config *cfg)
     if (!c.mr_block) c.mr_block = d.mr_block;
     if (!c.mr_blocks_per_cu) c.mr_blocks_per_cu = d.mr_blocks_per_cu;
     if (!c.mr_window) c.mr_window = d.mr_window;
+    if (!c.rest_test) c.rest_test = -1;
     if (!valid_config(c))
         return ISP_EINVAL;
     std::lock_guard<std::mutex> g(g_cfg_mu);

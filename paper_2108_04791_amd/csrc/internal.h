@@ -83,6 +83,7 @@ struct Tuning {
     int mr_block;
     int mr_blocks_per_cu;
     int mr_window;
+    int rest_test;  // 0: the six remaining Miller-Rabin bases; 1: strong Lucas (Baillie-PSW)
 };
 
 struct DeviceState {
@@ -111,6 +112,8 @@ hipError_t launch_classify(const ClassifyArgs &a, unsigned grid, int block, int 
 hipError_t launch_mr1(const MrArgs &a, int block, hipStream_t s);
 hipError_t launch_mr2(const MrArgs &a, int cus, int per_cu, unsigned max_grid, int block,
                       int window, hipStream_t s);
+hipError_t launch_lucas(const MrArgs &a, int cus, int per_cu, unsigned max_grid, int block,
+                        hipStream_t s);
 
 hipError_t launch_montmul_test(const uint64_t *a, const uint64_t *b, const uint64_t *n,
                                uint64_t *out, uint64_t len, hipStream_t s);

@@ -137,6 +137,129 @@ __device__ __forceinline__ bool sprp_one_base(uint64_t n, uint32_t a, uint64_t *
     return sprp_window<W>(to_mont(a, r2, c), e >> s, s, c, tbl);
 }
 
+// ------------------------------------------------------------------ Lucas
+// Strong Lucas probable-prime test with Selfridge's parameters (Baillie and
+// Wagstaff, Math. Comp. 35, 1980): D is the first of 5, -7, 9, -11, ... with
+// Jacobi symbol (D/n) = -1, P = 1, Q = (1 - D) / 4.  With n + 1 = 2^s d, n
+// is a strong Lucas probable prime iff U_d = 0 or V_(d 2^r) = 0 (mod n) for
+// some 0 <= r < s.  Together with the base-2 strong test this is the
+// Baillie-PSW test, the alternative the paper names as future work (section
+// 10.1); it selects the same primes below 2^64.
+
+// Jacobi symbol (a/m) for odd m > 0, by quadratic reciprocity.
+__device__ __forceinline__ int jacobi32(uint32_t a, uint32_t m, int t)
+{
+    while (a != 0) {
+        while ((a & 1) == 0) {
+            a >>= 1;
+            const uint32_t r = m & 7;
+            if (r == 3 || r == 5)
+                t = -t;
+        }
+        const uint32_t x = a;
+        a = m;
+        m = x;
+        if ((a & 3) == 3 && (m & 3) == 3)
+            t = -t;
+        a %= m;
+    }
+    return m == 1 ? t : 0;
+}
+
+// (D/n) for odd n > |D|, |D| odd and < 2^31.
+__device__ __forceinline__ int jacobi_d_n(int32_t D, uint64_t n)
+{
+    int t = 1;
+    const uint32_t a = (uint32_t)(D < 0 ? -D : D);
+    if (D < 0 && (n & 3) == 3)
+        t = -t;  // (-1/n)
+    if ((a & 3) == 3 && (n & 3) == 3)
+        t = -t;  // reciprocity, both odd
+    return jacobi32((uint32_t)(n % a), a, t);
+}
+
+__device__ __forceinline__ uint32_t gcd32(uint32_t a, uint32_t b)
+{
+    while (b) {
+        const uint32_t r = a % b;
+        a = b;
+        b = r;
+    }
+    return a;
+}
+
+__device__ __forceinline__ uint64_t sub_mod(uint64_t a, uint64_t b, uint64_t n)
+{
+    return a >= b ? a - b : a - b + n;
+}
+
+// 1: strong Lucas probable prime; 0: composite; -1: no D found (the caller
+// falls back to the remaining Miller-Rabin bases).
+__device__ __forceinline__ int strong_lucas(uint64_t n)
+{
+    if (n == ~(uint64_t)0)
+        return 0;  // 3 divides 2^64 - 1 (and n + 1 would wrap)
+    // a perfect square has no D with (D/n) = -1
+    uint64_t r = (uint64_t)sqrt((double)n);
+    if (r > 0xffffffffull)
+        r = 0xffffffffull;
+    while (r * r > n)
+        --r;
+    while (r < 0xffffffffull && (r + 1) * (r + 1) <= n)
+        ++r;
+    if (r * r == n)
+        return 0;
+    int32_t D = 5;
+    int k = 0;
+    for (;; ++k) {
+        if (k >= 4096)
+            return -1;
+        const int j = jacobi_d_n(D, n);
+        if (j == -1)
+            break;
+        if (j == 0)
+            return 0;  // gcd(|D|, n) > 1 and |D| < n
+        D = D > 0 ? -(D + 2) : -D + 2;
+    }
+    const int32_t Q = (1 - D) / 4;
+    const uint32_t aq = (uint32_t)(Q < 0 ? -Q : Q);
+    if (aq > 1 && gcd32((uint32_t)(n % aq), aq) > 1)
+        return 0;
+    const int L = 64 - __clzll(n);
+    const MontCtx c = make_ctx(n, L);
+    const uint64_t r2 = r2_mod_n(c);
+    const uint64_t qm = to_mont(Q < 0 ? n - aq : (uint64_t)aq, r2, c);
+    const uint64_t e = n + 1;
+    const int s = __ffsll((long long)e) - 1;
+    const uint64_t d = e >> s;
+    const int Ld = 64 - __clzll(d);
+    // ladder over the bits of d: (V_k, V_(k+1), Q^k) -> k' = 2k + bit
+    uint64_t vk = dbl_mod(c.one, n);  // V_0 = 2
+    uint64_t vk1 = c.one;             // V_1 = P = 1
+    uint64_t qk = c.one;              // Q^0
+    for (int i = Ld - 1; i >= 0; --i) {
+        const bool bit = (d >> i) & 1;
+        const uint64_t w = sub_mod(montmul(vk, vk1, n, c.ninv), qk, n);  // V_(2k+1)
+        const uint64_t qkq = montmul(qk, qm, n, c.ninv);                // Q^(k+1)
+        const uint64_t a = bit ? vk1 : vk;
+        const uint64_t qb = bit ? qkq : qk;                              // Q^(k+bit)
+        const uint64_t sq = sub_mod(montsqr(a, n, c.ninv), dbl_mod(qb, n), n);  // V_(2k+2bit)
+        qk = montmul(qb, qk, n, c.ninv);                                 // Q^(2k+bit)
+        vk = bit ? w : sq;
+        vk1 = bit ? sq : w;
+    }
+    // U_d = (2 V_(d+1) - P V_d) / D, and D is invertible mod n
+    if (dbl_mod(vk1, n) == vk || vk == 0)
+        return 1;
+    for (int rr = 1; rr < s; ++rr) {
+        vk = sub_mod(montsqr(vk, n, c.ninv), dbl_mod(qk, n), n);  // V_(2m) = V_m^2 - 2 Q^m
+        if (vk == 0)
+            return 1;
+        qk = montsqr(qk, n, c.ninv);
+    }
+    return 0;
+}
+
 // Exclusive prefix of counts[0..nc) into pre[0..nc] (pre[nc] = total), in
 // LDS.  nc <= MAX_GRID; blockDim is a multiple of 64, at most 256.
 __device__ __forceinline__ void lds_prefix(const uint32_t *__restrict__ counts, uint32_t nc,
@@ -275,6 +398,37 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase2_kernel(MrArgs a)
     }
 }
 
+// Remaining test of every base-2 passer by the strong Lucas test (one task
+// per candidate; see strong_lucas).  A composite stores out = 0.
+template <int W>
+__global__ void __launch_bounds__(MR_MAX_BLOCK) lucas_kernel(MrArgs a)
+{
+    extern __shared__ uint64_t dyn[];
+    uint64_t *tbl = dyn;  // used only by the rare fallback to the Miller-Rabin bases
+    uint32_t *pre = reinterpret_cast<uint32_t *>(dyn + (1u << W) * blockDim.x);
+    __shared__ uint32_t wsum[MR_MAX_BLOCK / 64];
+    constexpr uint32_t BASES[6] = {325u, 9375u, 28178u, 450775u, 9780504u, 1795265022u};
+    const uint64_t total = call_total(a);
+    const uint64_t chunk_1 = cand_chunk(total, a.grid1);
+    lds_prefix(a.counts1, a.grid1, pre, wsum);
+    const uint64_t n2 = pre[a.grid1];
+    const uint64_t g = blockIdx.x;
+    const uint64_t s0 = n2 * g / gridDim.x;
+    const uint64_t s1 = n2 * (g + 1) / gridDim.x;
+    for (uint64_t j = s0 + threadIdx.x; j < s1; j += blockDim.x) {
+        const uint32_t k = find_region(pre, a.grid1, (uint32_t)j);
+        const Survivor sv = a.cand[(uint64_t)k * chunk_1 + ((uint32_t)j - pre[k])];
+        int v = strong_lucas(sv.n);
+        if (v < 0) {
+            v = 1;
+            for (int b = 0; b < 6 && v; ++b)
+                v = sprp_one_base<W>(sv.n, BASES[b], tbl);
+        }
+        if (!v)
+            *sv.out = 0;
+    }
+}
+
 __global__ void montmul_test_kernel(const uint64_t *__restrict__ a, const uint64_t *__restrict__ b,
                                     const uint64_t *__restrict__ n, uint64_t *__restrict__ out,
                                     uint64_t len)
@@ -338,6 +492,22 @@ int mr2_resident_per_cu(int block, int window, size_t lds)
         nb = 1;
     cache[key] = nb;
     return nb;
+}
+
+hipError_t launch_lucas(const MrArgs &a, int cus, int per_cu, unsigned max_grid, int block,
+                        hipStream_t s)
+{
+    constexpr int W = 3;
+    const size_t lds = mr2_lds(a, block, W);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lucas_kernel<W>, block, lds) !=
+            hipSuccess ||
+        nb < 1)
+        nb = 1;
+    const unsigned grid = std::max(
+        1u, std::min({(unsigned)MAX_GRID, max_grid, (unsigned)(cus * std::min(per_cu, nb))}));
+    lucas_kernel<W><<<grid, block, lds, s>>>(a);
+    return hipGetLastError();
 }
 
 hipError_t launch_mr2(const MrArgs &a, int cus, int per_cu, unsigned max_grid, int block,
