@@ -84,6 +84,7 @@ SIGNATURES = {
     "isp_shutdown": (None, []),
     "isprime_u64": (_I, [_P, _P, _SZ, _P]),
     "isprime_u64_batched": (_I, [_P, _P, _P, _SZ, _P]),
+    "isprime_range_u64": (_I, [_U64, _P, _SZ, _P]),
     "isp_workspace_bytes": (_SZ, [_SZ]),
     "isp_last_device_error": (_I, []),
     "isp_strerror": (ctypes.c_char_p, [_I]),
@@ -208,6 +209,20 @@ def isprime_batched(arrays, outs=None, stream=None):
                                          ctypes.cast(lens, _P), k, _stream_handle(stream)),
                "isprime_u64_batched")
     return outs
+
+
+def isprime_range(lo: int, length: int, out: torch.Tensor | None = None, stream=None,
+                  device=None) -> torch.Tensor:
+    """Boolean tensor: element i is True iff lo + i is prime (a contiguous
+    interval; no input array)."""
+    if out is None:
+        out = torch.empty(length, dtype=torch.bool, device=device or "cuda")
+    if out.numel() != length or not out.is_contiguous() or out.dtype not in (torch.bool, torch.uint8):
+        raise ValueError("out must be a contiguous bool/uint8 tensor of `length` elements")
+    with torch.cuda.device(out.device):
+        _check(lib().isprime_range_u64(lo, out.data_ptr() if length else None, length,
+                                       _stream_handle(stream)), "isprime_range_u64")
+    return out
 
 
 def montmul(a: torch.Tensor, b: torch.Tensor, n: torch.Tensor, stream=None) -> torch.Tensor:

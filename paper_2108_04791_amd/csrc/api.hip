@@ -449,6 +449,12 @@ void isp_shutdown(void)
         (void)hipFree(ds.table);
         (void)hipFree(ds.base_primes);
         (void)hipFree(ds.base_count);
+        if (ds.range_primes)
+            (void)hipFree(ds.range_primes);
+        if (ds.range_inv)
+            (void)hipFree(ds.range_inv);
+        if (ds.range_count)
+            (void)hipFree(ds.range_count);
         ds = DeviceState();
     }
 }
@@ -479,6 +485,95 @@ int isprime_u64(const uint64_t *n, uint8_t *out, size_t len, void *stream)
         unsigned gc, g1;
         make_args(g_dev[dev], sw->ws, t, std::min(len, PLAIN_PIECE), ca, ma, gc, g1);
         note_counts(dev, stream, sw->ws, gc, g1);
+    }
+    return st;
+}
+
+// Builds the interval sieve's prime list for `dev` on first use.
+static int ensure_range_primes(int dev)
+{
+    std::lock_guard<std::mutex> g(g_init_mu);
+    DeviceState &ds = g_dev[dev];
+    if (ds.num_range_primes)
+        return ISP_OK;
+    hipStream_t s = nullptr;
+    hipError_t e = hipMalloc(&ds.range_primes, RANGE_MAX_PRIMES * sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMalloc(&ds.range_inv, RANGE_MAX_PRIMES * sizeof(uint64_t));
+    if (e == hipSuccess)
+        e = hipMalloc(&ds.range_count, sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = launch_range_primes(ds, s);
+    uint32_t count = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&count, ds.range_count, sizeof(count), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (s)
+        (void)hipStreamDestroy(s);
+    if (e == hipSuccess && count != RANGE_MAX_PRIMES - 1)
+        e = hipErrorUnknown;  // 82024 odd primes below 2^20
+    if (e != hipSuccess) {
+        (void)hipFree(ds.range_primes);
+        (void)hipFree(ds.range_inv);
+        (void)hipFree(ds.range_count);
+        ds.range_primes = nullptr;
+        ds.range_inv = nullptr;
+        ds.range_count = nullptr;
+        return fail(e);
+    }
+    ds.num_range_primes = (int)count;
+    return ISP_OK;
+}
+
+int isprime_range_u64(uint64_t lo, uint8_t *out, size_t len, void *stream)
+{
+    if (len == 0)
+        return ISP_OK;
+    if (!out || lo + (uint64_t)(len - 1) < lo)
+        return ISP_EINVAL;  // NULL, or the interval passes 2^64 - 1
+    int dev = 0;
+    int st = current_device(&dev);
+    if (st != ISP_OK)
+        return st;
+    st = ensure_range_primes(dev);
+    if (st != ISP_OK)
+        return st;
+    const DeviceState &ds = g_dev[dev];
+    const Tuning t = tuning_snapshot();
+    hipStream_t s = (hipStream_t)stream;
+    // below 2^32: the table
+    const uint64_t below = lo < TABLE_BOUND ? std::min<uint64_t>(len, TABLE_BOUND - lo) : 0;
+    if (below) {
+        hipError_t e = launch_range_table(lo, out, below, ds, s);
+        if (e != hipSuccess)
+            return fail(e);
+    }
+    if (below == len)
+        return ISP_OK;
+    StreamWs *sw = stream_ws(dev, stream);
+    std::lock_guard<std::mutex> g(sw->mu);
+    st = ensure_ws(sw->ws, std::min<uint64_t>(len - below, RANGE_PIECE), s);
+    for (uint64_t off = below; off < len && st == ISP_OK; off += RANGE_PIECE) {
+        const uint64_t piece = std::min<uint64_t>(RANGE_PIECE, len - off);
+        const unsigned grid = (unsigned)((piece + RANGE_SEG - 1) / RANGE_SEG);
+        ClassifyArgs ca;
+        MrArgs ma;
+        unsigned grid_c, grid1;
+        make_args(ds, sw->ws, t, piece, ca, ma, grid_c, grid1);
+        ma.total = piece;
+        ma.grid_c = grid;
+        hipError_t e = launch_range_sieve(lo + off, out + off, piece, grid, ds, sw->ws, s);
+        if (e == hipSuccess)
+            e = launch_mr1(ma, t.mr_block, s);
+        if (e == hipSuccess)
+            e = t.rest_test ? launch_lucas(ma, ds.cus, t.mr_blocks_per_cu, grid1, t.mr_block, s)
+                            : launch_mr2(ma, ds.cus, t.mr_blocks_per_cu, grid1, t.mr_block,
+                                         t.mr_window, s);
+        if (e != hipSuccess)
+            st = fail(e);
     }
     return st;
 }

@@ -27,6 +27,12 @@ struct Survivor {
 // counts are scanned in LDS by the consumer.
 constexpr int MAX_GRID = 4096;
 
+// Numbers per workgroup segment of the interval sieve (LDS holds the odd
+// ones: 2^18 bits), and numbers per piece of an interval call.
+constexpr uint64_t RANGE_SEG = (uint64_t)1 << 19;
+constexpr uint64_t RANGE_PIECE = (uint64_t)1 << 30;
+constexpr int RANGE_MAX_PRIMES = 82025;  // odd primes below 2^20: 82024
+
 // Device-resident descriptor of a batched call.  The arrays follow the
 // header in the same allocation; the pointers address them.
 struct BatchDesc {
@@ -93,6 +99,12 @@ struct DeviceState {
     uint32_t *base_primes = nullptr; // odd primes < 2^16
     uint32_t *base_count = nullptr;  // device word: how many
     int num_base_primes = 0;
+    // interval sieve: odd primes below 2^20 and floor((2^64-1)/p), built on
+    // first use of isprime_range_u64
+    uint32_t *range_primes = nullptr;
+    uint64_t *range_inv = nullptr;
+    uint32_t *range_count = nullptr;
+    int num_range_primes = 0;
 };
 
 // Per-call workspace (one per stream, or per batched context).
@@ -114,6 +126,12 @@ hipError_t launch_mr2(const MrArgs &a, int cus, int per_cu, unsigned max_grid, i
                       int window, hipStream_t s);
 hipError_t launch_lucas(const MrArgs &a, int cus, int per_cu, unsigned max_grid, int block,
                         hipStream_t s);
+
+hipError_t launch_range_primes(DeviceState &ds, hipStream_t s);
+hipError_t launch_range_table(uint64_t lo, uint8_t *out, uint64_t len, const DeviceState &ds,
+                              hipStream_t s);
+hipError_t launch_range_sieve(uint64_t lo, uint8_t *out, uint64_t len, unsigned grid,
+                              const DeviceState &ds, const Workspace &ws, hipStream_t s);
 
 hipError_t launch_montmul_test(const uint64_t *a, const uint64_t *b, const uint64_t *n,
                                uint64_t *out, uint64_t len, hipStream_t s);

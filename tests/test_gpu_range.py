@@ -1,0 +1,150 @@
+"""GPU parity of the interval entry point isprime_range_u64: out[i] is the
+primality of lo + i.  Checked against the oracle element by element on
+intervals that cross the table bound (2^32), the bound where the segment
+sieve stops being complete on its own (2^40), several segments with ragged
+tails, the top of the 64-bit range, and a call larger than one piece
+(sampled).  Tolerance: zero mismatching bytes."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+U64 = (1 << 64) - 1
+NTHREADS = min(16, os.cpu_count() or 1)
+SEG = 1 << 19      # numbers per workgroup segment
+PIECE = 1 << 30    # numbers per piece of one call
+
+
+@pytest.fixture(scope="module")
+def isp():
+    import paper_2108_04791_amd as isp
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    isp.init()
+    return isp
+
+
+def values(lo: int, length: int) -> np.ndarray:
+    return np.uint64(lo) + np.arange(length, dtype=np.uint64)
+
+
+def gpu_range(isp, lo: int, length: int) -> np.ndarray:
+    out = isp.isprime_range(lo, length)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.uint8)
+
+
+def check(isp, lo: int, length: int):
+    a = values(lo, length)
+    got = gpu_range(isp, lo, length)
+    exp, _ = oracle.isprime_array(a, nthreads=NTHREADS, use_table=None)
+    bad = np.nonzero(got != exp)[0]
+    if bad.size:
+        i = bad[:10]
+        raise AssertionError("[%d, +%d): %d mismatches, first %s gpu %s oracle %s" % (
+            lo, length, bad.size, a[i].tolist(), got[i].tolist(), exp[i].tolist()))
+    return got
+
+
+def test_small_interval_counts(isp):
+    """pi(2^20) = 82025 and pi(10^6) = 78498 (standard values of the prime
+    counting function)."""
+    assert int(gpu_range(isp, 0, 1 << 20).sum()) == 82025
+    assert int(gpu_range(isp, 0, 10 ** 6).sum()) == 78498
+
+
+def test_below_2_20(isp):
+    check(isp, 0, 1 << 20)
+
+
+def test_across_table_bound(isp):
+    check(isp, (1 << 32) - 300001, 600003)
+
+
+def test_across_complete_bound(isp):
+    """Segments ending below 2^40 are decided by the sieve alone; above it the
+    survivors go through Miller-Rabin.  This interval has both kinds."""
+    check(isp, (1 << 40) - 3 * SEG - 17, 6 * SEG + 33)
+
+
+@pytest.mark.parametrize("lo,length", [
+    (10 ** 12 + 7, 3 * SEG + 12345),
+    ((1 << 33) + 1, SEG),
+    ((1 << 33), SEG + 1),
+    ((1 << 36) + 5, 2 * SEG - 1),
+    ((1 << 61) - 1000, 200001),
+    ((1 << 63) - 99999, 199999),
+])
+def test_segments_and_ragged_tails(isp, lo, length):
+    check(isp, lo, length)
+
+
+def test_top_of_range(isp):
+    """The interval ends at 2^64 - 1 exactly."""
+    length = 10 ** 6
+    got = check(isp, U64 - length + 1, length)
+    assert got[-1] == 0 and got[-59] == 1  # 2^64 - 59 is the largest 64-bit prime
+
+
+@pytest.mark.parametrize("length", [1, 2, 3, 63, 64, 65, 1000])
+def test_tiny(isp, length):
+    for lo in (0, 1, 2, (1 << 32) - 2, (1 << 32) - 1, 1 << 32, (1 << 40) - 1, (1 << 61) - 1,
+               U64 - length + 1):
+        check(isp, lo, length)
+
+
+def test_random_intervals(isp):
+    rng = np.random.default_rng(20210810)
+    for _ in range(12):
+        lo = int(rng.integers(1 << 32, 1 << 63)) * 2 + int(rng.integers(0, 2))
+        length = int(rng.integers(1, 200000))
+        lo = min(lo, U64 - length + 1)
+        check(isp, lo, length)
+
+
+def test_equals_array_call(isp):
+    """The interval call and the array call agree over several segments."""
+    lo, length = (1 << 45) + 3, 5 * SEG + 999
+    got = gpu_range(isp, lo, length)
+    arr = torch.from_numpy(values(lo, length).view(np.int64)).cuda()
+    ref = isp.isprime(arr).cpu().numpy().astype(np.uint8)
+    assert np.array_equal(got, ref)
+
+
+def test_empty_and_invalid(isp):
+    assert gpu_range(isp, 123, 0).size == 0
+    with pytest.raises(isp.IsprimeError):
+        isp.isprime_range(U64 - 5, 7)
+    with pytest.raises(isp.IsprimeError):
+        isp.isprime_range(U64, 2)
+    assert gpu_range(isp, U64, 1)[0] == 0
+
+
+def test_larger_than_one_piece_sampled(isp):
+    """A call of more than 2^30 numbers runs in pieces; the outputs around the
+    piece boundary and a random sample are checked one by one, and the whole
+    equals the array call."""
+    lo, length = (1 << 50) + 1, PIECE + 3 * SEG + 7
+    out = isp.isprime_range(lo, length)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([
+        np.arange(PIECE - 50000, PIECE + 50000, dtype=np.int64),
+        np.arange(length - 20000, length, dtype=np.int64),
+        rng.integers(0, length, 200000, dtype=np.int64)]))
+    got = out[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.uint8)
+    a = np.uint64(lo) + idx.astype(np.uint64)
+    exp, _ = oracle.isprime_array(a, nthreads=NTHREADS, use_table=None)
+    assert np.array_equal(got, exp)
+    # whole-interval property: the array call on the same values agrees
+    step = 1 << 28
+    for s in range(0, length, step):
+        n = min(step, length - s)
+        arr = (torch.arange(n, dtype=torch.int64, device="cuda") + (lo + s))
+        ref = isp.isprime(arr)
+        assert torch.equal(ref, out[s:s + n].bool())
+    del out
