@@ -149,6 +149,94 @@ def bench_plain(isp, torch, a: np.ndarray, reps: int = 10) -> dict:
             "primes": int(out.sum().item())}
 
 
+# The paper's MATLAB seconds for its array workloads (Intel Core i7-9750H,
+# MATLAB R2020b): Table IncrementingSequence (section 6.1.3) for 1:N and
+# Table ArrayPerformance (section 8.2) for the rest.  Context from another
+# machine and another program, not a target.
+PAPER_MATLAB_S = {
+    "inc_1e4": 0.000829, "inc_1e5": 0.005502, "inc_1e6": 0.05697, "inc_1e7": 0.6294,
+    "inc_1e8": 6.728, "unix_2021": 12.26, "int16_primes_200": 5.0952e-05,
+    "matrix_1000x1000_u32": 3.927, "normal_primes_1m_mean_2_16": 0.1623,
+    "normal_odd_100k_mean_2_32": 2.689, "normal_1000_mean_2_53": 5.07,
+    "largest52_prime_x1000": 58.270, "composites_100_factors_gt_2e7": 0.4852,
+    "largest64_primes_100": 0.1442, "largest64_odd_5000": 76.201,
+}
+
+
+def _time_ms(torch, stream, fn, reps: int) -> float:
+    """Median of `reps` single calls, each bracketed by HIP events."""
+    fn()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def bench_paper_suite(isp, W, torch, reps: int = 7) -> dict:
+    """The paper's array workloads, rebuilt from their descriptions: the array
+    call on each (inputs resident), and for the contiguous intervals also the
+    interval call.  Values stay on the device; nothing is copied back inside
+    a timed call."""
+    stream = torch.cuda.current_stream()
+    res = {}
+    arrays = W.paper_arrays()
+    for name, (lo, length) in W.PAPER_INTERVALS.items():
+        dev = torch.arange(lo, lo + length, dtype=torch.int64, device="cuda")
+        out = torch.empty(length, dtype=torch.uint8, device="cuda")
+        rout = torch.empty(length, dtype=torch.bool, device="cuda")
+        ms = _time_ms(torch, stream, lambda: isp.isprime_into(dev, out, stream), reps)
+        rms = _time_ms(torch, stream, lambda: isp.isprime_range(lo, length, rout, stream), reps)
+        same = bool(torch.equal(out.bool(), rout))
+        res[name] = {"elements": length, "ms": ms, "tests_per_s": length / (ms * 1e-3),
+                     "interval_ms": rms, "interval_tests_per_s": length / (rms * 1e-3),
+                     "interval_equals_array": same, "primes": int(out.sum().item())}
+        del dev, out, rout
+    for name, a in arrays.items():
+        dev = torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()
+        out = torch.empty(a.shape, dtype=torch.uint8, device="cuda")
+        ms = _time_ms(torch, stream, lambda: isp.isprime_into(dev, out, stream), reps)
+        res[name] = {"elements": int(a.size), "ms": ms, "tests_per_s": a.size / (ms * 1e-3),
+                     "primes": int(out.sum().item()), "input_sha256_16": W.digest(a)}
+    for name, r in res.items():
+        r["paper_matlab_s"] = PAPER_MATLAB_S[name]
+        best = min(r["ms"], r.get("interval_ms", r["ms"])) * 1e-3
+        r["x_vs_paper_matlab"] = PAPER_MATLAB_S[name] / best
+    return res
+
+
+def bench_intervals(isp, torch, reps: int = 5) -> dict:
+    """The interval call above 2^32, where each workgroup sieves a segment in
+    LDS: one interval whose segments the sieve decides alone (below 2^40) and
+    one whose survivors go on to Miller-Rabin, each against the array call
+    on the same values."""
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, lo in (("2^34+[0,2^28)", 1 << 34), ("2^50+[0,2^28)", 1 << 50),
+                     ("2^63+[0,2^28)", 1 << 63)):
+        length = 1 << 28
+        rout = torch.empty(length, dtype=torch.bool, device="cuda")
+        rms = _time_ms(torch, stream, lambda: isp.isprime_range(lo, length, rout, stream), reps)
+        # the same values as an array (int64 view of the uint64 values)
+        base = lo if lo < (1 << 63) else lo - (1 << 64)
+        dev = torch.arange(base, base + length, dtype=torch.int64, device="cuda")
+        out = torch.empty(length, dtype=torch.uint8, device="cuda")
+        ms = _time_ms(torch, stream, lambda: isp.isprime_into(dev, out, stream), reps)
+        res[name] = {"elements": length, "interval_ms": rms,
+                     "interval_tests_per_s": length / (rms * 1e-3), "array_ms": ms,
+                     "array_tests_per_s": length / (ms * 1e-3),
+                     "same_bytes": bool(torch.equal(out.bool(), rout)),
+                     "primes": int(rout.sum().item())}
+        del dev, out, rout
+    return res
+
+
 def bench_batched(isp, W, torch, reps: int = 5) -> dict:
     """4096 arrays of log-uniform length in [1, 2^16], magnitude class per
     array: one isprime_u64_batched call (graph replay) vs one isprime_u64
@@ -391,6 +479,9 @@ def main() -> int:
         del c3
         forms["batched"] = with_tuning("c4_batched", 25341952, lambda: bench_batched(isp, W, torch))
         forms["served"] = bench_served(isp, W, torch)
+        isp.set_config(**defaults)
+        forms["paper_workloads"] = bench_paper_suite(isp, W, torch)
+        forms["intervals"] = bench_intervals(isp, torch)
 
     cpu = None
     bit_exact = None

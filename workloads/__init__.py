@@ -26,6 +26,16 @@ is measured on):
                      drawn from one magnitude class.
 * ``c5_requests``    a Poisson request stream of arrays, lengths log-uniform
                      in [1, 2^20], classes as in ``c4_batched``.
+
+``paper_arrays()`` rebuilds the array workloads of the paper's
+incrementing-sequence table (section 6.1.3) and array-performance table
+(section 8.2) from their descriptions; ``PAPER_INTERVALS`` names the ones
+that are contiguous intervals.  The lists they need that depend on
+primality (primes below 2^17, the largest 52-bit prime, the 100 largest
+64-bit primes, the 100 largest composites below 2^64 with every prime factor
+above 2*10^7) are read from ``paper_lists.txt``, written by
+``make_paper_lists.py`` with the oracle.  The normal distributions' standard
+deviation is not printed in the paper; it is taken as mean / 16.
 """
 from __future__ import annotations
 
@@ -45,6 +55,7 @@ SEED_C2 = 0x2108047900000002
 SEED_C3 = 0x2108047900000003
 SEED_C4 = 0x2108047900000004
 SEED_C5 = 0x2108047900000005
+SEED_PAPER = 0x2108047900000006
 
 # Magnitude classes of the batched and served workloads: [lo, hi) as
 # (shift, lo): a draw r gives r >> shift, accepted when >= lo.
@@ -190,6 +201,82 @@ def c5_requests(num: int = 2100, qps: float = 1000.0, max_len: int = 1 << 20,
         reqs.append((float(t[i]), class_values(vseed, idx, c), c))
         off += L
     return reqs
+
+
+def _paper_list(name: str) -> np.ndarray:
+    vals, cur = {}, None
+    for line in open(os.path.join(_HERE, "paper_lists.txt")):
+        if line.startswith("# "):
+            parts = line.split()
+            cur = parts[1] if len(parts) == 3 else None
+            if cur:
+                vals[cur] = []
+        elif cur:
+            vals[cur] += [int(x) for x in line.split()]
+    return np.array(vals[name], dtype=np.uint64)
+
+
+def _std_normal(seed: int, idx: np.ndarray, j: int) -> np.ndarray:
+    """Standard normal deviates by the Box-Muller transform of draws j, j+1."""
+    u1 = ((element_draws(seed, idx, j) >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+    u2 = (element_draws(seed, idx, j + 1) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def _normal_int(seed: int, n: int, mean: int, std: int) -> np.ndarray:
+    """mean + round(std * z): exact integer offsets around a power of two."""
+    z = _std_normal(seed, np.arange(n, dtype=np.uint64), 0)
+    off = np.rint(z * std).astype(np.int64)  # |z| < 9, so mean + off stays in [0, 2^63)
+    return (np.int64(mean) + off).astype(np.uint64)
+
+
+# 1:N of the incrementing-sequence table and the Unix seconds of 2021
+# (1609477200 through 1609477200 + 3600 * 24 * 365, inclusive): (lo, length).
+PAPER_INTERVALS = {
+    "inc_1e4": (1, 10 ** 4),
+    "inc_1e5": (1, 10 ** 5),
+    "inc_1e6": (1, 10 ** 6),
+    "inc_1e7": (1, 10 ** 7),
+    "inc_1e8": (1, 10 ** 8),
+    "unix_2021": (1609477200, 3600 * 24 * 365 + 1),
+}
+
+
+def interval(lo: int, length: int) -> np.ndarray:
+    return np.uint64(lo) + np.arange(length, dtype=np.uint64)
+
+
+def paper_arrays(seed: int = SEED_PAPER, include_intervals: bool = False) -> dict:
+    """name -> uint64 array (matrix workloads keep their 2-D shape)."""
+    sub = [int(x) for x in draws(seed, np.arange(16, dtype=np.uint64) + np.uint64(1 << 40))]
+    pool = _paper_list("primes_below_2_17")
+    out = {}
+    if include_intervals:
+        for name, (lo, length) in PAPER_INTERVALS.items():
+            out[name] = interval(lo, length)
+    # 200 primes of int16 (below 2^15), uniform over that list
+    p15 = pool[pool < np.uint64(1 << 15)]
+    r = element_draws(sub[0], np.arange(200, dtype=np.uint64), 0)
+    out["int16_primes_200"] = p15[(r % np.uint64(p15.size)).astype(np.int64)]
+    # 1000 x 1000 random 32-bit integers
+    r = element_draws(sub[1], np.arange(10 ** 6, dtype=np.uint64), 0) >> np.uint64(32)
+    out["matrix_1000x1000_u32"] = r.reshape(1000, 1000)
+    # 1M primes, normal around 2^16: each draw moves up to the next prime
+    v = np.clip(_normal_int(sub[2], 10 ** 6, 1 << 16, 1 << 12), 2, (1 << 17) - 1)
+    k = np.minimum(np.searchsorted(pool, v, side="left"), pool.size - 1)
+    out["normal_primes_1m_mean_2_16"] = pool[k]
+    # 100,000 odd numbers, normal around 2^32
+    out["normal_odd_100k_mean_2_32"] = _normal_int(sub[3], 10 ** 5, 1 << 32, 1 << 28) | np.uint64(1)
+    # 1000 numbers, normal around 2^53
+    out["normal_1000_mean_2_53"] = _normal_int(sub[4], 1000, 1 << 53, 1 << 49)
+    # the largest 52-bit prime, 1000 times
+    out["largest52_prime_x1000"] = np.repeat(_paper_list("largest_prime_below_2_52"), 1000)
+    # the 100 largest composites below 2^64 with all prime factors > 2*10^7
+    out["composites_100_factors_gt_2e7"] = _paper_list("largest_composites_factors_gt_2e7")
+    # the 100 largest 64-bit primes; the 5000 largest 64-bit odd integers
+    out["largest64_primes_100"] = _paper_list("largest_64bit_primes")
+    out["largest64_odd_5000"] = np.uint64((1 << 64) - 1) - np.uint64(2) * np.arange(5000, dtype=np.uint64)
+    return out
 
 
 def digest(a: np.ndarray) -> str:
