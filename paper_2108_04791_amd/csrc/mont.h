@@ -40,15 +40,57 @@ __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b)
     return __umul64hi(a, b);
 }
 
-// a * b * 2^-64 mod n, for a*b < n*2^64.
+__device__ __forceinline__ uint32_t lo32(uint64_t x) { return (uint32_t)x; }
+__device__ __forceinline__ uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }
+__device__ __forceinline__ uint64_t pair32(uint32_t lo, uint32_t hi)
+{
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// a*b + c for 32-bit a, b and 64-bit c, as one v_mad_u64_u32, with the
+// carry out of the 64-bit sum returned as 0 or 1 (the instruction's own
+// carry-out lane mask, turned into a value by v_cndmask).  A VALU write of
+// an SGPR followed by a VALU read of it needs two wait states on this
+// target, hence the s_nop.  Pure register arithmetic.
+__device__ __forceinline__ uint64_t mad_carry(uint32_t a, uint32_t b, uint64_t c, uint32_t &k)
+{
+    uint64_t r, cc;
+    asm("v_mad_u64_u32 %0, %1, %3, %4, %5\n\t"
+        "s_nop 1\n\t"
+        "v_cndmask_b32_e64 %2, 0, 1, %1"
+        : "=v"(r), "=&s"(cc), "=v"(k)
+        : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// a * b * 2^-64 mod n, for a*b < n*2^64, on 32-bit halves (x = x1 2^32 + x0).
+//
+// T = a*b: with c = floor(a0 b0 / 2^32), M1 = a1 b0 + c < 2^64 and
+// M2 = a0 b1 + M1 < 2^65 (carry k), T = (a1 b1 + floor(M2 / 2^32) + k 2^32) 2^64
+// + (M2 mod 2^32) 2^32 + (a0 b0 mod 2^32).  m = (T mod 2^64) ninv mod 2^64
+// needs only the low product and two low-half cross products.  floor(m n /
+// 2^64) is assembled the same way from m0 n0, m1 n0, m0 n1 and m1 n1.  Every
+// 32x32+64 step is one v_mad_u64_u32; the whole product is 22 VALU
+// instructions plus one compare that the compiler adds for the final select.
 __device__ __forceinline__ uint64_t montmul(uint64_t a, uint64_t b, uint64_t n, uint64_t ninv)
 {
-    unsigned __int128 T = (unsigned __int128)a * b;
-    uint64_t lo = (uint64_t)T, hi = (uint64_t)(T >> 64);
-    uint64_t m = lo * ninv;
-    uint64_t mh = mulhi64(m, n);
-    uint64_t t = hi - mh;
-    return hi < mh ? t + n : t;
+    const uint32_t a0 = lo32(a), a1 = hi32(a), b0 = lo32(b), b1 = hi32(b);
+    const uint32_t t0 = a0 * b0;
+    const uint64_t M1 = (uint64_t)a1 * b0 + __umulhi(a0, b0);
+    uint32_t k;
+    const uint64_t M2 = mad_carry(a0, b1, M1, k);
+    const uint64_t hi = (uint64_t)a1 * b1 + pair32(hi32(M2), k);
+    const uint32_t t1 = lo32(M2);
+    const uint32_t n0 = lo32(n), n1 = hi32(n), i0 = lo32(ninv), i1 = hi32(ninv);
+    const uint64_t X = (uint64_t)t0 * i0;
+    const uint32_t m0 = lo32(X);
+    const uint32_t m1 = hi32(X) + t0 * i1 + t1 * i0;
+    const uint64_t Z = (uint64_t)m1 * n0 + __umulhi(m0, n0);
+    uint32_t k2;
+    const uint64_t Z2 = mad_carry(m0, n1, Z, k2);
+    const uint64_t h = (uint64_t)m1 * n1 + pair32(hi32(Z2), k2);
+    const uint64_t t = hi - h;
+    return hi < h ? t + n : t;
 }
 
 __device__ __forceinline__ uint64_t montsqr(uint64_t a, uint64_t n, uint64_t ninv)

@@ -42,13 +42,13 @@ namespace isp {
 
 namespace {
 
-// (x << 1) + a modulo 2^64 as the single gfx950 instruction v_lshl_add_u64
-// (the compiler otherwise turns x*2 + (2^64 - n) into a select of n and a
-// two-instruction 64-bit subtract).  Pure VALU arithmetic, no memory access.
-__device__ __forceinline__ uint64_t shl1_add(uint64_t x, uint64_t a)
+// (x << b) + a modulo 2^64 for a per-lane shift b in {0, 1}, as the single
+// gfx950 instruction v_lshl_add_u64 (its shift operand takes 0 to 4).  Pure
+// VALU arithmetic, no memory access.
+__device__ __forceinline__ uint64_t shl_add(uint64_t x, uint32_t b, uint64_t a)
 {
     uint64_t r;
-    asm("v_lshl_add_u64 %0, %1, 1, %2" : "=v"(r) : "v"(x), "v"(a));
+    asm("v_lshl_add_u64 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(b), "v"(a));
     return r;
 }
 
@@ -71,13 +71,13 @@ __device__ __forceinline__ bool sprp_base2(uint64_t n)
     // and then 2x - n = 2x + (2^64 - n) modulo 2^64, carry or not.
     const uint64_t half = (n >> 1) + 1, neg_n = 0 - n;
     while (rest != 0) {
-        const bool bit = (int64_t)rest < 0;
+        const uint32_t bit = hi32(rest) >> 31;
         rest <<= 1;
         x = montsqr(x, n, c.ninv);
-        const uint64_t y = x << 1;
-        const uint64_t z = shl1_add(x, neg_n);  // both computed: selects, no branch
-        const bool wrap = x >= half;
-        x = bit ? (wrap ? z : y) : x;
+        // x <- 2^bit x mod n in one instruction: (x << bit) + (2^64 - n) when
+        // the bit is set and 2x wraps past n, (x << bit) + 0 otherwise
+        const uint64_t sub = (bit != 0 && x >= half) ? neg_n : 0;
+        x = shl_add(x, bit, sub);
     }
     bool pass = x == c.one || x == c.mone;
     const int s = __ffsll((long long)(n - 1)) - 1;
