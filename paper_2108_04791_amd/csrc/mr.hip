@@ -301,10 +301,16 @@ __device__ __forceinline__ void lds_prefix(const uint32_t *__restrict__ counts, 
     __syncthreads();
 }
 
-// Region of dense index i: the largest k < nc with pre[k] <= i.
-__device__ __forceinline__ uint32_t find_region(const uint32_t *pre, uint32_t nc, uint32_t i)
+// Region of dense index i: the largest k < nc with pre[k] <= i, given a k
+// with pre[k] <= i to start from.  A lane's indices only grow, so its
+// previous region is such a start: one LDS read while i stays in it, else a
+// binary search above it.  pre[nc] is the total, so pre[k + 1] is readable.
+__device__ __forceinline__ uint32_t find_region(const uint32_t *pre, uint32_t nc, uint32_t k,
+                                                uint32_t i)
 {
-    uint32_t lo = 0, hi = nc;  // pre[lo] <= i < pre[hi]
+    if (pre[k + 1] > i)
+        return k;
+    uint32_t lo = k + 1, hi = nc;  // pre[lo] <= i < pre[hi]
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
         if (pre[mid] <= i)
@@ -337,7 +343,7 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
     const uint32_t s1 = (uint32_t)((uint64_t)n1 * (g + 1) / a.grid1);
     Survivor *region = a.cand + (uint64_t)g * chunk_1;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    uint32_t filled = 0;
+    uint32_t filled = 0, k = 0;
     for (uint32_t r0 = s0; r0 < s1; r0 += blockDim.x) {
         const uint32_t i = r0 + threadIdx.x;
         bool pass = false;
@@ -345,7 +351,7 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
         sv.n = 0;
         sv.out = nullptr;
         if (i < s1) {
-            const uint32_t k = find_region(pre, a.grid_c, i);
+            k = find_region(pre, a.grid_c, k, i);
             sv = a.surv[(uint64_t)k * chunk_c + (i - pre[k])];
             pass = sprp_base2(sv.n);
         }
@@ -388,10 +394,11 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase2_kernel(MrArgs a)
     const uint64_t g = blockIdx.x;
     const uint64_t s0 = tasks * g / gridDim.x;
     const uint64_t s1 = tasks * (g + 1) / gridDim.x;
+    uint32_t k = 0;
     for (uint64_t t = s0 + threadIdx.x; t < s1; t += blockDim.x) {
         const uint32_t j = (uint32_t)(t / 6);
         const uint32_t b = (uint32_t)(t - 6ull * j);
-        const uint32_t k = find_region(pre, a.grid1, j);
+        k = find_region(pre, a.grid1, k, j);
         const Survivor sv = a.cand[(uint64_t)k * chunk_1 + (j - pre[k])];
         if (!sprp_one_base<W>(sv.n, BASES[b], tbl))
             *sv.out = 0;  // composite; the base-2 round had written 1
@@ -415,8 +422,9 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) lucas_kernel(MrArgs a)
     const uint64_t g = blockIdx.x;
     const uint64_t s0 = n2 * g / gridDim.x;
     const uint64_t s1 = n2 * (g + 1) / gridDim.x;
+    uint32_t k = 0;
     for (uint64_t j = s0 + threadIdx.x; j < s1; j += blockDim.x) {
-        const uint32_t k = find_region(pre, a.grid1, (uint32_t)j);
+        k = find_region(pre, a.grid1, k, (uint32_t)j);
         const Survivor sv = a.cand[(uint64_t)k * chunk_1 + ((uint32_t)j - pre[k])];
         int v = strong_lucas(sv.n);
         if (v < 0) {
