@@ -52,38 +52,63 @@ __device__ __forceinline__ uint64_t shl_add(uint64_t x, uint32_t b, uint64_t a)
     return r;
 }
 
+// Largest value of v over the wavefront; every lane must be active.
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
 // Strong probable-prime test to base 2 for odd n >= 2^32, n - 1 = 2^s d.
+// Called with all 64 lanes of the wavefront active.
 //
-// x runs over 2^(floor((n-1) / 2^t)) (Montgomery form) for t = L-1 down to
-// s: one squaring per bit and a modular doubling when the bit is set.
-// `rest` holds the bits of n - 1 below t shifted to the top, so the next
-// bit is its sign bit and rest == 0 right after bit s, the lowest set bit,
-// is consumed: then x = 2^d.  The chain 2^(2^r d), r = 1 .. s-1, follows
-// and stops as soon as -1 shows up.  A wavefront of one bit length runs
-// L - 2 steps plus the spread of s between its lanes.
+// x runs over x_t = 2^(floor((n-1) / 2^t)) (Montgomery form) for t = L-1
+// down to 1: one squaring per bit and a modular doubling when the bit is
+// set.  x_s = 2^d, and below s the bits are zero, so x_t = 2^(2^(s-t) d) for
+// t <= s: n passes iff x_s = 1 or x_t = -1 for some 1 <= t <= s.  Every
+// lane therefore runs the same L - 2 steps whatever its s, and only the
+// last smax steps (smax: the largest s in the wavefront) compare.
+//
+// The first L - 2 - smax bits come from `rest`, the bits of n - 1 shifted
+// to the top with a marker bit just below the last of them: the loop stops
+// when the marker reaches the top.
 __device__ __forceinline__ bool sprp_base2(uint64_t n)
 {
     const int L = 64 - __clzll(n);
     const MontCtx c = make_ctx(n, L);
-    uint64_t rest = (n - 1) << (65 - L);  // bits L-2 .. 0 of n - 1, at the top
-    uint64_t x = dbl_mod(c.one, n);        // bit L-1 (the leading one): x = 2
+    const uint64_t e = n - 1;
+    const int s = __ffsll((long long)e) - 1;
+    const int smax = wave_max(s);
+    uint64_t x = dbl_mod(c.one, n);  // bit L-1 (the leading one): x = 2
     // 2x mod n for x < n: 2x >= n exactly when x >= (n + 1) / 2 (n is odd),
     // and then 2x - n = 2x + (2^64 - n) modulo 2^64, carry or not.
     const uint64_t half = (n >> 1) + 1, neg_n = 0 - n;
-    while (rest != 0) {
-        const uint32_t bit = hi32(rest) >> 31;
-        rest <<= 1;
+    auto step = [&](uint32_t bit) {
         x = montsqr(x, n, c.ninv);
         // x <- 2^bit x mod n in one instruction: (x << bit) + (2^64 - n) when
         // the bit is set and 2x wraps past n, (x << bit) + 0 otherwise
         const uint64_t sub = (bit != 0 && x >= half) ? neg_n : 0;
         x = shl_add(x, bit, sub);
+    };
+    // bits L-2 .. smax+1: bit t of n - 1 sits at t + 65 - L, the marker at
+    // smax + 65 - L (bits below it cleared) and reaches bit 63 when done
+    const int mpos = smax + 65 - L;
+    uint64_t rest = (uint64_t)1 << 63;
+    if (mpos < 63)
+        rest = ((e << (65 - L)) & (~(uint64_t)0 << (mpos + 1))) | ((uint64_t)1 << mpos);
+    while (rest != ((uint64_t)1 << 63)) {
+        const uint32_t bit = hi32(rest) >> 31;
+        rest <<= 1;
+        step(bit);
     }
-    bool pass = x == c.one || x == c.mone;
-    const int s = __ffsll((long long)(n - 1)) - 1;
-    for (int r = 1; r < s && !pass; ++r) {
-        x = montsqr(x, n, c.ninv);
-        pass = x == c.mone;
+    // bits smax .. 1, comparing
+    bool pass = false;
+    for (int t = smax; t >= 1; --t) {
+        if (t <= L - 2)
+            step((uint32_t)(e >> t) & 1u);
+        pass |= (t <= s && x == c.mone) || (t == s && x == c.one);
     }
     return pass;
 }
@@ -350,10 +375,16 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
         Survivor sv;
         sv.n = 0;
         sv.out = nullptr;
-        if (i < s1) {
-            k = find_region(pre, a.grid_c, k, i);
-            sv = a.surv[(uint64_t)k * chunk_c + (i - pre[k])];
-            pass = sprp_base2(sv.n);
+        const uint64_t act = __ballot(i < s1);
+        if (act != 0) {  // uniform over the wavefront
+            if (i < s1) {
+                k = find_region(pre, a.grid_c, k, i);
+                sv = a.surv[(uint64_t)k * chunk_c + (i - pre[k])];
+            }
+            // idle lanes test a copy of an active lane's value, so the whole
+            // wavefront runs sprp_base2 together
+            const uint64_t nv = __shfl(sv.n, __ffsll((long long)act) - 1, 64);
+            pass = sprp_base2(i < s1 ? sv.n : nv) && i < s1;
         }
         const uint64_t m = __ballot(pass);
         if (lane == 0)
