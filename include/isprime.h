@@ -117,7 +117,7 @@ typedef struct {
     int32_t classify_blocks_per_cu; /* classify grid = CUs x this (at most 4096): 1..16 */
     int32_t filter_primes;          /* odd primes in the trial filter: -1 (none), 8, 16, 24, 32, 48 or 64 */
     int32_t sort_survivors;         /* 1: order survivors by bit length; -1: keep input order */
-    int32_t mr_block;               /* threads per Miller-Rabin block: 64..256, multiple of 64 */
+    int32_t mr_block;               /* threads per Miller-Rabin block: 64..1024, multiple of 64 */
     int32_t mr_blocks_per_cu;       /* Miller-Rabin grids = CUs x this (at most 4096): 1..16 */
     int32_t mr_window;              /* fixed window width for bases other than 2: 1..4 */
     int32_t rest_test;              /* after base 2: -1 the six remaining Miller-Rabin bases of

@@ -43,7 +43,7 @@ std::atomic<int> g_last_err{0};
 std::mutex g_cfg_mu;
 // The autotuner's choice for 2^24 64-bit values; other classes are in the
 // tuning database that paper_2108_04791_amd/tune.py writes.
-constexpr isp_config DEFAULT_CONFIG = {512, 8, 4, 24, 1, 256, 12, 3, -1};
+constexpr isp_config DEFAULT_CONFIG = {512, 8, 4, 24, 1, 1024, 2, 3, -1};
 isp_config g_cfg = DEFAULT_CONFIG;
 
 int fail(hipError_t e)

@@ -15,7 +15,7 @@ constexpr uint64_t TABLE_WORDS = (uint64_t)1 << 26;  // 2^31 odd numbers / 32
 constexpr int MAX_BASE_PRIMES = 6542;                // odd primes below 2^16: 6541
 constexpr int MAX_FILTER_PRIMES = 128;
 constexpr int NUM_BINS = 32;                         // bit lengths 33..64
-constexpr int MR_MAX_BLOCK = 256;                    // launch bound of the Miller-Rabin kernels
+constexpr int MR_MAX_BLOCK = 1024;                   // launch bound of the Miller-Rabin kernels
 
 // A survivor of the trial filter: the value and where its verdict goes.
 struct Survivor {

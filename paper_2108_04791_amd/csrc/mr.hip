@@ -356,8 +356,8 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
     extern __shared__ uint64_t dyn[];
     uint32_t *pre = reinterpret_cast<uint32_t *>(dyn);  // grid_c + 1 entries
     __shared__ uint32_t wsum[MR_MAX_BLOCK / 64];
-    __shared__ uint32_t wave_cnt[MR_MAX_BLOCK / 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    __shared__ uint32_t next, fill;
+    const int lane = threadIdx.x & 63;
     const uint64_t total = call_total(a);
     const uint64_t chunk_c = classify_chunk(total, a.grid_c);
     const uint64_t chunk_1 = cand_chunk(total, a.grid1);
@@ -366,45 +366,50 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
     const uint32_t g = blockIdx.x;
     const uint32_t s0 = (uint32_t)((uint64_t)n1 * g / a.grid1);
     const uint32_t s1 = (uint32_t)((uint64_t)n1 * (g + 1) / a.grid1);
+    if (threadIdx.x == 0) {
+        next = s0;
+        fill = 0;
+    }
+    __syncthreads();
     Survivor *region = a.cand + (uint64_t)g * chunk_1;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    uint32_t filled = 0, k = 0;
-    for (uint32_t r0 = s0; r0 < s1; r0 += blockDim.x) {
-        const uint32_t i = r0 + threadIdx.x;
-        bool pass = false;
+    uint32_t k = 0;
+    for (;;) {
+        // the wavefront takes the next 64 survivors of the workgroup's slice
+        uint32_t i0 = 0;
+        if (lane == 0)
+            i0 = atomicAdd(&next, 64u);
+        i0 = __shfl(i0, 0, 64);
+        if (i0 >= s1)
+            break;
+        const uint32_t i = i0 + lane;
         Survivor sv;
         sv.n = 0;
         sv.out = nullptr;
+        if (i < s1) {
+            k = find_region(pre, a.grid_c, k, i);
+            sv = a.surv[(uint64_t)k * chunk_c + (i - pre[k])];
+        }
+        // idle lanes test a copy of an active lane's value, so the whole
+        // wavefront runs sprp_base2 together
         const uint64_t act = __ballot(i < s1);
-        if (act != 0) {  // uniform over the wavefront
-            if (i < s1) {
-                k = find_region(pre, a.grid_c, k, i);
-                sv = a.surv[(uint64_t)k * chunk_c + (i - pre[k])];
-            }
-            // idle lanes test a copy of an active lane's value, so the whole
-            // wavefront runs sprp_base2 together
-            const uint64_t nv = __shfl(sv.n, __ffsll((long long)act) - 1, 64);
-            pass = sprp_base2(i < s1 ? sv.n : nv) && i < s1;
-        }
+        const uint64_t nv = __shfl(sv.n, __ffsll((long long)act) - 1, 64);
+        const bool pass = sprp_base2(i < s1 ? sv.n : nv) && i < s1;
         const uint64_t m = __ballot(pass);
-        if (lane == 0)
-            wave_cnt[wave] = (uint32_t)__popcll(m);
-        __syncthreads();
-        uint32_t before = 0, all = 0;
-        for (int w = 0; w < nwaves; ++w) {
-            const uint32_t c = wave_cnt[w];
-            before += w < wave ? c : 0u;
-            all += c;
+        if (m != 0) {
+            uint32_t at = 0;
+            if (lane == 0)
+                at = atomicAdd(&fill, (uint32_t)__popcll(m));
+            at = __shfl(at, 0, 64);
+            if (pass) {
+                region[at + __popcll(m & lt)] = sv;
+                *sv.out = 1;  // provisional: a failing later base clears it
+            }
         }
-        if (pass) {
-            region[filled + before + __popcll(m & lt)] = sv;
-            *sv.out = 1;  // provisional: a failing later base clears it
-        }
-        filled += all;
-        __syncthreads();  // wave_cnt is rewritten next round
     }
+    __syncthreads();
     if (threadIdx.x == 0)
-        a.counts1[g] = filled;
+        a.counts1[g] = fill;
 }
 
 template <int W>
@@ -416,7 +421,9 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase2_kernel(MrArgs a)
     uint64_t *tbl = dyn;
     uint32_t *pre = reinterpret_cast<uint32_t *>(dyn + (1u << W) * blockDim.x);
     __shared__ uint32_t wsum[MR_MAX_BLOCK / 64];
+    __shared__ unsigned long long next;
     constexpr uint32_t BASES[6] = {325u, 9375u, 28178u, 450775u, 9780504u, 1795265022u};
+    const int lane = threadIdx.x & 63;
     const uint64_t total = call_total(a);
     const uint64_t chunk_1 = cand_chunk(total, a.grid1);
     lds_prefix(a.counts1, a.grid1, pre, wsum);
@@ -425,14 +432,27 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase2_kernel(MrArgs a)
     const uint64_t g = blockIdx.x;
     const uint64_t s0 = tasks * g / gridDim.x;
     const uint64_t s1 = tasks * (g + 1) / gridDim.x;
+    if (threadIdx.x == 0)
+        next = s0;
+    __syncthreads();
     uint32_t k = 0;
-    for (uint64_t t = s0 + threadIdx.x; t < s1; t += blockDim.x) {
-        const uint32_t j = (uint32_t)(t / 6);
-        const uint32_t b = (uint32_t)(t - 6ull * j);
-        k = find_region(pre, a.grid1, k, j);
-        const Survivor sv = a.cand[(uint64_t)k * chunk_1 + (j - pre[k])];
-        if (!sprp_one_base<W>(sv.n, BASES[b], tbl))
-            *sv.out = 0;  // composite; the base-2 round had written 1
+    for (;;) {
+        // the wavefront takes the next 64 tasks of the workgroup's slice
+        unsigned long long t0 = 0;
+        if (lane == 0)
+            t0 = atomicAdd(&next, 64ull);
+        t0 = __shfl(t0, 0, 64);
+        if (t0 >= s1)
+            break;
+        const uint64_t t = t0 + lane;
+        if (t < s1) {
+            const uint32_t j = (uint32_t)(t / 6);
+            const uint32_t b = (uint32_t)(t - 6ull * j);
+            k = find_region(pre, a.grid1, k, j);
+            const Survivor sv = a.cand[(uint64_t)k * chunk_1 + (j - pre[k])];
+            if (!sprp_one_base<W>(sv.n, BASES[b], tbl))
+                *sv.out = 0;  // composite; the base-2 round had written 1
+        }
     }
 }
 
@@ -445,26 +465,40 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) lucas_kernel(MrArgs a)
     uint64_t *tbl = dyn;  // used only by the rare fallback to the Miller-Rabin bases
     uint32_t *pre = reinterpret_cast<uint32_t *>(dyn + (1u << W) * blockDim.x);
     __shared__ uint32_t wsum[MR_MAX_BLOCK / 64];
+    __shared__ uint32_t next;
     constexpr uint32_t BASES[6] = {325u, 9375u, 28178u, 450775u, 9780504u, 1795265022u};
+    const int lane = threadIdx.x & 63;
     const uint64_t total = call_total(a);
     const uint64_t chunk_1 = cand_chunk(total, a.grid1);
     lds_prefix(a.counts1, a.grid1, pre, wsum);
-    const uint64_t n2 = pre[a.grid1];
-    const uint64_t g = blockIdx.x;
-    const uint64_t s0 = n2 * g / gridDim.x;
-    const uint64_t s1 = n2 * (g + 1) / gridDim.x;
+    const uint32_t n2 = pre[a.grid1];
+    const uint32_t g = blockIdx.x;
+    const uint32_t s0 = (uint32_t)((uint64_t)n2 * g / gridDim.x);
+    const uint32_t s1 = (uint32_t)((uint64_t)n2 * (g + 1) / gridDim.x);
+    if (threadIdx.x == 0)
+        next = s0;
+    __syncthreads();
     uint32_t k = 0;
-    for (uint64_t j = s0 + threadIdx.x; j < s1; j += blockDim.x) {
-        k = find_region(pre, a.grid1, k, (uint32_t)j);
-        const Survivor sv = a.cand[(uint64_t)k * chunk_1 + ((uint32_t)j - pre[k])];
-        int v = strong_lucas(sv.n);
-        if (v < 0) {
-            v = 1;
-            for (int b = 0; b < 6 && v; ++b)
-                v = sprp_one_base<W>(sv.n, BASES[b], tbl);
+    for (;;) {
+        uint32_t j0 = 0;
+        if (lane == 0)
+            j0 = atomicAdd(&next, 64u);
+        j0 = __shfl(j0, 0, 64);
+        if (j0 >= s1)
+            break;
+        const uint32_t j = j0 + lane;
+        if (j < s1) {
+            k = find_region(pre, a.grid1, k, j);
+            const Survivor sv = a.cand[(uint64_t)k * chunk_1 + (j - pre[k])];
+            int v = strong_lucas(sv.n);
+            if (v < 0) {
+                v = 1;
+                for (int b = 0; b < 6 && v; ++b)
+                    v = sprp_one_base<W>(sv.n, BASES[b], tbl);
+            }
+            if (!v)
+                *sv.out = 0;
         }
-        if (!v)
-            *sv.out = 0;
     }
 }
 

@@ -26,11 +26,11 @@ from . import get_config, isprime_batched, isprime_into, set_config
 
 SPACE = {
     "classify_ept": [2, 4, 8],
-    "classify_block": [128, 256, 512],
-    "classify_blocks_per_cu": [4, 8, 16],
+    "classify_block": [256, 512, 1024],
+    "classify_blocks_per_cu": [1, 2, 4, 8],
     "filter_primes": [16, 24, 32, 48],
-    "mr_block": [128, 192, 256],
-    "mr_blocks_per_cu": [4, 8, 12, 16],
+    "mr_block": [256, 512, 1024],
+    "mr_blocks_per_cu": [1, 2, 4, 8],
     "mr_window": [2, 3, 4],
 }
 

@@ -185,6 +185,8 @@ def test_counts_match_host_accounting(isp):
     dict(mr_window=1), dict(mr_window=2), dict(mr_window=4),
     dict(mr_block=64, mr_blocks_per_cu=1),
     dict(mr_block=128, mr_blocks_per_cu=16),
+    dict(mr_block=1024, mr_blocks_per_cu=1),
+    dict(mr_block=512, mr_blocks_per_cu=4, mr_window=2),
 ])
 def test_configs_do_not_change_bits(isp, cfg):
     a = np.concatenate([np.array(EDGES, dtype=np.uint64), W.c3_mixed(30011, start=99),
