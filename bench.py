@@ -32,14 +32,16 @@ HBM_PEAK_GBS = 8000.0
 # full-rate VALU lane-instructions per second (on gfx950 the 32-bit
 # multiplies v_mad_u64_u32, v_mul_lo_u32 and v_mul_hi_u32 issue at full rate).
 VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
-# VALU instructions of the shortest gfx950 sequence for one 64-bit
-# Montgomery product (4 v_mad_u64_u32 + 4 carry adds for a*b, 1 v_mad_u64_u32
-# + 2 v_mul_lo_u32 + 1 v_add3_u32 for m, 1 v_mul_hi_u32 + 3 v_mad_u64_u32 + 4
-# carry adds for the high half of m*n, 2 subtracts + 2 selects + 1 add for the
-# correction: 27) and for one modular doubling (add, two tests, subtract,
-# select: 6).
-OPS_PER_MONTMUL = 27
-OPS_PER_DOUBLING = 6
+# VALU instructions of the shortest gfx950 sequence known here for one 64-bit
+# Montgomery product on 32-bit halves.  a*b: v_mul_lo_u32 and v_mul_hi_u32
+# for a0*b0, three v_mad_u64_u32 (a1*b0, a0*b1 with its carry-out, a1*b1),
+# one v_mov and one v_cndmask to form the carry pair: 7.  m = lo * n^-1: one
+# v_mad_u64_u32, two v_mul_lo_u32, one v_add3_u32: 4.  floor(m*n / 2^64): one
+# v_mul_hi_u32, three v_mad_u64_u32, one v_mov, one v_cndmask: 6.  The
+# correction: subtract with borrow (2), two selects and one 64-bit add: 5.
+# Total 22.  One modular doubling: shift, compare, two selects, add: 5.
+OPS_PER_MONTMUL = 22
+OPS_PER_DOUBLING = 5
 MR_BASES_AFTER_2 = 6
 
 

@@ -56,7 +56,7 @@ enum {
 
 /* Build the odd-only sieve table for n < 2^32 on `device` (bit i of the
  * table is 1 iff 2i+1 is prime; 2^31 bits = 256 MiB in HBM), together with
- * and the base primes.  Blocking; idempotent; thread-safe.
+ * the base primes.  Blocking; idempotent; thread-safe.
  * Every other entry point calls it lazily for the current device.
  * Paper: section 1 (sieve of Eratosthenes), section 4 (odd numbers only). */
 int isp_init(int device);

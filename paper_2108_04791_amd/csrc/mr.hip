@@ -52,36 +52,40 @@ __device__ __forceinline__ uint64_t shl_add(uint64_t x, uint32_t b, uint64_t a)
     return r;
 }
 
-// Largest value of v over the wavefront; every lane must be active.
+// Largest value of v over the wavefront, as a wavefront-uniform (scalar)
+// value; every lane must be active.
 __device__ __forceinline__ int wave_max(int v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
         v = max(v, __shfl_xor(v, o, 64));
-    return v;
+    return __builtin_amdgcn_readfirstlane(v);
 }
 
 // Strong probable-prime test to base 2 for odd n >= 2^32, n - 1 = 2^s d.
 // Called with all 64 lanes of the wavefront active.
 //
-// x runs over x_t = 2^(floor((n-1) / 2^t)) (Montgomery form) for t = L-1
-// down to 1: one squaring per bit and a modular doubling when the bit is
-// set.  x_s = 2^d, and below s the bits are zero, so x_t = 2^(2^(s-t) d) for
-// t <= s: n passes iff x_s = 1 or x_t = -1 for some 1 <= t <= s.  Every
-// lane therefore runs the same L - 2 steps whatever its s, and only the
-// last smax steps (smax: the largest s in the wavefront) compare.
+// x runs over x_t = 2^(floor((n-1) / 2^t)) (Montgomery form) for t from the
+// top down to 1: one squaring per bit and a modular doubling when the bit
+// is set.  x_s = 2^d, and below s the bits are zero, so x_t = 2^(2^(s-t) d)
+// for t <= s: n passes iff x_s = 1 or x_t = -1 for some 1 <= t <= s.
 //
-// The first L - 2 - smax bits come from `rest`, the bits of n - 1 shifted
-// to the top with a marker bit just below the last of them: the loop stops
-// when the marker reaches the top.
+// Every lane runs the same steps: bits Lmax - 2 down to 1, Lmax being the
+// largest bit length in the wavefront.  A lane with a shorter n starts from
+// x = 1 and squares it through its leading zero bits, so its first set bit
+// makes x = 2 exactly where its own exponent starts.  The loop count is the
+// same on all lanes (a scalar loop), and only the last smax steps (smax: the
+// largest s in the wavefront) compare.
 __device__ __forceinline__ bool sprp_base2(uint64_t n)
 {
     const int L = 64 - __clzll(n);
     const MontCtx c = make_ctx(n, L);
     const uint64_t e = n - 1;
     const int s = __ffsll((long long)e) - 1;
-    const int smax = wave_max(s);
-    uint64_t x = dbl_mod(c.one, n);  // bit L-1 (the leading one): x = 2
+    const int Lmax = wave_max(L), smax = wave_max(s);
+    // bit Lmax - 1: the leading one of the longest lanes (x = 2), a leading
+    // zero of the others (x = 1)
+    uint64_t x = L == Lmax ? dbl_mod(c.one, n) : c.one;
     // 2x mod n for x < n: 2x >= n exactly when x >= (n + 1) / 2 (n is odd),
     // and then 2x - n = 2x + (2^64 - n) modulo 2^64, carry or not.
     const uint64_t half = (n >> 1) + 1, neg_n = 0 - n;
@@ -92,22 +96,21 @@ __device__ __forceinline__ bool sprp_base2(uint64_t n)
         const uint64_t sub = (bit != 0 && x >= half) ? neg_n : 0;
         x = shl_add(x, bit, sub);
     };
-    // bits L-2 .. smax+1: bit t of n - 1 sits at t + 65 - L, the marker at
-    // smax + 65 - L (bits below it cleared) and reaches bit 63 when done
-    const int mpos = smax + 65 - L;
-    uint64_t rest = (uint64_t)1 << 63;
-    if (mpos < 63)
-        rest = ((e << (65 - L)) & (~(uint64_t)0 << (mpos + 1))) | ((uint64_t)1 << mpos);
-    while (rest != ((uint64_t)1 << 63)) {
-        const uint32_t bit = hi32(rest) >> 31;
+    // bits Lmax - 2 .. smax + 1 from the top of `rest` (bit t of n - 1 at
+    // t + 65 - Lmax)
+    uint64_t rest = e << (65 - Lmax);
+    for (int t = Lmax - 2; t > smax; --t) {
+        // the top bit as an opaque value, so the select below tests it
+        // rather than the old `rest` (which would keep a copy of it alive)
+        uint32_t bit;
+        asm("v_lshrrev_b32 %0, 31, %1" : "=v"(bit) : "v"(hi32(rest)));
         rest <<= 1;
         step(bit);
     }
-    // bits smax .. 1, comparing
+    // bits min(smax, Lmax - 2) .. 1, comparing
     bool pass = false;
-    for (int t = smax; t >= 1; --t) {
-        if (t <= L - 2)
-            step((uint32_t)(e >> t) & 1u);
+    for (int t = smax < Lmax - 2 ? smax : Lmax - 2; t >= 1; --t) {
+        step((uint32_t)(e >> t) & 1u);
         pass |= (t <= s && x == c.mone) || (t == s && x == c.one);
     }
     return pass;
