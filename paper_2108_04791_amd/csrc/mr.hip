@@ -133,9 +133,12 @@ __device__ __forceinline__ bool sprp_window(uint64_t am, uint64_t d, int s, cons
         p = k == 1 ? am : montmul(p, am, c.n, c.ninv);
         tbl[k * stride + col] = p;
     }
+    // windows from the wavefront's longest d down: a lane with a shorter d
+    // reads window value 0 (table entry 1) until its own top window, so every
+    // lane runs the same scalar loop (all lanes must be active)
     const int Ld = 64 - __clzll(d);
-    const int nwin = (Ld + W - 1) / W;
-    int pos = (nwin - 1) * W;
+    const int nwin = wave_max((Ld + W - 1) / W);
+    int pos = (nwin - 1) * W;  // at most 63 - W: d < 2^63
     uint64_t x = tbl[((unsigned)(d >> pos) & (TS - 1)) * stride + col];
     for (pos -= W; pos >= 0; pos -= W) {
 #pragma unroll
@@ -447,15 +450,16 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase2_kernel(MrArgs a)
         t0 = __shfl(t0, 0, 64);
         if (t0 >= s1)
             break;
-        const uint64_t t = t0 + lane;
-        if (t < s1) {
-            const uint32_t j = (uint32_t)(t / 6);
-            const uint32_t b = (uint32_t)(t - 6ull * j);
-            k = find_region(pre, a.grid1, k, j);
-            const Survivor sv = a.cand[(uint64_t)k * chunk_1 + (j - pre[k])];
-            if (!sprp_one_base<W>(sv.n, BASES[b], tbl))
-                *sv.out = 0;  // composite; the base-2 round had written 1
-        }
+        // idle lanes at the end of the slice repeat task t0 (lane 0's), so
+        // the whole wavefront runs the test together; only real tasks store
+        const bool real = t0 + lane < s1;
+        const uint64_t t = real ? t0 + lane : t0;
+        const uint32_t j = (uint32_t)(t / 6);
+        const uint32_t b = (uint32_t)(t - 6ull * j);
+        k = find_region(pre, a.grid1, k, j);
+        const Survivor sv = a.cand[(uint64_t)k * chunk_1 + (j - pre[k])];
+        if (!sprp_one_base<W>(sv.n, BASES[b], tbl) && real)
+            *sv.out = 0;  // composite; the base-2 round had written 1
     }
 }
 
@@ -489,19 +493,25 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) lucas_kernel(MrArgs a)
         j0 = __shfl(j0, 0, 64);
         if (j0 >= s1)
             break;
-        const uint32_t j = j0 + lane;
-        if (j < s1) {
-            k = find_region(pre, a.grid1, k, j);
-            const Survivor sv = a.cand[(uint64_t)k * chunk_1 + (j - pre[k])];
-            int v = strong_lucas(sv.n);
-            if (v < 0) {
-                v = 1;
-                for (int b = 0; b < 6 && v; ++b)
-                    v = sprp_one_base<W>(sv.n, BASES[b], tbl);
-            }
-            if (!v)
-                *sv.out = 0;
+        // idle lanes at the end of the slice repeat candidate j0 (lane 0's),
+        // so the whole wavefront runs the tests together
+        const bool real = j0 + lane < s1;
+        const uint32_t j = real ? j0 + lane : j0;
+        k = find_region(pre, a.grid1, k, j);
+        const Survivor sv = a.cand[(uint64_t)k * chunk_1 + (j - pre[k])];
+        int v = strong_lucas(sv.n);
+        const bool need = v < 0;
+        if (__ballot(need) != 0) {
+            // the Miller-Rabin bases run on every lane (they need the whole
+            // wavefront); only the lanes without a Lucas verdict use them
+            bool w = true;
+            for (int b = 0; b < 6; ++b)
+                w = sprp_one_base<W>(sv.n, BASES[b], tbl) && w;
+            if (need)
+                v = w ? 1 : 0;
         }
+        if (!v && real)
+            *sv.out = 0;
     }
 }
 
