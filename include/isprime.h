@@ -93,7 +93,7 @@ int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
  *   out  device pointer to len bytes, each written 0 or 1
  * The part below 2^32 is read from the sieve table; above it, each
  * workgroup sieves a segment of 2^19 numbers by the odd primes up to
- * min(2^20, sqrt(segment end)) and, above 2^40, the survivors go through the
+ * min(2^22, sqrt(segment end)) and, above 2^44, the survivors go through the
  * same Miller-Rabin kernels as isprime_u64.  Asynchronous on `stream`.
  * Paper: section 6.1.3 (sieve up to the maximum, then test membership),
  * section 1 (the sieve of Eratosthenes). */

@@ -514,7 +514,7 @@ static int ensure_range_primes(int dev)
     if (s)
         (void)hipStreamDestroy(s);
     if (e == hipSuccess && count != RANGE_MAX_PRIMES - 1)
-        e = hipErrorUnknown;  // 82024 odd primes below 2^20
+        e = hipErrorUnknown;  // 295946 odd primes below 2^22
     if (e != hipSuccess) {
         (void)hipFree(ds.range_primes);
         (void)hipFree(ds.range_inv);

@@ -31,7 +31,7 @@ constexpr int MAX_GRID = 4096;
 // ones: 2^18 bits), and numbers per piece of an interval call.
 constexpr uint64_t RANGE_SEG = (uint64_t)1 << 19;
 constexpr uint64_t RANGE_PIECE = (uint64_t)1 << 30;
-constexpr int RANGE_MAX_PRIMES = 82025;  // odd primes below 2^20: 82024
+constexpr int RANGE_MAX_PRIMES = 295947;  // odd primes below 2^22: 295946
 
 // Device-resident descriptor of a batched call.  The arrays follow the
 // header in the same allocation; the pointers address them.
@@ -99,7 +99,7 @@ struct DeviceState {
     uint32_t *base_primes = nullptr; // odd primes < 2^16
     uint32_t *base_count = nullptr;  // device word: how many
     int num_base_primes = 0;
-    // interval sieve: odd primes below 2^20 and floor((2^64-1)/p), built on
+    // interval sieve: odd primes below 2^22 and floor((2^64-1)/p), built on
     // first use of isprime_range_u64
     uint32_t *range_primes = nullptr;
     uint64_t *range_inv = nullptr;

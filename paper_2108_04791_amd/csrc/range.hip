@@ -6,19 +6,26 @@
 // For an interval that is the natural way to work: the part below 2^32 is
 // copied out of the device table, bit by bit; above it, each workgroup sieves
 // one segment of the interval in LDS by the odd primes up to
-// min(2^20, sqrt(segment end)).  When those primes reach the square root
-// (segment end <= 2^40) the survivors are exactly the primes; otherwise the
-// survivors (about 4% of the numbers: those with no factor below 2^20) go to
-// the same two Miller-Rabin kernels as array inputs, through the same
+// min(2^22, sqrt(segment end)).  When those primes reach the square root
+// (segment end <= 2^44) the survivors are exactly the primes; otherwise the
+// survivors (about 3.4% of the numbers: those with no factor below 2^22) go
+// to the same two Miller-Rabin kernels as array inputs, through the same
 // per-workgroup regions and counts.
 //
 // Segment layout: workgroup g covers numbers [lo + g*chunk, lo + (g+1)*chunk)
 // with chunk = classify_chunk(len, grid) (a multiple of 64, at most
-// RANGE_SEG + 63); bit j of its LDS bitset stands for the odd number o0 + 2j.
-// Crossing off: primes below 8192 by whole wavefronts (lane l takes the
-// multiples l, l+64, ...), larger primes one per thread.  The first odd
-// multiple of p at or above max(o0, p^2) needs o0 mod p, taken with a
-// precomputed floor((2^64 - 1) / p) (one 64-bit multiply-high, no division).
+// RANGE_SEG); bit j of its LDS bitset stands for the odd number o0 + 2j.
+// The multiples of 3 .. 31 come from periodic word masks (pre-sieve);
+// primes 37 .. 8191 are crossed off by whole wavefronts (lane l takes the
+// multiples l, l+64, ... of the stride), larger primes one per thread.  The
+// first odd multiple of p at or above max(o0, p^2) needs o0 mod p, taken
+// with a precomputed floor((2^64 - 1) / p) (one 64-bit multiply-high, no
+// division).
+//
+// Output: 32 consecutive numbers per thread per pass.  Their 16 odd members
+// are 16 consecutive bits; each group of 4 bits becomes 8 output bytes by one
+// multiply that spreads bit i to byte 2i (or 2i + 1), so a thread writes its
+// 32 bytes with two 16-byte stores.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -29,6 +36,25 @@ namespace {
 
 constexpr int RANGE_THREADS = 512;
 constexpr uint32_t WAVE_PRIME_LIMIT = 8192;  // primes below this: wavefront per prime
+constexpr int PRESIEVED = 10;                 // 3 .. 31: index of 37 in the prime list
+constexpr uint32_t SMALL_PRIMES[PRESIEVED] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
+
+// Bits j < 32 with j = 0 (mod p).
+__host__ __device__ constexpr uint32_t period_mask(uint32_t p)
+{
+    uint32_t m = 0;
+    for (uint32_t j = 0; j < 32; j += p)
+        m |= 1u << j;
+    return m;
+}
+
+// Bits 0..3 of `nib` moved to bits 0, 16, 32, 48 (bytes 0, 2, 4, 6): the
+// product nib * (1 + 2^15 + 2^30 + 2^45) holds bit i + 15k for every set bit
+// i and every k < 4, all distinct, and i + 15k = 16m only for i = k = m.
+__device__ __forceinline__ uint64_t spread4(uint32_t nib)
+{
+    return ((uint64_t)nib * 0x0000200040008001ull) & 0x0001000100010001ull;
+}
 
 __device__ __forceinline__ uint64_t umulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
 
@@ -44,19 +70,20 @@ __device__ __forceinline__ uint64_t mod_small(uint64_t x, uint32_t p, uint64_t i
     return r;
 }
 
-// Odd primes below 2^20 from the device table (bits of odd numbers below
-// 2^20 are the first 2^14 words), in order, with their reciprocals.  One
-// workgroup of 1024 threads, 16 words each.
+// Odd primes below 2^22 from the device table (bits of odd numbers below
+// 2^22 are the first 2^16 words), in order, with floor((2^64 - 1) / p).  One
+// workgroup of 1024 threads, 64 words each; runs once per device.
 __global__ void __launch_bounds__(1024) range_primes_kernel(const uint32_t *__restrict__ table,
                                                             uint32_t *__restrict__ primes,
                                                             uint64_t *__restrict__ inv,
                                                             uint32_t *__restrict__ count)
 {
+    constexpr int WORDS = (1 << 16) / 1024;
     __shared__ uint32_t wsum[16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int w0 = tid * 16;
+    const int w0 = tid * WORDS;
     uint32_t c = 0;
-    for (int k = 0; k < 16; ++k)
+    for (int k = 0; k < WORDS; ++k)
         c += __popc(table[w0 + k]);
     uint32_t incl = c;
 #pragma unroll
@@ -71,52 +98,58 @@ __global__ void __launch_bounds__(1024) range_primes_kernel(const uint32_t *__re
     uint32_t pos = incl - c;
     for (int w = 0; w < wave; ++w)
         pos += wsum[w];
-    for (int k = 0; k < 16; ++k) {
-        const uint32_t word = table[w0 + k];
-        for (int b = 0; b < 32; ++b) {
-            if ((word >> b) & 1) {
-                const uint32_t p = 2u * (32u * (uint32_t)(w0 + k) + (uint32_t)b) + 1u;
-                primes[pos] = p;
-                inv[pos] = ~(uint64_t)0 / p;
-                ++pos;
-            }
+    for (int k = 0; k < WORDS; ++k) {
+        uint32_t word = table[w0 + k];
+        while (word) {
+            const int b = __ffs(word) - 1;
+            word &= word - 1;
+            const uint32_t p = 2u * (32u * (uint32_t)(w0 + k) + (uint32_t)b) + 1u;
+            primes[pos] = p;
+            inv[pos] = ~(uint64_t)0 / p;
+            ++pos;
         }
     }
     if (tid == blockDim.x - 1)
         *count = pos;
 }
 
-// out[i] = primality of lo + i for lo + len <= 2^32: one table bit per odd number.
-__global__ void range_table_kernel(uint64_t lo, uint8_t *__restrict__ out, uint64_t len,
-                                   const uint32_t *__restrict__ table)
+// out[i] = primality of lo + i for lo + len <= 2^32: one table bit per odd
+// number.  Thread t writes the 64 numbers lo + 64t .. lo + 64t + 63, whose 32
+// odd members are 32 consecutive table bits.
+__global__ void __launch_bounds__(256) range_table_kernel(uint64_t lo, uint8_t *__restrict__ out,
+                                                         uint64_t len,
+                                                         const uint32_t *__restrict__ table)
 {
-    const uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16;
+    const uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 64;
     if (i0 >= len)
         return;
-    const uint64_t i1 = i0 + 16 < len ? i0 + 16 : len;
-    uint8_t r[16];
+    const uint64_t v0 = lo + i0;          // < 2^32
+    const uint64_t b = (v0 | 1) >> 1;     // table bit of the first odd number
+    const uint64_t w = b >> 5;
+    const uint64_t pair = (uint64_t)table[w] |
+                          (w + 1 < TABLE_WORDS ? (uint64_t)table[w + 1] << 32 : 0ull);
+    const uint32_t bits = (uint32_t)(pair >> (b & 31));
+    const int odd_at = (int)(~v0 & 1) * 8;  // odd numbers at bytes 1, 3, .. (v0 even) or 0, 2, ..
+    uint64_t q[8];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const uint64_t v = lo + i0 + j;
-        uint8_t b = 0;
-        if (i0 + j < i1) {
-            if (v == 2)
-                b = 1;
-            else if ((v & 1) && v > 1)
-                b = (uint8_t)((table[v >> 6] >> ((v >> 1) & 31)) & 1u);
-        }
-        r[j] = b;
+    for (int k = 0; k < 8; ++k)
+        q[k] = spread4((bits >> (4 * k)) & 0xfu) << odd_at;
+    if (v0 <= 2 && v0 + 64 > 2) {
+        const int at = (int)(2 - v0);  // 2 is prime; its table bit is that of 1
+        q[at >> 3] |= 1ull << (8 * (at & 7));
     }
-    if (i1 - i0 == 16) {
-        typedef uint32_t u32u __attribute__((aligned(1)));
+    if (i0 + 64 <= len) {
+        typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(1)));
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            *reinterpret_cast<u32u *>(out + i0 + 4 * q) =
-                (uint32_t)r[4 * q] | ((uint32_t)r[4 * q + 1] << 8) |
-                ((uint32_t)r[4 * q + 2] << 16) | ((uint32_t)r[4 * q + 3] << 24);
+        for (int k = 0; k < 4; ++k) {
+            u64x2 v;
+            v.x = q[2 * k];
+            v.y = q[2 * k + 1];
+            *reinterpret_cast<u64x2 *>(out + i0 + 16 * k) = v;
+        }
     } else {
-        for (uint64_t i = i0; i < i1; ++i)
-            out[i] = r[i - i0];
+        for (uint64_t i = i0; i < len; ++i)
+            out[i] = (uint8_t)(q[(i - i0) >> 3] >> (8 * ((i - i0) & 7)));
     }
 }
 
@@ -146,7 +179,8 @@ __device__ __forceinline__ uint64_t isqrt64(uint64_t x)
 
 __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
 {
-    __shared__ uint32_t bits[(RANGE_SEG + 64) / 64 + 1];  // odd numbers of the segment
+    constexpr int MAX_WORDS = (int)(RANGE_SEG / 64);  // 2^13 words of odd-number bits
+    __shared__ uint32_t bits[MAX_WORDS + 1];          // + one zero word past the end
     __shared__ uint32_t wsum[RANGE_THREADS / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nwaves = blockDim.x >> 6;
@@ -160,17 +194,42 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
     }
     const uint64_t s_lo = a.lo + r0;          // first number of the segment
     const uint64_t s_last = a.lo + r1 - 1;    // last number (no overflow: <= 2^64 - 1)
-    const uint64_t o0 = s_lo | 1;             // first odd number
+    // first odd number; s_lo | 1 cannot wrap (s_lo = 2^64 - 1 is already odd)
+    const uint64_t o0 = s_lo | 1;
     const uint32_t nbits = o0 > s_last ? 0u : (uint32_t)((s_last - o0) / 2 + 1);
-    // (o0 <= s_last whenever the segment holds an odd number; o0 = s_lo | 1
-    // cannot wrap because s_lo <= s_last <= 2^64 - 1 and a wrap needs s_lo = 2^64 - 1,
-    // which is odd)
     const uint32_t nwords = (nbits + 31) / 32;
-    for (uint32_t w = tid; w < nwords; w += blockDim.x)
-        bits[w] = w + 1 < nwords || (nbits & 31) == 0 ? 0xffffffffu : (1u << (nbits & 31)) - 1u;
+
+    // pre-sieve: bit j of word w (j = 32w + i) is o0 + 2j, which p divides
+    // iff j = jp (mod p) with jp = -o0 / 2 mod p
+    {
+        uint32_t jp[PRESIEVED], dp[PRESIEVED], rp[PRESIEVED];
+        const uint32_t per = (nwords + blockDim.x - 1) / blockDim.x;
+        const uint32_t ws = tid * per;
+#pragma unroll
+        for (int q = 0; q < PRESIEVED; ++q) {
+            const uint32_t p = SMALL_PRIMES[q];
+            jp[q] = (uint32_t)(((p - o0 % p) % p) * ((p + 1) / 2) % p);
+            dp[q] = (p - 32u % p) % p;  // position shift from one word to the next
+            rp[q] = (jp[q] + p - (32u * ws) % p) % p;
+        }
+        for (uint32_t w = ws; w < ws + per && w < nwords; ++w) {
+            uint32_t word = w + 1 < nwords || (nbits & 31) == 0 ? 0xffffffffu
+                                                                 : (1u << (nbits & 31)) - 1u;
+#pragma unroll
+            for (int q = 0; q < PRESIEVED; ++q) {
+                word &= ~(period_mask(SMALL_PRIMES[q]) << rp[q]);
+                rp[q] += dp[q];
+                if (rp[q] >= SMALL_PRIMES[q])
+                    rp[q] -= SMALL_PRIMES[q];
+            }
+            bits[w] = word;
+        }
+        if (tid == 0)
+            bits[nwords] = 0;
+    }
     __syncthreads();
     const uint64_t root = isqrt64(s_last);
-    // primes up to min(2^20, root); the list is sorted, so stop at the first above
+    // primes up to min(2^22, root); the list is sorted, so stop at the first above
     uint32_t np = a.nprimes;
     {
         uint32_t lo_i = 0, hi_i = np;  // first index with prime > root
@@ -183,13 +242,13 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
         }
         np = lo_i;
     }
-    // every prime up to the root is in the list when the root is below 2^20
-    const bool complete = root < ((uint64_t)1 << 20);
+    // every prime up to the root is in the list when the root is below 2^22
+    const bool complete = root < ((uint64_t)1 << 22);
     // first bit index of the odd multiples of p at or above max(o0, p^2), or
     // "none" (all offsets are taken from o0, so nothing wraps near 2^64)
     const uint64_t span = s_last - o0;  // valid only when nbits > 0
     auto first_bit = [&](uint32_t k, uint32_t p) -> uint64_t {
-        const uint64_t pp = (uint64_t)p * p;  // < 2^40, odd
+        const uint64_t pp = (uint64_t)p * p;  // < 2^44, odd
         uint64_t off;
         if (pp >= o0) {
             off = pp - o0;
@@ -201,7 +260,7 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
         }
         return off > span ? ~(uint64_t)0 : off >> 1;
     };
-    // small primes: one wavefront per prime
+    // primes 37 .. 8191: one wavefront per prime
     uint32_t k_split;
     {
         uint32_t lo_i = 0, hi_i = np;  // first index with prime >= WAVE_PRIME_LIMIT
@@ -214,7 +273,7 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
         }
         k_split = lo_i;
     }
-    for (uint32_t k = wave; k < k_split; k += nwaves) {
+    for (uint32_t k = PRESIEVED + wave; k < k_split; k += nwaves) {
         const uint32_t p = a.primes[k];
         const uint64_t j0 = first_bit(k, p);
         if (j0 >= nbits)
@@ -229,29 +288,42 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
             atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
     }
     __syncthreads();
-    // outputs: 8 consecutive numbers per thread per pass; survivors of an
-    // incomplete sieve go to the Miller-Rabin kernels (out = 0 until then)
+    // outputs: 32 consecutive numbers per thread per pass (16 odd ones: bits
+    // 16m .. 16m + 15, m = the thread's group index in the segment); the
+    // survivors of an incomplete sieve go to the Miller-Rabin kernels (their
+    // bytes are 0 until then)
     Survivor *region = a.surv + r0;
+    const int odd_at = (int)(~s_lo & 1) * 8;
     uint32_t filled = 0;
-    for (uint64_t p0 = r0; p0 < r1; p0 += 8ull * blockDim.x) {
-        const uint64_t i0 = p0 + 8ull * tid;
-        uint8_t r[8];
-        uint32_t cnt = 0;
+    for (uint64_t p0 = r0; p0 < r1; p0 += 32ull * blockDim.x) {
+        const uint64_t i0 = p0 + 32ull * tid;
+        const uint32_t m = (uint32_t)((i0 - r0) >> 5);
+        uint32_t b16 = 0;
+        if (i0 < r1)
+            b16 = (bits[m >> 1] >> (16 * (m & 1))) & 0xffffu;
+        const uint32_t cnt = complete ? 0u : (uint32_t)__popc(b16);
+        if (i0 < r1) {
+            const uint32_t shown = complete ? b16 : 0u;
+            uint64_t q[4];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            r[j] = 0;
-            const uint64_t i = i0 + j;
-            if (i < r1) {
-                const uint64_t v = a.lo + i;
-                if (v & 1) {
-                    const uint64_t b = (v - o0) >> 1;
-                    const bool sv = (bits[b >> 5] >> (b & 31)) & 1u;
-                    if (sv && complete)
-                        r[j] = 1;
-                    cnt += sv && !complete;
-                }
+            for (int k = 0; k < 4; ++k)
+                q[k] = spread4((shown >> (4 * k)) & 0xfu) << odd_at;
+            if (i0 + 32 <= r1) {
+                typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(1)));
+                u64x2 v;
+                v.x = q[0];
+                v.y = q[1];
+                *reinterpret_cast<u64x2 *>(a.out + i0) = v;
+                v.x = q[2];
+                v.y = q[3];
+                *reinterpret_cast<u64x2 *>(a.out + i0 + 16) = v;
+            } else {
+                for (uint64_t i = i0; i < r1; ++i)
+                    a.out[i] = (uint8_t)(q[(i - i0) >> 3] >> (8 * ((i - i0) & 7)));
             }
         }
+        if (complete)
+            continue;  // uniform over the workgroup
         // block-wide exclusive scan of cnt
         uint32_t incl = cnt;
 #pragma unroll
@@ -268,22 +340,15 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
             pos += w < wave ? wsum[w] : 0u;
             all += wsum[w];
         }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const uint64_t i = i0 + j;
-            if (i < r1) {
-                a.out[i] = r[j];
-                const uint64_t v = a.lo + i;
-                if (!complete && (v & 1)) {
-                    const uint64_t b = (v - o0) >> 1;
-                    if ((bits[b >> 5] >> (b & 31)) & 1u) {
-                        Survivor s;
-                        s.n = v;
-                        s.out = a.out + i;
-                        region[pos++] = s;
-                    }
-                }
-            }
+        uint32_t rest = b16;
+        const uint64_t first_odd = (a.lo + i0) | 1;
+        while (rest) {
+            const int t = __ffs(rest) - 1;
+            rest &= rest - 1;
+            Survivor sv;
+            sv.n = first_odd + 2ull * (uint64_t)t;
+            sv.out = a.out + (sv.n - a.lo);
+            region[pos++] = sv;
         }
         filled += all;
         __syncthreads();  // wsum is rewritten next pass
@@ -304,7 +369,7 @@ hipError_t launch_range_primes(DeviceState &ds, hipStream_t s)
 hipError_t launch_range_table(uint64_t lo, uint8_t *out, uint64_t len, const DeviceState &ds,
                               hipStream_t s)
 {
-    const uint64_t threads = (len + 15) / 16;
+    const uint64_t threads = (len + 63) / 64;
     const uint64_t blocks = (threads + 255) / 256;
     if (blocks > 0x7fffffffull)
         return hipErrorInvalidValue;
