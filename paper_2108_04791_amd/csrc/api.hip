@@ -111,6 +111,8 @@ void free_ws(Workspace &ws)
         (void)hipFree(ws.surv);
     if (ws.cand)
         (void)hipFree(ws.cand);
+    if (ws.prep)
+        (void)hipFree(ws.prep);
     if (ws.counts)
         (void)hipFree(ws.counts);
     ws = Workspace();
@@ -136,6 +138,8 @@ int ensure_ws(Workspace &ws, size_t cap, hipStream_t stream)
     hipError_t e = hipMalloc(&ws.surv, (newcap + 64 * (size_t)MAX_GRID) * sizeof(Survivor));
     if (e == hipSuccess)
         e = hipMalloc(&ws.cand, (newcap + (size_t)MAX_GRID) * sizeof(Survivor));
+    if (e == hipSuccess)
+        e = hipMalloc(&ws.prep, (newcap + (size_t)MAX_GRID) * sizeof(MontPrep));
     if (e == hipSuccess)
         e = hipMalloc(&ws.counts, 2 * (size_t)MAX_GRID * sizeof(uint32_t));
     if (e != hipSuccess) {
@@ -188,6 +192,7 @@ void make_args(const DeviceState &ds, const Workspace &ws, const Tuning &t, size
     ma.counts_c = ws.counts;
     ma.grid1 = grid1;
     ma.cand = ws.cand;
+    ma.prep = t.rest_test > 0 ? nullptr : ws.prep;
     ma.counts1 = ws.counts + MAX_GRID;
 }
 
@@ -709,7 +714,8 @@ size_t isp_workspace_bytes(size_t len)
     size_t cap = 1 << 16;
     while (cap < std::min(len, PLAIN_PIECE))
         cap <<= 1;
-    return (2 * cap + 65 * (size_t)MAX_GRID) * sizeof(Survivor) + 2 * MAX_GRID * sizeof(uint32_t);
+    return (2 * cap + 65 * (size_t)MAX_GRID) * sizeof(Survivor) +
+           (cap + (size_t)MAX_GRID) * sizeof(MontPrep) + 2 * MAX_GRID * sizeof(uint32_t);
 }
 
 int isp_last_device_error(void) { return g_last_err.load(); }

@@ -68,6 +68,14 @@ struct ClassifyArgs {
     uint32_t *counts;       // [grid] survivors per region
 };
 
+// Montgomery constants of one base-2 passer, computed once by the base-2
+// kernel and read by every one of its later tasks.
+struct MontPrep {
+    uint64_t ninv;  // n^-1 mod 2^64
+    uint64_t one;   // 2^64 mod n
+    uint64_t r2;    // 2^128 mod n
+};
+
 struct MrArgs {
     uint64_t total;              // elements of the call ...
     const uint64_t *total_dev;   // ... or where to read them (batched)
@@ -76,6 +84,8 @@ struct MrArgs {
     const uint32_t *counts_c;    // [grid_c]
     uint32_t grid1;              // base-2 grid
     Survivor *cand;              // base-2 passer regions of cand_chunk() entries
+    MontPrep *prep;              // the passers' constants, indexed like cand (or null:
+                                 // not needed by the Lucas test)
     uint32_t *counts1;           // [grid1]
 };
 
@@ -111,6 +121,7 @@ struct DeviceState {
 struct Workspace {
     Survivor *surv = nullptr;   // classify regions (cap + 64 * MAX_GRID entries)
     Survivor *cand = nullptr;   // base-2 passer regions (cap + MAX_GRID entries)
+    MontPrep *prep = nullptr;   // constants of the passers, indexed like cand
     uint32_t *counts = nullptr; // 2 * MAX_GRID
     size_t cap = 0;             // elements per call this workspace serves
 };

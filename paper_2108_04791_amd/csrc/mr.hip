@@ -156,16 +156,31 @@ __device__ __forceinline__ bool sprp_window(uint64_t am, uint64_t d, int s, cons
     return false;
 }
 
-// Strong test of odd n >= 2^32 to one base a < 2^32.
+// Strong test of odd n >= 2^32 to one base a < 2^32, given n's Montgomery
+// constants.
 template <int W>
-__device__ __forceinline__ bool sprp_one_base(uint64_t n, uint32_t a, uint64_t *tbl)
+__device__ __forceinline__ bool sprp_one_base(uint64_t n, const MontPrep &pr, uint32_t a,
+                                              uint64_t *tbl)
 {
-    const int L = 64 - __clzll(n);
-    const MontCtx c = make_ctx(n, L);
-    const uint64_t r2 = r2_mod_n(c);
+    MontCtx c;
+    c.n = n;
+    c.ninv = pr.ninv;
+    c.one = pr.one;
+    c.mone = n - pr.one;
     const uint64_t e = n - 1;
     const int s = __ffsll((long long)e) - 1;
-    return sprp_window<W>(to_mont(a, r2, c), e >> s, s, c, tbl);
+    return sprp_window<W>(to_mont(a, pr.r2, c), e >> s, s, c, tbl);
+}
+
+// The Montgomery constants of odd n >= 2^32.
+__device__ __forceinline__ MontPrep mont_prep(uint64_t n)
+{
+    const MontCtx c = make_ctx(n, 64 - __clzll(n));
+    MontPrep pr;
+    pr.ninv = c.ninv;
+    pr.one = c.one;
+    pr.r2 = r2_mod_n(c);
+    return pr;
 }
 
 // ------------------------------------------------------------------ Lucas
@@ -414,8 +429,16 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
         }
     }
     __syncthreads();
+    // the Montgomery constants of this workgroup's passers, once each, for
+    // all the later tasks of each (dense over the workgroup's threads)
+    const uint32_t npass = fill;
+    if (a.prep) {
+        MontPrep *prep = a.prep + (uint64_t)g * chunk_1;
+        for (uint32_t i = threadIdx.x; i < npass; i += blockDim.x)
+            prep[i] = mont_prep(region[i].n);
+    }
     if (threadIdx.x == 0)
-        a.counts1[g] = fill;
+        a.counts1[g] = npass;
 }
 
 template <int W>
@@ -457,8 +480,10 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase2_kernel(MrArgs a)
         const uint32_t j = (uint32_t)(t / 6);
         const uint32_t b = (uint32_t)(t - 6ull * j);
         k = find_region(pre, a.grid1, k, j);
-        const Survivor sv = a.cand[(uint64_t)k * chunk_1 + (j - pre[k])];
-        if (!sprp_one_base<W>(sv.n, BASES[b], tbl) && real)
+        const uint64_t slot = (uint64_t)k * chunk_1 + (j - pre[k]);
+        const Survivor sv = a.cand[slot];
+        const MontPrep pr = a.prep[slot];
+        if (!sprp_one_base<W>(sv.n, pr, BASES[b], tbl) && real)
             *sv.out = 0;  // composite; the base-2 round had written 1
     }
 }
@@ -498,15 +523,17 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) lucas_kernel(MrArgs a)
         const bool real = j0 + lane < s1;
         const uint32_t j = real ? j0 + lane : j0;
         k = find_region(pre, a.grid1, k, j);
-        const Survivor sv = a.cand[(uint64_t)k * chunk_1 + (j - pre[k])];
+        const uint64_t slot = (uint64_t)k * chunk_1 + (j - pre[k]);
+        const Survivor sv = a.cand[slot];
         int v = strong_lucas(sv.n);
         const bool need = v < 0;
         if (__ballot(need) != 0) {
             // the Miller-Rabin bases run on every lane (they need the whole
             // wavefront); only the lanes without a Lucas verdict use them
+            const MontPrep pr = mont_prep(sv.n);
             bool w = true;
             for (int b = 0; b < 6; ++b)
-                w = sprp_one_base<W>(sv.n, BASES[b], tbl) && w;
+                w = sprp_one_base<W>(sv.n, pr, BASES[b], tbl) && w;
             if (need)
                 v = w ? 1 : 0;
         }
