@@ -99,13 +99,25 @@ __device__ __forceinline__ bool sprp_base2(uint64_t n)
     // bits Lmax - 2 .. smax + 1 from the top of `rest` (bit t of n - 1 at
     // t + 65 - Lmax)
     uint64_t rest = e << (65 - Lmax);
-    for (int t = Lmax - 2; t > smax; --t) {
-        // the top bit as an opaque value, so the select below tests it
-        // rather than the old `rest` (which would keep a copy of it alive)
-        uint32_t bit;
-        asm("v_lshrrev_b32 %0, 31, %1" : "=v"(bit) : "v"(hi32(rest)));
-        rest <<= 1;
-        step(bit);
+    if (Lmax <= 62) {
+        // n < 2^62: x may stay in [0, 2n) between squarings (a product of
+        // two such values is below 4 n^2 < n 2^64, which the Montgomery
+        // product accepts, and its result is reduced), so the doubling is a
+        // plain shift
+        for (int t = Lmax - 2; t > smax; --t) {
+            const uint32_t bit = hi32(rest) >> 31;
+            rest <<= 1;
+            x = montsqr(x, n, c.ninv) << bit;
+        }
+    } else {
+        for (int t = Lmax - 2; t > smax; --t) {
+            // the top bit as an opaque value, so the select below tests it
+            // rather than the old `rest` (which would keep a copy of it alive)
+            uint32_t bit;
+            asm("v_lshrrev_b32 %0, 31, %1" : "=v"(bit) : "v"(hi32(rest)));
+            rest <<= 1;
+            step(bit);
+        }
     }
     // bits min(smax, Lmax - 2) .. 1, comparing
     bool pass = false;
