@@ -152,6 +152,23 @@ def test_c2_full(isp):
     assert 0.02 < got.mean() < 0.05
 
 
+@pytest.mark.parametrize("bits", [33, 48, 59, 60, 61, 62, 63, 64])
+def test_one_bit_length_per_array(isp, bits):
+    """Arrays of a single bit length (the Miller-Rabin loops run one length per
+    wavefront; below 2^62 the base-2 doubling is a plain shift), with base-2
+    strong pseudoprimes of that length mixed in."""
+    rng = np.random.default_rng(bits)
+    lo = 1 << (bits - 1)
+    a = (rng.integers(0, lo, 40000, dtype=np.uint64) + np.uint64(lo)) | np.uint64(1)
+    ch = W.chernick_values()
+    top = (1 << bits) - 1  # the largest value of this bit length
+    ch = ch[(ch >= np.uint64(lo)) & (ch <= np.uint64(top))]
+    a = np.concatenate([a, ch, np.array([lo + 1, top], dtype=np.uint64)])
+    rng.shuffle(a)
+    got = gpu_isprime(isp, a)
+    assert_same(a, got, expect(a, use_table=False), "bit length %d" % bits)
+
+
 def test_c3_full(isp, oracle_table):
     a = W.c3_mixed()
     got = gpu_isprime(isp, a)
