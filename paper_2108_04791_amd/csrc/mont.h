@@ -63,23 +63,24 @@ __device__ __forceinline__ uint64_t mad_carry(uint32_t a, uint32_t b, uint64_t c
     return r;
 }
 
-// a * b * 2^-64 mod n, for a*b < n*2^64, on 32-bit halves (x = x1 2^32 + x0).
+// T = a*b (as hi:lo) and h = floor(m n / 2^64) with m = lo * n^-1 mod 2^64,
+// on 32-bit halves (x = x1 2^32 + x0).
 //
 // T = a*b: with c = floor(a0 b0 / 2^32), M1 = a1 b0 + c < 2^64 and
 // M2 = a0 b1 + M1 < 2^65 (carry k), T = (a1 b1 + floor(M2 / 2^32) + k 2^32) 2^64
 // + (M2 mod 2^32) 2^32 + (a0 b0 mod 2^32).  m = (T mod 2^64) ninv mod 2^64
 // needs only the low product and two low-half cross products.  floor(m n /
 // 2^64) is assembled the same way from m0 n0, m1 n0, m0 n1 and m1 n1.  Every
-// 32x32+64 step is one v_mad_u64_u32; the whole product is 22 VALU
-// instructions plus one compare that the compiler adds for the final select.
-__device__ __forceinline__ uint64_t montmul(uint64_t a, uint64_t b, uint64_t n, uint64_t ninv)
+// 32x32+64 step is one v_mad_u64_u32: 17 VALU instructions.
+__device__ __forceinline__ void redc_parts(uint64_t a, uint64_t b, uint64_t n, uint64_t ninv,
+                                           uint64_t &hi, uint64_t &h)
 {
     const uint32_t a0 = lo32(a), a1 = hi32(a), b0 = lo32(b), b1 = hi32(b);
     const uint32_t t0 = a0 * b0;
     const uint64_t M1 = (uint64_t)a1 * b0 + __umulhi(a0, b0);
     uint32_t k;
     const uint64_t M2 = mad_carry(a0, b1, M1, k);
-    const uint64_t hi = (uint64_t)a1 * b1 + pair32(hi32(M2), k);
+    hi = (uint64_t)a1 * b1 + pair32(hi32(M2), k);
     const uint32_t t1 = lo32(M2);
     const uint32_t n0 = lo32(n), n1 = hi32(n), i0 = lo32(ninv), i1 = hi32(ninv);
     const uint64_t X = (uint64_t)t0 * i0;
@@ -88,9 +89,30 @@ __device__ __forceinline__ uint64_t montmul(uint64_t a, uint64_t b, uint64_t n, 
     const uint64_t Z = (uint64_t)m1 * n0 + __umulhi(m0, n0);
     uint32_t k2;
     const uint64_t Z2 = mad_carry(m0, n1, Z, k2);
-    const uint64_t h = (uint64_t)m1 * n1 + pair32(hi32(Z2), k2);
+    h = (uint64_t)m1 * n1 + pair32(hi32(Z2), k2);
+}
+
+// a * b * 2^-64 mod n, for a*b < n*2^64.  Because m n = T (mod 2^64), the low
+// halves cancel exactly and hi - h lies in (-n, n); one conditional add of n
+// reduces it: 22 VALU instructions plus one compare that the compiler adds
+// for the final select.
+__device__ __forceinline__ uint64_t montmul(uint64_t a, uint64_t b, uint64_t n, uint64_t ninv)
+{
+    uint64_t hi, h;
+    redc_parts(a, b, n, ninv, hi, h);
     const uint64_t t = hi - h;
     return hi < h ? t + n : t;
+}
+
+// The same product for n < 2^62 and a, b < 2n, returned in (0, 2n) without
+// the final select: a*b < 4 n^2 < n 2^64, so hi < n and (hi + n) - h lies in
+// (0, 2n) with no overflow.  20 VALU instructions.
+__device__ __forceinline__ uint64_t montmul_lazy(uint64_t a, uint64_t b, uint64_t n,
+                                                 uint64_t ninv)
+{
+    uint64_t hi, h;
+    redc_parts(a, b, n, ninv, hi, h);
+    return (hi + n) - h;
 }
 
 __device__ __forceinline__ uint64_t montsqr(uint64_t a, uint64_t n, uint64_t ninv)

@@ -132,17 +132,22 @@ __device__ __forceinline__ bool sprp_base2(uint64_t n)
 // a^d by a fixed window of W bits: the lane's table a^0 .. a^(2^W - 1) sits
 // in LDS, column threadIdx.x of tbl[2^W][blockDim] (each lane reads only
 // its own column, so no barrier is needed and the rows are bank-aligned).
-template <int W>
+// LAZY (every n of the wavefront below 2^62): products stay in (0, 2n) and
+// are reduced once before the comparisons.
+template <int W, bool LAZY>
 __device__ __forceinline__ bool sprp_window(uint64_t am, uint64_t d, int s, const MontCtx &c,
                                             uint64_t *tbl)
 {
     constexpr int TS = 1 << W;
+    auto mul = [&](uint64_t x, uint64_t y) {
+        return LAZY ? montmul_lazy(x, y, c.n, c.ninv) : montmul(x, y, c.n, c.ninv);
+    };
     const unsigned col = threadIdx.x, stride = blockDim.x;
     uint64_t p = c.one;
     tbl[col] = p;
 #pragma unroll
     for (int k = 1; k < TS; ++k) {
-        p = k == 1 ? am : montmul(p, am, c.n, c.ninv);
+        p = k == 1 ? am : mul(p, am);
         tbl[k * stride + col] = p;
     }
     // windows from the wavefront's longest d down: a lane with a shorter d
@@ -155,9 +160,11 @@ __device__ __forceinline__ bool sprp_window(uint64_t am, uint64_t d, int s, cons
     for (pos -= W; pos >= 0; pos -= W) {
 #pragma unroll
         for (int k = 0; k < W; ++k)
-            x = montsqr(x, c.n, c.ninv);
-        x = montmul(x, tbl[((unsigned)(d >> pos) & (TS - 1)) * stride + col], c.n, c.ninv);
+            x = mul(x, x);
+        x = mul(x, tbl[((unsigned)(d >> pos) & (TS - 1)) * stride + col]);
     }
+    if (LAZY && x >= c.n)
+        x -= c.n;
     if (x == c.one || x == c.mone)
         return true;
     for (int r = 1; r < s; ++r) {
@@ -169,7 +176,7 @@ __device__ __forceinline__ bool sprp_window(uint64_t am, uint64_t d, int s, cons
 }
 
 // Strong test of odd n >= 2^32 to one base a < 2^32, given n's Montgomery
-// constants.
+// constants.  Called with all 64 lanes of the wavefront active.
 template <int W>
 __device__ __forceinline__ bool sprp_one_base(uint64_t n, const MontPrep &pr, uint32_t a,
                                               uint64_t *tbl)
@@ -181,7 +188,10 @@ __device__ __forceinline__ bool sprp_one_base(uint64_t n, const MontPrep &pr, ui
     c.mone = n - pr.one;
     const uint64_t e = n - 1;
     const int s = __ffsll((long long)e) - 1;
-    return sprp_window<W>(to_mont(a, pr.r2, c), e >> s, s, c, tbl);
+    const uint64_t am = to_mont(a, pr.r2, c);
+    if (wave_max(64 - __clzll(n)) <= 62)
+        return sprp_window<W, true>(am, e >> s, s, c, tbl);
+    return sprp_window<W, false>(am, e >> s, s, c, tbl);
 }
 
 // The Montgomery constants of odd n >= 2^32.
