@@ -22,10 +22,10 @@
 // with a precomputed floor((2^64 - 1) / p) (one 64-bit multiply-high, no
 // division).
 //
-// Output: 32 consecutive numbers per thread per pass.  Their 16 odd members
-// are 16 consecutive bits; each group of 4 bits becomes 8 output bytes by one
-// multiply that spreads bit i to byte 2i (or 2i + 1), so a thread writes its
-// 32 bytes with two 16-byte stores.
+// Output: 16 consecutive numbers per thread per pass, consecutive threads on
+// consecutive 16-byte pieces.  Their 8 odd members are 8 consecutive bits;
+// each group of 4 bits becomes 8 output bytes by one multiply that spreads
+// bit i to byte 2i (or 2i + 1), and the piece goes out as one 16-byte store.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -114,42 +114,46 @@ __global__ void __launch_bounds__(1024) range_primes_kernel(const uint32_t *__re
 }
 
 // out[i] = primality of lo + i for lo + len <= 2^32: one table bit per odd
-// number.  Thread t writes the 64 numbers lo + 64t .. lo + 64t + 63, whose 32
-// odd members are 32 consecutive table bits.
+// number.  A wavefront writes 4096 consecutive bytes in four stores of 1 KiB:
+// in store k, lane l writes the 16 bytes of numbers 1024k + 16l .. + 15 of
+// the wavefront's block, whose 8 odd members are 8 consecutive table bits.
 __global__ void __launch_bounds__(256) range_table_kernel(uint64_t lo, uint8_t *__restrict__ out,
                                                          uint64_t len,
                                                          const uint32_t *__restrict__ table)
 {
-    const uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 64;
-    if (i0 >= len)
-        return;
-    const uint64_t v0 = lo + i0;          // < 2^32
-    const uint64_t b = (v0 | 1) >> 1;     // table bit of the first odd number
-    const uint64_t w = b >> 5;
-    const uint64_t pair = (uint64_t)table[w] |
-                          (w + 1 < TABLE_WORDS ? (uint64_t)table[w + 1] << 32 : 0ull);
-    const uint32_t bits = (uint32_t)(pair >> (b & 31));
-    const int odd_at = (int)(~v0 & 1) * 8;  // odd numbers at bytes 1, 3, .. (v0 even) or 0, 2, ..
-    uint64_t q[8];
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t block0 = wave * 4096;
+    if (block0 >= len)
+        return;  // uniform over the wavefront
+    const int odd_at = (int)(~lo & 1) * 8;  // odd numbers at bytes 1, 3, .. (lo even) or 0, 2, ..
+    typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(1)));
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-        q[k] = spread4((bits >> (4 * k)) & 0xfu) << odd_at;
-    if (v0 <= 2 && v0 + 64 > 2) {
-        const int at = (int)(2 - v0);  // 2 is prime; its table bit is that of 1
-        q[at >> 3] |= 1ull << (8 * (at & 7));
-    }
-    if (i0 + 64 <= len) {
-        typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(1)));
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            u64x2 v;
-            v.x = q[2 * k];
-            v.y = q[2 * k + 1];
-            *reinterpret_cast<u64x2 *>(out + i0 + 16 * k) = v;
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t i0 = block0 + 1024 * k + 16 * lane;
+        if (i0 >= len)
+            break;
+        const uint64_t v0 = lo + i0;          // < 2^32
+        const uint64_t b = (v0 | 1) >> 1;     // table bit of the first odd number
+        const uint64_t w = b >> 5;
+        const uint64_t pair = (uint64_t)table[w] |
+                              (w + 1 < TABLE_WORDS ? (uint64_t)table[w + 1] << 32 : 0ull);
+        const uint32_t bits = (uint32_t)(pair >> (b & 31));
+        u64x2 q;
+        q.x = spread4(bits & 0xfu) << odd_at;
+        q.y = spread4((bits >> 4) & 0xfu) << odd_at;
+        if (v0 <= 2 && v0 + 16 > 2) {
+            const int at = (int)(2 - v0);  // 2 is prime; its table bit is that of 1
+            q.x |= 1ull << (8 * at);
         }
-    } else {
-        for (uint64_t i = i0; i < len; ++i)
-            out[i] = (uint8_t)(q[(i - i0) >> 3] >> (8 * ((i - i0) & 7)));
+        if (i0 + 16 <= len) {
+            *reinterpret_cast<u64x2 *>(out + i0) = q;
+        } else {
+            for (uint64_t i = i0; i < len; ++i) {
+                const uint64_t word = (i - i0) < 8 ? q.x : q.y;
+                out[i] = (uint8_t)(word >> (8 * ((i - i0) & 7)));
+            }
+        }
     }
 }
 
@@ -288,38 +292,33 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
             atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
     }
     __syncthreads();
-    // outputs: 32 consecutive numbers per thread per pass (16 odd ones: bits
-    // 16m .. 16m + 15, m = the thread's group index in the segment); the
-    // survivors of an incomplete sieve go to the Miller-Rabin kernels (their
-    // bytes are 0 until then)
+    // outputs: 16 consecutive numbers per thread per pass, consecutive threads
+    // on consecutive 16-byte pieces (8 odd numbers: bits 8m .. 8m + 7, m =
+    // the piece's index in the segment); the survivors of an incomplete sieve
+    // go to the Miller-Rabin kernels (their bytes are 0 until then)
     Survivor *region = a.surv + r0;
     const int odd_at = (int)(~s_lo & 1) * 8;
     uint32_t filled = 0;
-    for (uint64_t p0 = r0; p0 < r1; p0 += 32ull * blockDim.x) {
-        const uint64_t i0 = p0 + 32ull * tid;
-        const uint32_t m = (uint32_t)((i0 - r0) >> 5);
-        uint32_t b16 = 0;
+    typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(1)));
+    for (uint64_t p0 = r0; p0 < r1; p0 += 16ull * blockDim.x) {
+        const uint64_t i0 = p0 + 16ull * tid;
+        const uint32_t m = (uint32_t)((i0 - r0) >> 4);
+        uint32_t b8 = 0;
         if (i0 < r1)
-            b16 = (bits[m >> 1] >> (16 * (m & 1))) & 0xffffu;
-        const uint32_t cnt = complete ? 0u : (uint32_t)__popc(b16);
+            b8 = (bits[m >> 2] >> (8 * (m & 3))) & 0xffu;
+        const uint32_t cnt = complete ? 0u : (uint32_t)__popc(b8);
         if (i0 < r1) {
-            const uint32_t shown = complete ? b16 : 0u;
-            uint64_t q[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                q[k] = spread4((shown >> (4 * k)) & 0xfu) << odd_at;
-            if (i0 + 32 <= r1) {
-                typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(1)));
-                u64x2 v;
-                v.x = q[0];
-                v.y = q[1];
-                *reinterpret_cast<u64x2 *>(a.out + i0) = v;
-                v.x = q[2];
-                v.y = q[3];
-                *reinterpret_cast<u64x2 *>(a.out + i0 + 16) = v;
+            const uint32_t shown = complete ? b8 : 0u;
+            u64x2 q;
+            q.x = spread4(shown & 0xfu) << odd_at;
+            q.y = spread4(shown >> 4) << odd_at;
+            if (i0 + 16 <= r1) {
+                *reinterpret_cast<u64x2 *>(a.out + i0) = q;
             } else {
-                for (uint64_t i = i0; i < r1; ++i)
-                    a.out[i] = (uint8_t)(q[(i - i0) >> 3] >> (8 * ((i - i0) & 7)));
+                for (uint64_t i = i0; i < r1; ++i) {
+                    const uint64_t word = (i - i0) < 8 ? q.x : q.y;
+                    a.out[i] = (uint8_t)(word >> (8 * ((i - i0) & 7)));
+                }
             }
         }
         if (complete)
@@ -340,7 +339,7 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
             pos += w < wave ? wsum[w] : 0u;
             all += wsum[w];
         }
-        uint32_t rest = b16;
+        uint32_t rest = b8;
         const uint64_t first_odd = (a.lo + i0) | 1;
         while (rest) {
             const int t = __ffs(rest) - 1;
@@ -369,7 +368,7 @@ hipError_t launch_range_primes(DeviceState &ds, hipStream_t s)
 hipError_t launch_range_table(uint64_t lo, uint8_t *out, uint64_t len, const DeviceState &ds,
                               hipStream_t s)
 {
-    const uint64_t threads = (len + 63) / 64;
+    const uint64_t threads = (len + 4095) / 4096 * 64;  // one wavefront per 4096 numbers
     const uint64_t blocks = (threads + 255) / 256;
     if (blocks > 0x7fffffffull)
         return hipErrorInvalidValue;
