@@ -10,12 +10,12 @@
 // and >= 2^32, so every base is already reduced (all are below 2^31).
 //
 // Phase 1 (all survivors): base 2 only.  The exponent is processed over the
-// bits of n - 1 from the top, so every lane with the same bit length L runs
-// exactly L - 2 squarings; the multiply by 2 is a modular doubling (the
-// ModAdd of section 2.2) selected without a branch.  About 4 in 5 survivors
-// of random inputs fail here.  Passers go to the workgroup's own region.
-//
-// Phase 1 stores out = 1 for every base-2 passer.
+// bits of n - 1 from the top in a loop whose count is the same on every lane
+// of a wavefront (L - 2 steps for the longest n in it); the multiply by 2 is
+// a modular doubling (the ModAdd of section 2.2) selected without a branch.
+// About 4 in 5 survivors of random inputs fail here.  Passers go to the
+// workgroup's own region with out = 1, and the workgroup then computes each
+// passer's Montgomery constants once for phase 2.
 //
 // Phase 2 (base-2 passers, almost all prime): the six remaining bases as
 // six independent tasks per candidate, laid out densely over the lanes
@@ -27,9 +27,12 @@
 //
 // Work split without global atomics (a single hot device-scope atomic
 // sustains only about 1e8 operations per second on this part): each
-// workgroup scans the producer's per-workgroup counts in LDS, takes an
-// equal slice of the resulting dense index space, and finds each element's
-// producer region by binary search in LDS.
+// workgroup scans the producer's per-workgroup counts in LDS and takes an
+// equal slice of the resulting dense index space; inside the workgroup each
+// wavefront takes the next 64 items of the slice from an LDS counter, so the
+// wavefronts the issue arbiter favours (older ones first) simply do more of
+// the slice.  An item's producer region is found by a search in LDS that
+// starts from the wavefront's previous region.
 #include <algorithm>
 #include <map>
 #include <mutex>
