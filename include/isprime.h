@@ -91,10 +91,11 @@ int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
 /* out[i] = primality of lo + i for 0 <= i < len: a contiguous interval,
  * with no input array.  lo + len - 1 must not exceed 2^64 - 1 (ISP_EINVAL).
  *   out  device pointer to len bytes, each written 0 or 1
- * The part below 2^32 is read from the sieve table; above it, each
- * workgroup sieves a segment of 2^19 numbers by the odd primes up to
- * min(2^22, sqrt(segment end)) and, above 2^44, the survivors go through the
- * same Miller-Rabin kernels as isprime_u64.  Asynchronous on `stream`.
+ * The part below 2^32 is read from the sieve table.  Above it, each
+ * workgroup sieves a segment of 2^19 numbers in LDS: below 2^50 by every
+ * odd prime up to the square root of its end, which decides it; above, by
+ * the odd primes below 2^22, and the survivors go through the same
+ * Miller-Rabin kernels as isprime_u64.  Asynchronous on `stream`.
  * Paper: section 6.1.3 (sieve up to the maximum, then test membership),
  * section 1 (the sieve of Eratosthenes). */
 int isprime_range_u64(uint64_t lo, uint8_t *out, size_t len, void *stream);

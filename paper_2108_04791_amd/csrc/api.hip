@@ -506,20 +506,21 @@ static int ensure_range_primes(int dev)
     if (e == hipSuccess)
         e = hipMalloc(&ds.range_inv, RANGE_MAX_PRIMES * sizeof(uint64_t));
     if (e == hipSuccess)
-        e = hipMalloc(&ds.range_count, sizeof(uint32_t));
+        e = hipMalloc(&ds.range_count, (RANGE_LIST_GROUPS + 1) * sizeof(uint32_t));
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (e == hipSuccess)
         e = launch_range_primes(ds, s);
     uint32_t count = 0;
     if (e == hipSuccess)
-        e = hipMemcpyAsync(&count, ds.range_count, sizeof(count), hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(&count, ds.range_count + RANGE_LIST_GROUPS, sizeof(count),
+                           hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
     if (s)
         (void)hipStreamDestroy(s);
     if (e == hipSuccess && count != RANGE_MAX_PRIMES - 1)
-        e = hipErrorUnknown;  // 295946 odd primes below 2^22
+        e = hipErrorUnknown;  // 2063688 odd primes below 2^25
     if (e != hipSuccess) {
         (void)hipFree(ds.range_primes);
         (void)hipFree(ds.range_inv);

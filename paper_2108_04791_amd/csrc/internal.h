@@ -31,7 +31,10 @@ constexpr int MAX_GRID = 4096;
 // ones: 2^18 bits), and numbers per piece of an interval call.
 constexpr uint64_t RANGE_SEG = (uint64_t)1 << 19;
 constexpr uint64_t RANGE_PIECE = (uint64_t)1 << 30;
-constexpr int RANGE_MAX_PRIMES = 295947;  // odd primes below 2^22: 295946
+constexpr int RANGE_PRIME_LOG2 = 25;      // interval sieve primes: the odd primes below 2^25
+constexpr int RANGE_PARTIAL_LOG2 = 22;    // primes used where the sieve cannot be complete
+constexpr int RANGE_MAX_PRIMES = 2063689; // odd primes below 2^25: 2063688
+constexpr int RANGE_LIST_GROUPS = 512;    // workgroups of the list build
 
 // Device-resident descriptor of a batched call.  The arrays follow the
 // header in the same allocation; the pointers address them.
@@ -109,11 +112,11 @@ struct DeviceState {
     uint32_t *base_primes = nullptr; // odd primes < 2^16
     uint32_t *base_count = nullptr;  // device word: how many
     int num_base_primes = 0;
-    // interval sieve: odd primes below 2^22 and floor((2^64-1)/p), built on
+    // interval sieve: odd primes below 2^25 and floor((2^64-1)/p), built on
     // first use of isprime_range_u64
     uint32_t *range_primes = nullptr;
     uint64_t *range_inv = nullptr;
-    uint32_t *range_count = nullptr;
+    uint32_t *range_count = nullptr;  // RANGE_LIST_GROUPS + 1 words
     int num_range_primes = 0;
 };
 

@@ -6,11 +6,11 @@
 // For an interval that is the natural way to work: the part below 2^32 is
 // copied out of the device table, bit by bit; above it, each workgroup sieves
 // one segment of the interval in LDS by the odd primes up to
-// min(2^22, sqrt(segment end)).  When those primes reach the square root
-// (segment end <= 2^44) the survivors are exactly the primes; otherwise the
-// survivors (about 3.4% of the numbers: those with no factor below 2^22) go
-// to the same two Miller-Rabin kernels as array inputs, through the same
-// per-workgroup regions and counts.
+// sqrt(segment end) while that is below 2^25 (segment end below 2^50); then
+// the survivors are exactly the primes.  Above it the segment is sieved by
+// the odd primes below 2^22 and the survivors (about 3.4% of the numbers:
+// those with no factor below 2^22) go to the same two Miller-Rabin kernels
+// as array inputs, through the same per-workgroup regions and counts.
 //
 // Segment layout: workgroup g covers numbers [lo + g*chunk, lo + (g+1)*chunk)
 // with chunk = classify_chunk(len, grid) (a multiple of 64, at most
@@ -70,21 +70,61 @@ __device__ __forceinline__ uint64_t mod_small(uint64_t x, uint32_t p, uint64_t i
     return r;
 }
 
-// Odd primes below 2^22 from the device table (bits of odd numbers below
-// 2^22 are the first 2^16 words), in order, with floor((2^64 - 1) / p).  One
-// workgroup of 1024 threads, 64 words each; runs once per device.
-__global__ void __launch_bounds__(1024) range_primes_kernel(const uint32_t *__restrict__ table,
-                                                            uint32_t *__restrict__ primes,
-                                                            uint64_t *__restrict__ inv,
-                                                            uint32_t *__restrict__ count)
+// The interval sieve's primes: the odd primes below 2^25 from the device
+// table (bits of odd numbers below 2^25 are its first 2^19 words), in order,
+// with floor((2^64 - 1) / p).  Two passes of RANGE_LIST_GROUPS workgroups,
+// each over 1024 consecutive words: count, then write at the group's offset.
+constexpr int LIST_WORDS = (1 << (RANGE_PRIME_LOG2 - 6)) / RANGE_LIST_GROUPS;  // per group
+static_assert(LIST_WORDS == 1024, "one word per thread-slot below");
+
+__global__ void __launch_bounds__(256) range_count_kernel(const uint32_t *__restrict__ table,
+                                                         uint32_t *__restrict__ counts)
 {
-    constexpr int WORDS = (1 << 16) / 1024;
-    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t wsum[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int w0 = tid * WORDS;
+    const uint32_t w0 = blockIdx.x * LIST_WORDS + tid * 4;
     uint32_t c = 0;
-    for (int k = 0; k < WORDS; ++k)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
         c += __popc(table[w0 + k]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        c += __shfl_xor(c, o, 64);
+    if (lane == 0)
+        wsum[wave] = c;
+    __syncthreads();
+    if (tid == 0)
+        counts[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+__global__ void __launch_bounds__(256) range_list_kernel(const uint32_t *__restrict__ table,
+                                                        uint32_t *__restrict__ counts,
+                                                        uint32_t *__restrict__ primes,
+                                                        uint64_t *__restrict__ inv)
+{
+    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t base;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // this group's offset: the counts of the groups before it
+    uint32_t before = 0;
+    for (uint32_t g = tid; g < blockIdx.x; g += blockDim.x)
+        before += counts[g];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        before += __shfl_xor(before, o, 64);
+    if (lane == 0)
+        wsum[wave] = before;
+    __syncthreads();
+    if (tid == 0)
+        base = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    const uint32_t w0 = blockIdx.x * LIST_WORDS + tid * 4;
+    uint32_t word[4], c = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        word[k] = table[w0 + k];
+        c += __popc(word[k]);
+    }
     uint32_t incl = c;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -92,25 +132,27 @@ __global__ void __launch_bounds__(1024) range_primes_kernel(const uint32_t *__re
         if (lane >= o)
             incl += y;
     }
+    __syncthreads();  // wsum is reused
     if (lane == 63)
         wsum[wave] = incl;
     __syncthreads();
-    uint32_t pos = incl - c;
+    uint32_t pos = base + incl - c;
     for (int w = 0; w < wave; ++w)
         pos += wsum[w];
-    for (int k = 0; k < WORDS; ++k) {
-        uint32_t word = table[w0 + k];
-        while (word) {
-            const int b = __ffs(word) - 1;
-            word &= word - 1;
-            const uint32_t p = 2u * (32u * (uint32_t)(w0 + k) + (uint32_t)b) + 1u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        uint32_t x = word[k];
+        while (x) {
+            const int b = __ffs(x) - 1;
+            x &= x - 1;
+            const uint32_t p = 2u * (32u * (w0 + k) + (uint32_t)b) + 1u;
             primes[pos] = p;
             inv[pos] = ~(uint64_t)0 / p;
             ++pos;
         }
     }
-    if (tid == blockDim.x - 1)
-        *count = pos;
+    if (blockIdx.x == gridDim.x - 1 && tid == blockDim.x - 1)
+        counts[RANGE_LIST_GROUPS] = pos;  // the total
 }
 
 // out[i] = primality of lo + i for lo + len <= 2^32: one table bit per odd
@@ -233,26 +275,31 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
     }
     __syncthreads();
     const uint64_t root = isqrt64(s_last);
-    // primes up to min(2^22, root); the list is sorted, so stop at the first above
+    // Crossing off every prime up to the root costs about one reduction per
+    // prime and segment; below a root of 2^25 (2 million primes) that is
+    // cheaper than Miller-Rabin on the survivors, and the sieve alone decides
+    // the segment.  Above it the segment is sieved by the primes below 2^22
+    // and its survivors (about 3.4% of the numbers) go to Miller-Rabin.
+    const bool complete = root < ((uint64_t)1 << RANGE_PRIME_LOG2);
+    const uint64_t bound = complete ? root : ((uint64_t)1 << RANGE_PARTIAL_LOG2) - 1;
+    // the list is sorted: use the primes up to `bound`
     uint32_t np = a.nprimes;
     {
-        uint32_t lo_i = 0, hi_i = np;  // first index with prime > root
+        uint32_t lo_i = 0, hi_i = np;  // first index with prime > bound
         while (lo_i < hi_i) {
             const uint32_t mid = (lo_i + hi_i) >> 1;
-            if ((uint64_t)a.primes[mid] <= root)
+            if ((uint64_t)a.primes[mid] <= bound)
                 lo_i = mid + 1;
             else
                 hi_i = mid;
         }
         np = lo_i;
     }
-    // every prime up to the root is in the list when the root is below 2^22
-    const bool complete = root < ((uint64_t)1 << 22);
     // first bit index of the odd multiples of p at or above max(o0, p^2), or
     // "none" (all offsets are taken from o0, so nothing wraps near 2^64)
     const uint64_t span = s_last - o0;  // valid only when nbits > 0
     auto first_bit = [&](uint32_t k, uint32_t p) -> uint64_t {
-        const uint64_t pp = (uint64_t)p * p;  // < 2^44, odd
+        const uint64_t pp = (uint64_t)p * p;  // < 2^50, odd
         uint64_t off;
         if (pp >= o0) {
             off = pp - o0;
@@ -360,8 +407,12 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
 
 hipError_t launch_range_primes(DeviceState &ds, hipStream_t s)
 {
-    range_primes_kernel<<<1, 1024, 0, s>>>(ds.table, ds.range_primes, ds.range_inv,
-                                           ds.range_count);
+    range_count_kernel<<<RANGE_LIST_GROUPS, 256, 0, s>>>(ds.table, ds.range_count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    range_list_kernel<<<RANGE_LIST_GROUPS, 256, 0, s>>>(ds.table, ds.range_count,
+                                                        ds.range_primes, ds.range_inv);
     return hipGetLastError();
 }
 

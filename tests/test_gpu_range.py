@@ -1,7 +1,7 @@
 """GPU parity of the interval entry point isprime_range_u64: out[i] is the
 primality of lo + i.  Checked against the oracle element by element on
 intervals that cross the table bound (2^32), the bound where the segment
-sieve stops being complete on its own (2^44), several segments with ragged
+sieve stops being complete on its own (2^50), several segments with ragged
 tails, the top of the 64-bit range, and a call larger than one piece
 (sampled).  Tolerance: zero mismatching bytes."""
 import os
@@ -66,17 +66,18 @@ def test_across_table_bound(isp):
 
 
 def test_across_complete_bound(isp):
-    """Segments ending below 2^44 are decided by the sieve alone (primes up to
-    2^22 reach the square root); above it the survivors go through
-    Miller-Rabin.  This interval has both kinds."""
-    check(isp, (1 << 44) - 3 * SEG - 17, 6 * SEG + 33)
+    """Segments ending below 2^50 are decided by the sieve alone (the primes up
+    to the square root, below 2^25); above it the survivors of the primes below
+    2^22 go through Miller-Rabin.  This interval has both kinds."""
+    check(isp, (1 << 50) - 3 * SEG - 17, 6 * SEG + 33)
 
 
-def test_across_old_and_mid_bounds(isp):
-    """Around 2^40 and 2^42 every segment is complete, sieved by primes past
-    2^20."""
+def test_complete_at_several_magnitudes(isp):
+    """Around 2^40, 2^44 and 2^48 every segment is complete, sieved by primes
+    past 2^20, 2^22 and 2^24."""
     check(isp, (1 << 40) - SEG - 5, 2 * SEG + 11)
-    check(isp, (1 << 42) + 1, SEG + 7)
+    check(isp, (1 << 44) + 1, SEG + 7)
+    check(isp, (1 << 48) - SEG // 2, SEG)
 
 
 @pytest.mark.parametrize("lo,length", [
