@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <cstring>
 #include <map>
@@ -93,7 +94,70 @@ struct StreamWs {
     std::mutex mu;  // held while a call enqueues work that uses the buffers
     int device = -1;
     Workspace ws;
+    RangeWs rws;    // interval buckets
 };
+
+void free_range_ws(RangeWs &rw)
+{
+    if (rw.counts)
+        (void)hipFree(rw.counts);
+    if (rw.hits)
+        (void)hipFree(rw.hits);
+    rw = RangeWs();
+}
+
+// Grows `rw` to the given capacities (words); `stream` is synchronised
+// before old buffers are freed.
+int ensure_range_ws(RangeWs &rw, uint64_t count_cap, uint64_t hit_cap, hipStream_t stream)
+{
+    if (rw.counts && rw.count_cap >= count_cap && rw.hit_cap >= hit_cap)
+        return ISP_OK;
+    count_cap = std::max(count_cap, rw.count_cap);
+    hit_cap = std::max(hit_cap, rw.hit_cap);
+    if (rw.counts) {
+        hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess)
+            return fail(e);
+    }
+    free_range_ws(rw);
+    hipError_t e = hipMalloc(&rw.counts, count_cap * sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMalloc(&rw.hits, hit_cap * sizeof(uint32_t));
+    if (e != hipSuccess) {
+        free_range_ws(rw);
+        return fail(e);
+    }
+    rw.count_cap = count_cap;
+    rw.hit_cap = hit_cap;
+    return ISP_OK;
+}
+
+// floor(sqrt(x)) for x < 2^64.
+uint64_t isqrt_host(uint64_t x)
+{
+    uint64_t r = (uint64_t)std::sqrt((double)x);
+    if (r > 0xffffffffull)
+        r = 0xffffffffull;
+    while (r * r > x)
+        --r;
+    while (r < 0xffffffffull && (r + 1) * (r + 1) <= x)
+        ++r;
+    return r;
+}
+
+// An upper bound on the bucket hits of one piece of `len` numbers: each odd
+// prime p in (BUCKET_SMALL, root] has at most floor(len / 2p) + 1 odd
+// multiples in it.  Rosser and Schoenfeld (Illinois J. Math. 6, 1962) give
+// sum_{p <= x} 1/p < ln ln x + B + 1/ln^2 x and > ln ln x + B - 1/(2 ln^2 x),
+// and pi(x) < 1.25506 x / ln x, for x > 1.
+uint64_t bucket_hit_bound(uint64_t len, uint64_t root)
+{
+    const double x = (double)root, y = (double)BUCKET_SMALL;
+    const double lx = std::log(x), ly = std::log(y);
+    const double recip = std::log(lx / ly) + 1.0 / (lx * lx) + 1.0 / (2.0 * ly * ly);
+    const double pi_x = 1.25506 * x / lx;
+    return (uint64_t)(0.5 * (double)len * recip * 1.02 + pi_x * 1.02) + 4096;
+}
 
 std::mutex g_ws_mu;
 std::map<std::pair<int, void *>, std::unique_ptr<StreamWs>> g_ws;
@@ -443,6 +507,7 @@ void isp_shutdown(void)
         for (auto &kv : g_ws) {
             std::lock_guard<std::mutex> gg(kv.second->mu);
             free_ws(kv.second->ws);
+            free_range_ws(kv.second->rws);
         }
         g_ws.clear();
         g_last.clear();
@@ -564,20 +629,47 @@ int isprime_range_u64(uint64_t lo, uint8_t *out, size_t len, void *stream)
     st = ensure_ws(sw->ws, std::min<uint64_t>(len - below, RANGE_PIECE), s);
     for (uint64_t off = below; off < len && st == ISP_OK; off += RANGE_PIECE) {
         const uint64_t piece = std::min<uint64_t>(RANGE_PIECE, len - off);
-        const unsigned grid = (unsigned)((piece + RANGE_SEG - 1) / RANGE_SEG);
-        ClassifyArgs ca;
-        MrArgs ma;
-        unsigned grid_c, grid1;
-        make_args(ds, sw->ws, t, piece, ca, ma, grid_c, grid1);
-        ma.total = piece;
-        ma.grid_c = grid;
-        hipError_t e = launch_range_sieve(lo + off, out + off, piece, grid, ds, sw->ws, s);
-        if (e == hipSuccess)
-            e = launch_mr1(ma, t.mr_block, s);
-        if (e == hipSuccess)
-            e = t.rest_test ? launch_lucas(ma, ds.cus, t.mr_blocks_per_cu, grid1, t.mr_block, s)
-                            : launch_mr2(ma, ds.cus, t.mr_blocks_per_cu, grid1, t.mr_block,
-                                         t.mr_window, s);
+        const uint64_t root = isqrt_host(lo + off + (piece - 1));
+        // Bucket mode (every segment complete, no Miller-Rabin) once the
+        // per-segment loop over the primes up to the root costs more than the
+        // bucket passes (measured: roots above 2^23), and while the passes'
+        // one-off cost, about one reduction per prime up to the root, is below
+        // Miller-Rabin's on the piece's survivors (a few hundred instructions
+        // per number).
+        const double pi_root = (double)root / std::log((double)root + 2.0);
+        const bool bucket = root > ((uint64_t)1 << BUCKET_FROM_LOG2) && pi_root < 16.0 * (double)piece;
+        hipError_t e = hipSuccess;
+        if (bucket) {
+            const unsigned grid = (unsigned)((piece + RANGE_SEG - 1) / RANGE_SEG);
+            const uint64_t words = (root >> 6) + 1 - ((BUCKET_SMALL + 1) >> 6);
+            const unsigned groups = (unsigned)std::max<uint64_t>(
+                1, std::min<uint64_t>(MAX_BUCKET_GROUPS, words / 1024));
+            // counts (+ total) and the scan's tile sums (+ total)
+            const uint64_t n = (uint64_t)grid * groups;
+            st = ensure_range_ws(sw->rws, n + 1 + n / 8192 + 2, bucket_hit_bound(piece, root), s);
+            if (st != ISP_OK)
+                break;
+            e = launch_range_buckets(lo + off, piece, root, groups, ds, sw->rws, s);
+            if (e == hipSuccess)
+                e = launch_range_sieve(lo + off, out + off, piece, grid, RANGE_SEG, groups, ds,
+                                       sw->ws, sw->rws, s);
+        } else {
+            const unsigned grid = (unsigned)((piece + RANGE_SEG - 1) / RANGE_SEG);
+            ClassifyArgs ca;
+            MrArgs ma;
+            unsigned grid_c, grid1;
+            make_args(ds, sw->ws, t, piece, ca, ma, grid_c, grid1);
+            ma.total = piece;
+            ma.grid_c = grid;
+            e = launch_range_sieve(lo + off, out + off, piece, grid, classify_chunk(piece, grid),
+                                   0, ds, sw->ws, sw->rws, s);
+            if (e == hipSuccess)
+                e = launch_mr1(ma, t.mr_block, s);
+            if (e == hipSuccess)
+                e = t.rest_test ? launch_lucas(ma, ds.cus, t.mr_blocks_per_cu, grid1, t.mr_block, s)
+                                : launch_mr2(ma, ds.cus, t.mr_blocks_per_cu, grid1, t.mr_block,
+                                             t.mr_window, s);
+        }
         if (e != hipSuccess)
             st = fail(e);
     }

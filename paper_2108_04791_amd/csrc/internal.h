@@ -29,12 +29,19 @@ constexpr int MAX_GRID = 4096;
 
 // Numbers per workgroup segment of the interval sieve (LDS holds the odd
 // ones: 2^18 bits), and numbers per piece of an interval call.
-constexpr uint64_t RANGE_SEG = (uint64_t)1 << 19;
+constexpr int RANGE_SEG_LOG2 = 19;
+constexpr uint64_t RANGE_SEG = (uint64_t)1 << RANGE_SEG_LOG2;
 constexpr uint64_t RANGE_PIECE = (uint64_t)1 << 30;
 constexpr int RANGE_PRIME_LOG2 = 25;      // interval sieve primes: the odd primes below 2^25
 constexpr int RANGE_PARTIAL_LOG2 = 22;    // primes used where the sieve cannot be complete
 constexpr int RANGE_MAX_PRIMES = 2063689; // odd primes below 2^25: 2063688
 constexpr int RANGE_LIST_GROUPS = 512;    // workgroups of the list build
+// bucket mode: primes above this come as precomputed hits (at most one per
+// segment of RANGE_SEG numbers)
+constexpr uint32_t BUCKET_SMALL = (uint32_t)1 << 19;
+constexpr int MAX_BUCKET_SEGS = (int)(RANGE_PIECE / RANGE_SEG);  // 2048
+constexpr int MAX_BUCKET_GROUPS = 256;
+constexpr int BUCKET_FROM_LOG2 = 23;  // bucket mode for pieces whose root exceeds 2^23
 
 // Device-resident descriptor of a batched call.  The arrays follow the
 // header in the same allocation; the pointers address them.
@@ -121,6 +128,13 @@ struct DeviceState {
 };
 
 // Per-call workspace (one per stream, or per batched context).
+// Interval buckets: per-(segment, group) counts turned offsets, and the hits.
+struct RangeWs {
+    uint32_t *counts = nullptr;  // count_cap words
+    uint32_t *hits = nullptr;    // hit_cap words
+    uint64_t count_cap = 0, hit_cap = 0;
+};
+
 struct Workspace {
     Survivor *surv = nullptr;   // classify regions (cap + 64 * MAX_GRID entries)
     Survivor *cand = nullptr;   // base-2 passer regions (cap + MAX_GRID entries)
@@ -144,8 +158,11 @@ hipError_t launch_lucas(const MrArgs &a, int cus, int per_cu, unsigned max_grid,
 hipError_t launch_range_primes(DeviceState &ds, hipStream_t s);
 hipError_t launch_range_table(uint64_t lo, uint8_t *out, uint64_t len, const DeviceState &ds,
                               hipStream_t s);
+hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsigned groups,
+                                const DeviceState &ds, const RangeWs &rw, hipStream_t s);
 hipError_t launch_range_sieve(uint64_t lo, uint8_t *out, uint64_t len, unsigned grid,
-                              const DeviceState &ds, const Workspace &ws, hipStream_t s);
+                              uint64_t chunk, unsigned groups, const DeviceState &ds,
+                              const Workspace &ws, const RangeWs &rw, hipStream_t s);
 
 hipError_t launch_montmul_test(const uint64_t *a, const uint64_t *b, const uint64_t *n,
                                uint64_t *out, uint64_t len, hipStream_t s);

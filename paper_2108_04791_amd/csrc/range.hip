@@ -202,12 +202,18 @@ __global__ void __launch_bounds__(256) range_table_kernel(uint64_t lo, uint8_t *
 struct RangeArgs {
     uint64_t lo;         // first number of this piece (>= 2^32)
     uint64_t len;        // numbers in this piece
+    uint64_t chunk;      // numbers per segment (the last one may be shorter)
     uint8_t *out;        // out[i] <-> lo + i
     const uint32_t *primes;
     const uint64_t *inv;
     uint32_t nprimes;
-    Survivor *surv;      // grid regions of classify_chunk(len, grid) entries
+    Survivor *surv;      // grid regions of `chunk` entries
     uint32_t *counts;    // [grid]
+    // bucket mode: the primes above BUCKET_SMALL come as precomputed hits
+    const uint32_t *hit_start;  // [grid * groups + 1]: hits of segment g start at
+                                // hit_start[g * groups]
+    const uint32_t *hits;       // bit indices within their segment
+    uint32_t groups;            // 0: no buckets
 };
 
 // Integer square root of x < 2^64 (floor), from a double estimate.
@@ -230,7 +236,7 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
     __shared__ uint32_t wsum[RANGE_THREADS / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nwaves = blockDim.x >> 6;
-    const uint64_t chunk = classify_chunk(a.len, gridDim.x);
+    const uint64_t chunk = a.chunk;
     const uint64_t r0 = (uint64_t)blockIdx.x * chunk;
     const uint64_t r1 = r0 + chunk < a.len ? r0 + chunk : a.len;
     if (r0 >= r1) {
@@ -280,8 +286,12 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
     // cheaper than Miller-Rabin on the survivors, and the sieve alone decides
     // the segment.  Above it the segment is sieved by the primes below 2^22
     // and its survivors (about 3.4% of the numbers) go to Miller-Rabin.
-    const bool complete = root < ((uint64_t)1 << RANGE_PRIME_LOG2);
-    const uint64_t bound = complete ? root : ((uint64_t)1 << RANGE_PARTIAL_LOG2) - 1;
+    // (in bucket mode the primes above BUCKET_SMALL arrive as hits, and every
+    // segment is complete)
+    const bool buckets = a.groups != 0;
+    const bool complete = buckets || root < ((uint64_t)1 << RANGE_PRIME_LOG2);
+    const uint64_t bound = buckets ? (root < BUCKET_SMALL ? root : BUCKET_SMALL)
+                           : complete ? root : ((uint64_t)1 << RANGE_PARTIAL_LOG2) - 1;
     // the list is sorted: use the primes up to `bound`
     uint32_t np = a.nprimes;
     {
@@ -337,6 +347,15 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
         const uint32_t p = a.primes[k];
         for (uint64_t j = first_bit(k, p); j < nbits; j += p)
             atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
+    }
+    // bucket mode: the hits of the primes above BUCKET_SMALL in this segment
+    if (buckets) {
+        const uint32_t h0 = a.hit_start[(uint64_t)blockIdx.x * a.groups];
+        const uint32_t h1 = a.hit_start[(uint64_t)(blockIdx.x + 1) * a.groups];
+        for (uint32_t h = h0 + tid; h < h1; h += blockDim.x) {
+            const uint32_t j = a.hits[h];
+            atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
+        }
     }
     __syncthreads();
     // outputs: 16 consecutive numbers per thread per pass, consecutive threads
@@ -403,6 +422,237 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
         a.counts[blockIdx.x] = filled;
 }
 
+// ---- bucket mode: crossing off by the primes above BUCKET_SMALL ----------
+//
+// A prime p > 2^19 has at most one odd multiple in a segment of 2^19
+// numbers, so visiting every such prime in every segment costs one
+// reduction per prime and segment.  Bucket mode inverts the loop (the
+// bucket sieve of segmented sieving): the odd primes in (BUCKET_SMALL,
+// sqrt(end)] are read from the device table, each prime's odd multiples at
+// or above max(lo, p^2) are enumerated once over the whole piece, and each
+// becomes a hit (its bit index) in the bucket of its segment.  Two passes
+// over the same primes by `groups` workgroups: count the hits per (segment,
+// group) in LDS, then after an exclusive scan write them at their places,
+// so no global atomic is needed.  The segment kernel then applies its
+// bucket.  With every prime up to the square root crossed off, the
+// segments are complete at any magnitude below 2^64.
+
+struct BucketArgs {
+    uint64_t lo, len;        // the piece
+    uint64_t w_begin, w_end; // table words holding the odd primes in (BUCKET_SMALL, root]
+    uint64_t root;
+    const uint32_t *table;
+    uint32_t nseg;           // segments of RANGE_SEG numbers
+    uint32_t *counts;        // [nseg * groups + 1], segment-major: (g, group)
+    uint32_t *hits;
+    uint64_t hit_cap;
+};
+
+// lo mod p for p < 2^32 from a double-precision quotient estimate (error
+// below one unit: lo < 2^64 is rounded to 53 bits and the quotient is below
+// 2^45, so the estimate is within 2^-7 of lo / p) and one correction each way.
+__device__ __forceinline__ uint64_t mod_u32(uint64_t x, uint32_t p)
+{
+    const double q = (double)x * (1.0 / (double)p);
+    uint64_t qi = q < 1.0 ? 0 : (uint64_t)q;
+    int64_t r = (int64_t)(x - qi * (uint64_t)p);
+    if (r < 0)
+        r += p;
+    if (r >= (int64_t)p)
+        r -= p;
+    return (uint64_t)r;
+}
+
+// Offset from lo of p's first odd multiple at or above max(lo, p^2), or an
+// offset >= len when there is none.
+__device__ __forceinline__ uint64_t bucket_first(const BucketArgs &a, uint32_t p)
+{
+    const uint64_t pp = (uint64_t)p * p;
+    uint64_t off;
+    if (pp >= a.lo) {
+        off = pp - a.lo;  // odd square: odd when lo is even, and lo + off is odd
+    } else {
+        const uint64_t r = mod_u32(a.lo, p);
+        off = r ? p - r : 0;
+        if (((a.lo + off) & 1) == 0)
+            off += p;  // the next multiple is odd
+    }
+    return off;
+}
+
+// Cost of the primes below x, up to constants: one first-hit computation per
+// prime (x / ln x primes) and one bucket entry per hit (len/2 * sum 1/p, which
+// grows like ln ln x).  Group g takes the primes whose cumulative cost falls
+// in its equal share, so the low primes with hundreds of hits each and the
+// high primes with at most one are spread evenly.
+__device__ __forceinline__ double bucket_cost(double x, double len)
+{
+    const double lx = log(x);
+    return 24.0 * x / lx + 4.0 * 0.5 * len * log(lx);
+}
+
+// The prime bound where the cumulative cost reaches `target` (bisection).
+__device__ double bucket_split(double target, double lo, double hi, double len)
+{
+    for (int it = 0; it < 80; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (bucket_cost(mid, len) < target)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return hi;
+}
+
+template <bool FILL>
+__global__ void __launch_bounds__(1024) range_bucket_kernel(BucketArgs a)
+{
+    __shared__ uint32_t cnt[MAX_BUCKET_SEGS];
+    __shared__ uint64_t wrange[2];
+    const uint32_t groups = gridDim.x;
+    for (uint32_t g = threadIdx.x; g < a.nseg; g += blockDim.x)
+        cnt[g] = 0;
+    if (threadIdx.x == 0) {
+        // this group's words: equal shares of the cost between BUCKET_SMALL and root
+        const double len = (double)a.len, x0 = (double)BUCKET_SMALL, x1 = (double)a.root + 1.0;
+        const double c0 = bucket_cost(x0, len), c1 = bucket_cost(x1, len);
+        uint64_t wb = a.w_begin, we = a.w_end;
+        if (blockIdx.x > 0)
+            wb = (uint64_t)bucket_split(c0 + (c1 - c0) * blockIdx.x / groups, x0, x1, len) >> 6;
+        if (blockIdx.x + 1 < groups)
+            we = (uint64_t)bucket_split(c0 + (c1 - c0) * (blockIdx.x + 1) / groups, x0, x1, len) >> 6;
+        wrange[0] = wb < a.w_begin ? a.w_begin : (wb > a.w_end ? a.w_end : wb);
+        wrange[1] = we < a.w_begin ? a.w_begin : (we > a.w_end ? a.w_end : we);
+    }
+    __syncthreads();
+    const uint64_t wb = wrange[0], we = wrange[1];
+    for (uint64_t w = wb + threadIdx.x; w < we; w += blockDim.x) {
+        uint32_t word = a.table[w];
+        while (word) {
+            const int b = __ffs(word) - 1;
+            word &= word - 1;
+            const uint32_t p = (uint32_t)(2 * (32 * w + (uint64_t)b) + 1);
+            if (p <= BUCKET_SMALL || p > a.root)
+                continue;
+            for (uint64_t off = bucket_first(a, p); off < a.len; off += 2ull * p) {
+                const uint32_t g = (uint32_t)(off >> RANGE_SEG_LOG2);
+                if (FILL) {
+                    const uint32_t k = atomicAdd(&cnt[g], 1u);
+                    const uint64_t at = (uint64_t)a.counts[(uint64_t)g * groups + blockIdx.x] + k;
+                    if (at < a.hit_cap)
+                        a.hits[at] = (uint32_t)((off & (RANGE_SEG - 1)) >> 1);
+                } else {
+                    atomicAdd(&cnt[g], 1u);
+                }
+            }
+        }
+    }
+    if (!FILL) {
+        __syncthreads();
+        for (uint32_t g = threadIdx.x; g < a.nseg; g += blockDim.x)
+            a.counts[(uint64_t)g * groups + blockIdx.x] = cnt[g];
+    }
+}
+
+// Exclusive scan of counts[0 .. n) in place, total at counts[n], in three
+// passes over tiles of SCAN_TILE words: tile sums, a scan of the sums (one
+// workgroup), then each tile scanned and offset.
+constexpr int SCAN_TILE = 8192;  // 1024 threads x 8
+
+__device__ __forceinline__ uint32_t block_sum_1024(uint32_t v, uint32_t *wsum)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    if (lane == 0)
+        wsum[wave] = v;
+    __syncthreads();
+    uint32_t t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+        t += wsum[w];
+    return t;
+}
+
+__global__ void __launch_bounds__(1024) scan_tile_sums(const uint32_t *counts, uint32_t n,
+                                                      uint32_t *sums)
+{
+    __shared__ uint32_t wsum[16];
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+    uint32_t v = 0;
+    for (int k = 0; k < SCAN_TILE / 1024; ++k) {
+        const uint64_t i = base + (uint64_t)k * blockDim.x + threadIdx.x;
+        if (i < n)
+            v += counts[i];
+    }
+    const uint32_t t = block_sum_1024(v, wsum);
+    if (threadIdx.x == 0)
+        sums[blockIdx.x] = t;
+}
+
+// Exclusive scan of up to 1024 values in place (one workgroup); total at [m].
+__global__ void __launch_bounds__(1024) scan_small(uint32_t *v, uint32_t m)
+{
+    __shared__ uint32_t wsum[16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t x = threadIdx.x < m ? v[threadIdx.x] : 0u;
+    uint32_t incl = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o)
+            incl += y;
+    }
+    if (lane == 63)
+        wsum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w)
+        before += wsum[w];
+    if (threadIdx.x < m)
+        v[threadIdx.x] = before + incl - x;
+    if (threadIdx.x == blockDim.x - 1)
+        v[m] = before + incl;
+}
+
+__global__ void __launch_bounds__(1024) scan_tiles(uint32_t *counts, uint32_t n,
+                                                  const uint32_t *sums)
+{
+    __shared__ uint32_t wsum[16];
+    constexpr int PER = SCAN_TILE / 1024;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // thread t owns the PER consecutive words t*PER .. of the tile
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * PER;
+    uint32_t x[PER], local = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        x[k] = base + k < n ? counts[base + k] : 0u;
+        local += x[k];
+    }
+    uint32_t incl = local;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o)
+            incl += y;
+    }
+    if (lane == 63)
+        wsum[wave] = incl;
+    __syncthreads();
+    uint32_t run = sums[blockIdx.x] + incl - local;
+    for (int w = 0; w < wave; ++w)
+        run += wsum[w];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        if (base + k < n)
+            counts[base + k] = run;
+        run += x[k];
+    }
+    const uint32_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (blockIdx.x == ntiles - 1 && threadIdx.x == blockDim.x - 1)
+        counts[n] = run;  // the total
+}
+
 }  // namespace
 
 hipError_t launch_range_primes(DeviceState &ds, hipStream_t s)
@@ -427,12 +677,60 @@ hipError_t launch_range_table(uint64_t lo, uint8_t *out, uint64_t len, const Dev
     return hipGetLastError();
 }
 
+hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsigned groups,
+                                const DeviceState &ds, const RangeWs &rw, hipStream_t s)
+{
+    BucketArgs a;
+    a.lo = lo;
+    a.len = len;
+    a.root = root;
+    a.table = ds.table;
+    a.w_begin = (BUCKET_SMALL + 1) >> 6;
+    a.w_end = (root >> 6) + 1;
+    a.nseg = (uint32_t)((len + RANGE_SEG - 1) / RANGE_SEG);
+    a.counts = rw.counts;
+    a.hits = rw.hits;
+    a.hit_cap = rw.hit_cap;
+    if (a.nseg > (uint32_t)MAX_BUCKET_SEGS || a.w_end > (uint64_t)TABLE_WORDS ||
+        a.w_end <= a.w_begin)
+        return hipErrorInvalidValue;
+    const uint32_t n = a.nseg * groups;
+    const uint32_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (ntiles > 1024 || rw.count_cap < (uint64_t)n + 1 + ntiles + 1)
+        return hipErrorInvalidValue;
+    uint32_t *sums = rw.counts + n + 1;  // ntiles + 1 words after the counts
+    range_bucket_kernel<false><<<groups, 1024, 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        scan_tile_sums<<<ntiles, 1024, 0, s>>>(rw.counts, n, sums);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        scan_small<<<1, 1024, 0, s>>>(sums, ntiles);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        scan_tiles<<<ntiles, 1024, 0, s>>>(rw.counts, n, sums);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        range_bucket_kernel<true><<<groups, 1024, 0, s>>>(a);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
 hipError_t launch_range_sieve(uint64_t lo, uint8_t *out, uint64_t len, unsigned grid,
-                              const DeviceState &ds, const Workspace &ws, hipStream_t s)
+                              uint64_t chunk, unsigned groups, const DeviceState &ds,
+                              const Workspace &ws, const RangeWs &rw, hipStream_t s)
 {
     RangeArgs a;
     a.lo = lo;
     a.len = len;
+    a.chunk = chunk;
+    a.hit_start = rw.counts;
+    a.hits = rw.hits;
+    a.groups = groups;
     a.out = out;
     a.primes = ds.range_primes;
     a.inv = ds.range_inv;

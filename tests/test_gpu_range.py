@@ -133,6 +133,25 @@ def test_empty_and_invalid(isp):
     assert gpu_range(isp, U64, 1)[0] == 0
 
 
+@pytest.mark.parametrize("lo", [(1 << 56) + 12345, (1 << 62) - 3, (1 << 64) - (1 << 24)])
+def test_bucket_mode_high_magnitude(isp, lo):
+    """Long intervals far above 2^50 run as a complete bucketed sieve (every
+    prime up to the square root, up to 2^32, crossed off; no Miller-Rabin):
+    the whole interval equals the array call, and a sample equals the
+    oracle."""
+    length = 1 << 24
+    got = isp.isprime_range(lo, length)
+    base = lo if lo < (1 << 63) else lo - (1 << 64)
+    arr = torch.arange(base, base + length, dtype=torch.int64, device="cuda")
+    assert torch.equal(isp.isprime(arr), got)
+    rng = np.random.default_rng(lo & 0xffff)
+    idx = np.unique(np.concatenate([np.arange(0, 3000), np.arange(length - 3000, length),
+                                    rng.integers(0, length, 20000)])).astype(np.int64)
+    a = np.uint64(lo) + idx.astype(np.uint64)
+    exp, _ = oracle.isprime_array(a, nthreads=NTHREADS, use_table=False)
+    assert np.array_equal(got[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.uint8), exp)
+
+
 def test_larger_than_one_piece_sampled(isp):
     """A call of more than 2^30 numbers runs in pieces; the outputs around the
     piece boundary and a random sample are checked one by one, and the whole
