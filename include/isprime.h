@@ -92,10 +92,15 @@ int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
  * with no input array.  lo + len - 1 must not exceed 2^64 - 1 (ISP_EINVAL).
  *   out  device pointer to len bytes, each written 0 or 1
  * The part below 2^32 is read from the sieve table.  Above it, each
- * workgroup sieves a segment of 2^19 numbers in LDS: below 2^50 by every
- * odd prime up to the square root of its end, which decides it; above, by
- * the odd primes below 2^22, and the survivors go through the same
- * Miller-Rabin kernels as isprime_u64.  Asynchronous on `stream`.
+ * workgroup sieves a segment of 2^19 numbers in LDS, in pieces of at most
+ * 2^30 numbers.  A piece ending below 2^50 is sieved by every odd prime up
+ * to the square root of its end, which decides it.  Above, a piece long
+ * enough for the primes up to its square root (pi(sqrt) below 16 times its
+ * length) also gets every such prime: those above 2^19 are sorted once into
+ * per-segment buckets (bucket sieve), and the segments are again complete.
+ * Otherwise it is sieved by the odd primes below 2^22 and the survivors go
+ * through the same Miller-Rabin kernels as isprime_u64.  The workspace kept
+ * for the stream grows to the largest call seen.  Asynchronous on `stream`.
  * Paper: section 6.1.3 (sieve up to the maximum, then test membership),
  * section 1 (the sieve of Eratosthenes). */
 int isprime_range_u64(uint64_t lo, uint8_t *out, size_t len, void *stream);

@@ -79,13 +79,16 @@ __device__ __forceinline__ int wave_max(int v)
 // makes x = 2 exactly where its own exponent starts.  The loop count is the
 // same on all lanes (a scalar loop), and only the last smax steps (smax: the
 // largest s in the wavefront) compare.
-__device__ __forceinline__ bool sprp_base2(uint64_t n)
+//
+// SQ (wavefront-uniform): 0 when every n is below 2^62, 1 below 2^63, 2
+// otherwise.  Below 2^63 the squares take the carry-free form (montsqr63).
+template <int SQ>
+__device__ __forceinline__ bool sprp_base2_run(uint64_t n, const MontCtx &c, uint64_t e, int s,
+                                               int L, int Lmax, int smax)
 {
-    const int L = 64 - __clzll(n);
-    const MontCtx c = make_ctx(n, L);
-    const uint64_t e = n - 1;
-    const int s = __ffsll((long long)e) - 1;
-    const int Lmax = wave_max(L), smax = wave_max(s);
+    auto sqr = [&](uint64_t y) {
+        return SQ == 2 ? montsqr(y, n, c.ninv) : montsqr63(y, n, c.ninv);
+    };
     // bit Lmax - 1: the leading one of the longest lanes (x = 2), a leading
     // zero of the others (x = 1)
     uint64_t x = L == Lmax ? dbl_mod(c.one, n) : c.one;
@@ -93,7 +96,7 @@ __device__ __forceinline__ bool sprp_base2(uint64_t n)
     // and then 2x - n = 2x + (2^64 - n) modulo 2^64, carry or not.
     const uint64_t half = (n >> 1) + 1, neg_n = 0 - n;
     auto step = [&](uint32_t bit) {
-        x = montsqr(x, n, c.ninv);
+        x = sqr(x);
         // x <- 2^bit x mod n in one instruction: (x << bit) + (2^64 - n) when
         // the bit is set and 2x wraps past n, (x << bit) + 0 otherwise
         const uint64_t sub = (bit != 0 && x >= half) ? neg_n : 0;
@@ -102,7 +105,7 @@ __device__ __forceinline__ bool sprp_base2(uint64_t n)
     // bits Lmax - 2 .. smax + 1 from the top of `rest` (bit t of n - 1 at
     // t + 65 - Lmax)
     uint64_t rest = e << (65 - Lmax);
-    if (Lmax <= 62) {
+    if constexpr (SQ == 0) {
         // n < 2^62: x may stay in [0, 2n) between squarings (a product of
         // two such values is below 4 n^2 < n 2^64, which the Montgomery
         // product accepts, and its result is reduced), so the doubling is a
@@ -110,7 +113,7 @@ __device__ __forceinline__ bool sprp_base2(uint64_t n)
         for (int t = Lmax - 2; t > smax; --t) {
             const uint32_t bit = hi32(rest) >> 31;
             rest <<= 1;
-            x = montsqr(x, n, c.ninv) << bit;
+            x = sqr(x) << bit;
         }
     } else {
         for (int t = Lmax - 2; t > smax; --t) {
@@ -131,19 +134,39 @@ __device__ __forceinline__ bool sprp_base2(uint64_t n)
     return pass;
 }
 
+__device__ __forceinline__ bool sprp_base2(uint64_t n)
+{
+    const int L = 64 - __clzll(n);
+    const MontCtx c = make_ctx(n, L);
+    const uint64_t e = n - 1;
+    const int s = __ffsll((long long)e) - 1;
+    const int Lmax = wave_max(L), smax = wave_max(s);
+    if (Lmax <= 62)
+        return sprp_base2_run<0>(n, c, e, s, L, Lmax, smax);
+    if (Lmax == 63)
+        return sprp_base2_run<1>(n, c, e, s, L, Lmax, smax);
+    return sprp_base2_run<2>(n, c, e, s, L, Lmax, smax);
+}
+
 // Strong test for one base (am: its Montgomery form) with n - 1 = 2^s d.
 // a^d by a fixed window of W bits: the lane's table a^0 .. a^(2^W - 1) sits
 // in LDS, column threadIdx.x of tbl[2^W][blockDim] (each lane reads only
 // its own column, so no barrier is needed and the rows are bank-aligned).
-// LAZY (every n of the wavefront below 2^62): products stay in (0, 2n) and
-// are reduced once before the comparisons.
-template <int W, bool LAZY>
+// SQ as for sprp_base2_run.  SQ 0 (every n of the wavefront below 2^62):
+// products stay in (0, 2n) and are reduced once before the comparisons.
+template <int W, int SQ>
 __device__ __forceinline__ bool sprp_window(uint64_t am, uint64_t d, int s, const MontCtx &c,
                                             uint64_t *tbl)
 {
     constexpr int TS = 1 << W;
     auto mul = [&](uint64_t x, uint64_t y) {
-        return LAZY ? montmul_lazy(x, y, c.n, c.ninv) : montmul(x, y, c.n, c.ninv);
+        return SQ == 0 ? montmul_lazy(x, y, c.n, c.ninv) : montmul(x, y, c.n, c.ninv);
+    };
+    // (the lazy square keeps the general form: with the carry-free square
+    // the compiler needs one more register move per step)
+    auto sqr = [&](uint64_t x) {
+        return SQ == 0 ? montmul_lazy(x, x, c.n, c.ninv)
+                       : SQ == 1 ? montsqr63(x, c.n, c.ninv) : montsqr(x, c.n, c.ninv);
     };
     const unsigned col = threadIdx.x, stride = blockDim.x;
     uint64_t p = c.one;
@@ -163,15 +186,15 @@ __device__ __forceinline__ bool sprp_window(uint64_t am, uint64_t d, int s, cons
     for (pos -= W; pos >= 0; pos -= W) {
 #pragma unroll
         for (int k = 0; k < W; ++k)
-            x = mul(x, x);
+            x = sqr(x);
         x = mul(x, tbl[((unsigned)(d >> pos) & (TS - 1)) * stride + col]);
     }
-    if (LAZY && x >= c.n)
+    if (SQ == 0 && x >= c.n)
         x -= c.n;
     if (x == c.one || x == c.mone)
         return true;
     for (int r = 1; r < s; ++r) {
-        x = montsqr(x, c.n, c.ninv);
+        x = SQ == 2 ? montsqr(x, c.n, c.ninv) : montsqr63(x, c.n, c.ninv);
         if (x == c.mone)
             return true;
     }
@@ -192,9 +215,12 @@ __device__ __forceinline__ bool sprp_one_base(uint64_t n, const MontPrep &pr, ui
     const uint64_t e = n - 1;
     const int s = __ffsll((long long)e) - 1;
     const uint64_t am = to_mont(a, pr.r2, c);
-    if (wave_max(64 - __clzll(n)) <= 62)
-        return sprp_window<W, true>(am, e >> s, s, c, tbl);
-    return sprp_window<W, false>(am, e >> s, s, c, tbl);
+    const int Lmax = wave_max(64 - __clzll(n));
+    if (Lmax <= 62)
+        return sprp_window<W, 0>(am, e >> s, s, c, tbl);
+    if (Lmax == 63)
+        return sprp_window<W, 1>(am, e >> s, s, c, tbl);
+    return sprp_window<W, 2>(am, e >> s, s, c, tbl);
 }
 
 // The Montgomery constants of odd n >= 2^32.

@@ -7,10 +7,13 @@
 // copied out of the device table, bit by bit; above it, each workgroup sieves
 // one segment of the interval in LDS by the odd primes up to
 // sqrt(segment end) while that is below 2^25 (segment end below 2^50); then
-// the survivors are exactly the primes.  Above it the segment is sieved by
-// the odd primes below 2^22 and the survivors (about 3.4% of the numbers:
-// those with no factor below 2^22) go to the same two Miller-Rabin kernels
-// as array inputs, through the same per-workgroup regions and counts.
+// the survivors are exactly the primes.  Above it, a long piece runs in
+// bucket mode (below): the primes above 2^19 up to the square root are
+// sorted into per-segment buckets first, and the segments are complete
+// again.  A short piece is sieved by the odd primes below 2^22 and the
+// survivors (about 3.4% of the numbers: those with no factor below 2^22) go
+// to the same two Miller-Rabin kernels as array inputs, through the same
+// per-workgroup regions and counts.
 //
 // Segment layout: workgroup g covers numbers [lo + g*chunk, lo + (g+1)*chunk)
 // with chunk = classify_chunk(len, grid) (a multiple of 64, at most
@@ -210,9 +213,11 @@ struct RangeArgs {
     Survivor *surv;      // grid regions of `chunk` entries
     uint32_t *counts;    // [grid]
     // bucket mode: the primes above BUCKET_SMALL come as precomputed hits
-    const uint32_t *hit_start;  // [grid * groups + 1]: hits of segment g start at
-                                // hit_start[g * groups]
+    const uint32_t *hit_start;  // [groups * grid + 1]: the hits of segment g found
+                                // by group q are hits[hit_start[q * grid + g] ..
+                                // hit_start[q * grid + g + 1])
     const uint32_t *hits;       // bit indices within their segment
+    uint64_t hit_cap;           // entries allocated in hits
     uint32_t groups;            // 0: no buckets
 };
 
@@ -234,7 +239,10 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
     constexpr int MAX_WORDS = (int)(RANGE_SEG / 64);  // 2^13 words of odd-number bits
     __shared__ uint32_t bits[MAX_WORDS + 1];          // + one zero word past the end
     __shared__ uint32_t wsum[RANGE_THREADS / 64];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // the wavefront index as a scalar, so per-prime work of the wavefront
+    // loop below (the prime, its first multiple) runs on the scalar unit
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nwaves = blockDim.x >> 6;
     const uint64_t chunk = a.chunk;
     const uint64_t r0 = (uint64_t)blockIdx.x * chunk;
@@ -339,22 +347,32 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
         const uint64_t j0 = first_bit(k, p);
         if (j0 >= nbits)
             continue;
-        for (uint64_t j = j0 + (uint64_t)lane * p; j < nbits; j += 64ull * p)
+        // bit indices below 2^18: 32-bit arithmetic
+        const uint32_t stride = 64u * p;
+        for (uint32_t j = (uint32_t)j0 + (uint32_t)lane * p; j < nbits; j += stride)
             atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
     }
     // larger primes: one thread per prime
     for (uint32_t k = k_split + tid; k < np; k += blockDim.x) {
         const uint32_t p = a.primes[k];
-        for (uint64_t j = first_bit(k, p); j < nbits; j += p)
+        const uint64_t j0 = first_bit(k, p);
+        if (j0 >= nbits)
+            continue;
+        for (uint32_t j = (uint32_t)j0; j < nbits; j += p)
             atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
     }
     // bucket mode: the hits of the primes above BUCKET_SMALL in this segment
     if (buckets) {
-        const uint32_t h0 = a.hit_start[(uint64_t)blockIdx.x * a.groups];
-        const uint32_t h1 = a.hit_start[(uint64_t)(blockIdx.x + 1) * a.groups];
-        for (uint32_t h = h0 + tid; h < h1; h += blockDim.x) {
-            const uint32_t j = a.hits[h];
-            atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
+        // one run per group, read by one wavefront (the hits fit by
+        // construction; the clamp only keeps reads inside the allocation)
+        for (uint32_t q = wave; q < a.groups; q += nwaves) {
+            const uint64_t at = (uint64_t)q * gridDim.x + blockIdx.x;
+            const uint32_t h0 = a.hit_start[at];
+            const uint32_t h1 = (uint32_t)min((uint64_t)a.hit_start[at + 1], a.hit_cap);
+            for (uint32_t h = h0 + lane; h < h1; h += 64) {
+                const uint32_t j = a.hits[h];
+                atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
+            }
         }
     }
     __syncthreads();
@@ -443,7 +461,7 @@ struct BucketArgs {
     uint64_t root;
     const uint32_t *table;
     uint32_t nseg;           // segments of RANGE_SEG numbers
-    uint32_t *counts;        // [nseg * groups + 1], segment-major: (g, group)
+    uint32_t *counts;        // [groups * nseg + 1], group-major: (group, g)
     uint32_t *hits;
     uint64_t hit_cap;
 };
@@ -504,14 +522,69 @@ __device__ double bucket_split(double target, double lo, double hi, double len)
     return hi;
 }
 
+constexpr int BUCKET_THREADS = 1024;
+// Dense prime list per wavefront and chunk of 64 table words (4096
+// consecutive integers).  An interval of y >= 2 integers holds at most
+// 2y / ln y primes (Montgomery and Vaughan, Mathematika 20, 1973): 985 for
+// y = 4096; a chunk that still had more would take the per-lane path.
+constexpr uint32_t BUCKET_PBUF = 1024;
+// Table words are loaded BUCKET_PREF chunks at a time per wavefront (into
+// LDS): the wait for a load also waits for the wavefront's earlier stores
+// (one counter covers both), so the fill pass waits once per BUCKET_PREF
+// chunks instead of once per chunk.
+constexpr uint32_t BUCKET_PREF = 16;
+
+// Every odd multiple of p in the piece, each counted in (FILL: written to)
+// the bucket of its segment.  The lanes of a wavefront hold consecutive
+// primes, whose multiples march through the segments together; each lane
+// starts at its own share (lane / 64) of its K multiples and wraps around,
+// so at each step the lanes touch different segments instead of queueing on
+// the same LDS counter.
 template <bool FILL>
-__global__ void __launch_bounds__(1024) range_bucket_kernel(BucketArgs a)
+__device__ __forceinline__ void bucket_hits(const BucketArgs &a, uint32_t p, uint32_t lane,
+                                            uint32_t *cnt)
+{
+    const uint64_t first = bucket_first(a, p);
+    if (first >= a.len)
+        return;
+    const uint64_t step = 2ull * p;
+    const uint64_t span = a.len - 1 - first;  // < 2^30
+    // K = floor(span / step) + 1; step > span means a single multiple, and
+    // otherwise step < 2^30 fits 32 bits
+    uint32_t K = 1;
+    if (step <= span)
+        K = (uint32_t)span / (uint32_t)step + 1u;
+    uint64_t off = first + (uint64_t)((lane * K) >> 6) * step;
+    for (uint32_t j = 0; j < K; ++j) {
+        const uint32_t g = (uint32_t)(off >> RANGE_SEG_LOG2);
+        if (FILL) {
+            const uint32_t at = atomicAdd(&cnt[g], 1u);
+            if (at < a.hit_cap)
+                a.hits[at] = (uint32_t)((off & (RANGE_SEG - 1)) >> 1);
+        } else {
+            atomicAdd(&cnt[g], 1u);
+        }
+        off += step;
+        if (off >= a.len)
+            off = first;
+    }
+}
+
+// Count pass (FILL false): cnt[g] counts this group's hits in segment g and
+// goes to counts[group * nseg + g] (group-major, so that each group's hits
+// land in one contiguous stretch of `hits`).  Fill pass: cnt[g] starts at the
+// scanned offset of (g, group), so each atomic increment yields the hit's
+// place in `hits` directly.
+template <bool FILL>
+__global__ void __launch_bounds__(BUCKET_THREADS) range_bucket_kernel(BucketArgs a)
 {
     __shared__ uint32_t cnt[MAX_BUCKET_SEGS];
+    __shared__ uint32_t pbuf[BUCKET_THREADS / 64][BUCKET_PBUF];
+    __shared__ uint32_t pref[BUCKET_THREADS / 64][64 * BUCKET_PREF];
     __shared__ uint64_t wrange[2];
     const uint32_t groups = gridDim.x;
     for (uint32_t g = threadIdx.x; g < a.nseg; g += blockDim.x)
-        cnt[g] = 0;
+        cnt[g] = FILL ? a.counts[(uint64_t)blockIdx.x * a.nseg + g] : 0u;
     if (threadIdx.x == 0) {
         // this group's words: equal shares of the cost between BUCKET_SMALL and root
         const double len = (double)a.len, x0 = (double)BUCKET_SMALL, x1 = (double)a.root + 1.0;
@@ -526,31 +599,81 @@ __global__ void __launch_bounds__(1024) range_bucket_kernel(BucketArgs a)
     }
     __syncthreads();
     const uint64_t wb = wrange[0], we = wrange[1];
-    for (uint64_t w = wb + threadIdx.x; w < we; w += blockDim.x) {
-        uint32_t word = a.table[w];
-        while (word) {
-            const int b = __ffs(word) - 1;
-            word &= word - 1;
-            const uint32_t p = (uint32_t)(2 * (32 * w + (uint64_t)b) + 1);
-            if (p <= BUCKET_SMALL || p > a.root)
-                continue;
-            for (uint64_t off = bucket_first(a, p); off < a.len; off += 2ull * p) {
-                const uint32_t g = (uint32_t)(off >> RANGE_SEG_LOG2);
-                if (FILL) {
-                    const uint32_t k = atomicAdd(&cnt[g], 1u);
-                    const uint64_t at = (uint64_t)a.counts[(uint64_t)g * groups + blockIdx.x] + k;
-                    if (at < a.hit_cap)
-                        a.hits[at] = (uint32_t)((off & (RANGE_SEG - 1)) >> 1);
-                } else {
-                    atomicAdd(&cnt[g], 1u);
-                }
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t nwaves = blockDim.x >> 6;
+    uint32_t *buf = pbuf[wave];
+    uint32_t *words = pref[wave];
+    auto take = [&](uint32_t p) {
+        if (p > BUCKET_SMALL && p <= a.root)
+            bucket_hits<FILL>(a, p, lane, cnt);
+    };
+    // the primes of a chunk of 64 words (w0 .. w0 + 63; lane l holds word
+    // w0 + l) are listed densely in LDS (a wavefront prefix sum of the
+    // words' popcounts) and then taken one per lane
+    auto chunk = [&](uint64_t w0, uint32_t word) {
+        const uint64_t w = w0 + lane;
+        const uint32_t c = (uint32_t)__popc(word);
+        uint32_t inc = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(inc, o, 64);
+            if (lane >= (uint32_t)o)
+                inc += t;
+        }
+        const uint32_t total = __shfl(inc, 63, 64);
+        if (total <= BUCKET_PBUF) {
+            uint32_t at = inc - c;
+            while (word) {
+                const int b = __ffs(word) - 1;
+                word &= word - 1;
+                buf[at++] = (uint32_t)(2 * (32 * w + (uint64_t)b) + 1);
             }
+            // the list is read by the other lanes of the wavefront
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (uint32_t i = lane; i < total; i += 64)
+                take(buf[i]);
+            // and overwritten by the next chunk
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            while (word) {
+                const int b = __ffs(word) - 1;
+                word &= word - 1;
+                take((uint32_t)(2 * (32 * w + (uint64_t)b) + 1));
+            }
+        }
+    };
+    // the wavefronts take the chunks in turn (wavefront v: chunks v, v +
+    // nwaves, ...), BUCKET_PREF of them at a time; lane l loads (and later
+    // reads) word l of each
+    const uint64_t nch = we > wb ? (we - wb + 63) / 64 : 0;
+    for (uint64_t c0 = 0; c0 < nch; c0 += (uint64_t)BUCKET_PREF * nwaves) {
+        // (unconditional loads from clamped addresses, so all of them are
+        // in flight together)
+        uint32_t v[BUCKET_PREF];
+#pragma unroll
+        for (uint32_t c = 0; c < BUCKET_PREF; ++c) {
+            const uint64_t w = wb + 64 * (c0 + (uint64_t)c * nwaves + wave) + lane;
+            v[c] = a.table[w < we ? w : we - 1];
+        }
+#pragma unroll
+        for (uint32_t c = 0; c < BUCKET_PREF; ++c)
+            words[64 * c + lane] = wb + 64 * (c0 + (uint64_t)c * nwaves + wave) + lane < we ? v[c] : 0u;
+        for (uint32_t c = 0; c < BUCKET_PREF; ++c) {
+            const uint64_t ch = c0 + (uint64_t)c * nwaves + wave;
+            if (ch >= nch)
+                break;
+            chunk(wb + 64 * ch, words[64 * c + lane]);
         }
     }
     if (!FILL) {
         __syncthreads();
         for (uint32_t g = threadIdx.x; g < a.nseg; g += blockDim.x)
-            a.counts[(uint64_t)g * groups + blockIdx.x] = cnt[g];
+            a.counts[(uint64_t)blockIdx.x * a.nseg + g] = cnt[g];
     }
 }
 
@@ -699,7 +822,7 @@ hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsign
     if (ntiles > 1024 || rw.count_cap < (uint64_t)n + 1 + ntiles + 1)
         return hipErrorInvalidValue;
     uint32_t *sums = rw.counts + n + 1;  // ntiles + 1 words after the counts
-    range_bucket_kernel<false><<<groups, 1024, 0, s>>>(a);
+    range_bucket_kernel<false><<<groups, BUCKET_THREADS, 0, s>>>(a);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
         scan_tile_sums<<<ntiles, 1024, 0, s>>>(rw.counts, n, sums);
@@ -714,7 +837,7 @@ hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsign
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
-        range_bucket_kernel<true><<<groups, 1024, 0, s>>>(a);
+        range_bucket_kernel<true><<<groups, BUCKET_THREADS, 0, s>>>(a);
         e = hipGetLastError();
     }
     return e;
@@ -729,6 +852,7 @@ hipError_t launch_range_sieve(uint64_t lo, uint8_t *out, uint64_t len, unsigned 
     a.len = len;
     a.chunk = chunk;
     a.hit_start = rw.counts;
+    a.hit_cap = rw.hit_cap;
     a.hits = rw.hits;
     a.groups = groups;
     a.out = out;
@@ -737,6 +861,10 @@ hipError_t launch_range_sieve(uint64_t lo, uint8_t *out, uint64_t len, unsigned 
     a.nprimes = (uint32_t)ds.num_range_primes;
     a.surv = ws.surv;
     a.counts = ws.counts;
+    // bucket mode: one workgroup per segment of RANGE_SEG numbers, as the
+    // bucket passes counted them
+    if (groups != 0 && (chunk != RANGE_SEG || grid != (len + RANGE_SEG - 1) / RANGE_SEG))
+        return hipErrorInvalidValue;
     range_sieve_kernel<<<grid, RANGE_THREADS, 0, s>>>(a);
     return hipGetLastError();
 }

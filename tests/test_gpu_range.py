@@ -133,13 +133,14 @@ def test_empty_and_invalid(isp):
     assert gpu_range(isp, U64, 1)[0] == 0
 
 
-@pytest.mark.parametrize("lo", [(1 << 56) + 12345, (1 << 62) - 3, (1 << 64) - (1 << 24)])
-def test_bucket_mode_high_magnitude(isp, lo):
-    """Long intervals far above 2^50 run as a complete bucketed sieve (every
-    prime up to the square root, up to 2^32, crossed off; no Miller-Rabin):
-    the whole interval equals the array call, and a sample equals the
-    oracle."""
-    length = 1 << 24
+@pytest.mark.parametrize("lo,length", [((1 << 56) + 12345, 1 << 26), ((1 << 62) - 3, 1 << 28),
+                                       ((1 << 64) - (1 << 29), 1 << 29)])
+def test_bucket_mode_high_magnitude(isp, lo, length):
+    """Intervals far above 2^50 that are long next to the number of primes up
+    to their square root run as a complete bucketed sieve (every prime up to
+    the square root, up to 2^32, crossed off; no Miller-Rabin): the whole
+    interval equals the array call, and a sample equals the oracle.  The
+    last case ends at 2^64 - 1."""
     got = isp.isprime_range(lo, length)
     base = lo if lo < (1 << 63) else lo - (1 << 64)
     arr = torch.arange(base, base + length, dtype=torch.int64, device="cuda")
