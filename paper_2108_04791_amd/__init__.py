@@ -192,23 +192,44 @@ def isprime(n: torch.Tensor, stream=None) -> torch.Tensor:
     return isprime_into(n, out, stream)
 
 
+class Batch:
+    """A prepared isprime_u64_batched call: the host arrays of device
+    pointers and lengths are built once, so repeated calls over the same
+    tensors cost one C call each.  The tensors must stay alive and keep
+    their storage while the Batch is used."""
+
+    def __init__(self, arrays, outs=None):
+        self.arrays = [_as_u64(a) for a in arrays]
+        if outs is None:
+            outs = [torch.empty(a.shape, dtype=torch.bool, device=a.device) for a in self.arrays]
+        if len(outs) != len(self.arrays):
+            raise ValueError("one output per array")
+        for a, o in zip(self.arrays, outs):
+            if o.numel() != a.numel() or not o.is_contiguous() or o.dtype not in (torch.bool, torch.uint8):
+                raise ValueError("each output must be a contiguous bool/uint8 tensor of its array's size")
+        self.outs = list(outs)
+        self.k = len(self.arrays)
+        NP = ctypes.c_uint64 * max(self.k, 1)
+        self._nps = NP(*[a.data_ptr() if a.numel() else 0 for a in self.arrays])
+        self._ops = NP(*[o.data_ptr() if o.numel() else 0 for o in self.outs])
+        self._lens = NP(*[a.numel() for a in self.arrays])
+        self._device = self.arrays[0].device if self.k else None
+
+    def run(self, stream=None):
+        """Enqueue the call on `stream`; returns the outputs."""
+        if self.k == 0:
+            return self.outs
+        with torch.cuda.device(self._device):
+            _check(lib().isprime_u64_batched(ctypes.cast(self._nps, _P), ctypes.cast(self._ops, _P),
+                                             ctypes.cast(self._lens, _P), self.k,
+                                             _stream_handle(stream)),
+                   "isprime_u64_batched")
+        return self.outs
+
+
 def isprime_batched(arrays, outs=None, stream=None):
     """Many arrays in one graph-replayed launch sequence; returns the outputs."""
-    arrays = [_as_u64(a) for a in arrays]
-    if outs is None:
-        outs = [torch.empty(a.shape, dtype=torch.bool, device=a.device) for a in arrays]
-    k = len(arrays)
-    if k == 0:
-        return outs
-    NP = ctypes.c_uint64 * k
-    nps = NP(*[a.data_ptr() if a.numel() else 0 for a in arrays])
-    ops = NP(*[o.data_ptr() if o.numel() else 0 for o in outs])
-    lens = NP(*[a.numel() for a in arrays])
-    with torch.cuda.device(arrays[0].device):
-        _check(lib().isprime_u64_batched(ctypes.cast(nps, _P), ctypes.cast(ops, _P),
-                                         ctypes.cast(lens, _P), k, _stream_handle(stream)),
-               "isprime_u64_batched")
-    return outs
+    return Batch(arrays, outs).run(stream)
 
 
 def isprime_range(lo: int, length: int, out: torch.Tensor | None = None, stream=None,

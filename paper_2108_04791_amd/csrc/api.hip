@@ -325,6 +325,10 @@ int current_device(int *dev)
 
 // -------------------------------------------------------------- batched
 
+// Two pinned descriptor buffers, each with its own recorded graph (whose
+// first node copies that buffer to the device): a call writes the buffer
+// the call before last used, so it waits only for that replay (normally
+// long finished), and back-to-back calls keep the device busy.
 struct BatchCtx {
     std::mutex mu;
     int device = -1;
@@ -332,11 +336,12 @@ struct BatchCtx {
     size_t arr_cap = 0;
     size_t desc_bytes = 0;
     void *d_desc = nullptr;
-    void *h_desc = nullptr;  // pinned
+    void *h_desc[2] = {nullptr, nullptr};  // pinned
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipEvent_t done = nullptr;
-    bool pending = false;  // `done` recorded after the last replay
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipEvent_t done[2] = {nullptr, nullptr};
+    bool pending[2] = {false, false};  // done[k] recorded after the last replay of exec[k]
+    unsigned next = 0;                 // buffer of the next call
     Tuning tuned{};
     unsigned grid_c = 0, grid1 = 0;
 };
@@ -357,31 +362,51 @@ size_t desc_size(size_t arrays)
 
 void free_batch(BatchCtx &c)
 {
-    if (c.exec)
-        (void)hipGraphExecDestroy(c.exec);
+    for (int k = 0; k < 2; ++k) {
+        if (c.exec[k])
+            (void)hipGraphExecDestroy(c.exec[k]);
+        if (c.h_desc[k])
+            (void)hipHostFree(c.h_desc[k]);
+        if (c.done[k])
+            (void)hipEventDestroy(c.done[k]);
+        c.exec[k] = nullptr;
+        c.h_desc[k] = nullptr;
+        c.done[k] = nullptr;
+        c.pending[k] = false;
+    }
     if (c.d_desc)
         (void)hipFree(c.d_desc);
-    if (c.h_desc)
-        (void)hipHostFree(c.h_desc);
     if (c.cap_stream)
         (void)hipStreamDestroy(c.cap_stream);
-    if (c.done)
-        (void)hipEventDestroy(c.done);
     free_ws(c.ws);
-    c.exec = nullptr;
-    c.d_desc = c.h_desc = nullptr;
+    c.d_desc = nullptr;
     c.cap_stream = nullptr;
-    c.done = nullptr;
     c.arr_cap = 0;
     c.desc_bytes = 0;
-    c.pending = false;
+    c.next = 0;
 }
 
-int build_graph(BatchCtx &c, const DeviceState &ds, const Tuning &t)
+// Wait for both buffers' last replays (before anything they use is replaced).
+hipError_t drain_batch(BatchCtx &c)
 {
-    if (c.exec) {
-        (void)hipGraphExecDestroy(c.exec);
-        c.exec = nullptr;
+    for (int k = 0; k < 2; ++k) {
+        if (c.pending[k]) {
+            const hipError_t e = hipEventSynchronize(c.done[k]);
+            if (e != hipSuccess)
+                return e;
+            c.pending[k] = false;
+        }
+    }
+    return hipSuccess;
+}
+
+// Records exec[k]: the copy of h_desc[k] to the device descriptor, then the
+// three kernels over the virtual concatenation of the arrays.
+int build_graph_one(BatchCtx &c, const DeviceState &ds, const Tuning &t, int k)
+{
+    if (c.exec[k]) {
+        (void)hipGraphExecDestroy(c.exec[k]);
+        c.exec[k] = nullptr;
     }
     ClassifyArgs ca;
     MrArgs ma;
@@ -393,7 +418,7 @@ int build_graph(BatchCtx &c, const DeviceState &ds, const Tuning &t)
     hipError_t e = hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess)
         return fail(e);
-    hipError_t ee = hipMemcpyAsync(c.d_desc, c.h_desc, c.desc_bytes, hipMemcpyHostToDevice,
+    hipError_t ee = hipMemcpyAsync(c.d_desc, c.h_desc[k], c.desc_bytes, hipMemcpyHostToDevice,
                                    c.cap_stream);
     if (ee == hipSuccess)
         ee = launch_classify(ca, grid_c, t.classify_block, t.classify_ept, c.cap_stream);
@@ -413,16 +438,24 @@ int build_graph(BatchCtx &c, const DeviceState &ds, const Tuning &t)
     }
     if (e != hipSuccess)
         return fail(e);
-    e = hipGraphInstantiate(&c.exec, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&c.exec[k], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-        c.exec = nullptr;
+        c.exec[k] = nullptr;
         return fail(e);
     }
     c.tuned = t;
     c.grid_c = grid_c;
     c.grid1 = grid1;
     return ISP_OK;
+}
+
+int build_graph(BatchCtx &c, const DeviceState &ds, const Tuning &t)
+{
+    int st = build_graph_one(c, ds, t, 0);
+    if (st == ISP_OK)
+        st = build_graph_one(c, ds, t, 1);
+    return st;
 }
 
 }  // namespace
@@ -498,6 +531,7 @@ void isp_shutdown(void)
         std::lock_guard<std::mutex> g(g_batch_mu);
         for (auto &kv : g_batch) {
             std::lock_guard<std::mutex> gg(kv.second->mu);
+            (void)drain_batch(*kv.second);
             free_batch(*kv.second);
         }
         g_batch.clear();
@@ -719,27 +753,31 @@ int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
     hipError_t e;
     // The descriptor buffers and the workspace are baked into the graph, so
     // growing either re-records it.
-    bool rebuild = !c->exec || !same_tuning(c->tuned, t);
+    bool rebuild = !c->exec[0] || !c->exec[1] || !same_tuning(c->tuned, t);
+    if (rebuild || num_arrays > c->arr_cap || !c->ws.surv || c->ws.cap < total) {
+        // (re-recording or reallocating: nothing of the old replays may
+        // still run)
+        e = drain_batch(*c);
+        if (e != hipSuccess)
+            return fail(e);
+    }
     if (num_arrays > c->arr_cap || !c->ws.surv || c->ws.cap < total) {
-        if (c->pending) {
-            e = hipEventSynchronize(c->done);
-            if (e != hipSuccess)
-                return fail(e);
-            c->pending = false;
-        }
         if (num_arrays > c->arr_cap || !c->d_desc) {
             size_t arr_cap = std::max<size_t>(c->arr_cap, 1024);
             while (arr_cap < num_arrays)
                 arr_cap <<= 1;
             if (c->d_desc)
                 (void)hipFree(c->d_desc);
-            if (c->h_desc)
-                (void)hipHostFree(c->h_desc);
-            c->d_desc = c->h_desc = nullptr;
+            for (int k = 0; k < 2; ++k) {
+                if (c->h_desc[k])
+                    (void)hipHostFree(c->h_desc[k]);
+                c->h_desc[k] = nullptr;
+            }
+            c->d_desc = nullptr;
             c->desc_bytes = desc_size(arr_cap);
             e = hipMalloc(&c->d_desc, c->desc_bytes);
-            if (e == hipSuccess)
-                e = hipHostMalloc(&c->h_desc, c->desc_bytes, hipHostMallocDefault);
+            for (int k = 0; k < 2 && e == hipSuccess; ++k)
+                e = hipHostMalloc(&c->h_desc[k], c->desc_bytes, hipHostMallocDefault);
             if (e != hipSuccess) {
                 free_batch(*c);
                 return fail(e);
@@ -755,19 +793,21 @@ int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
     }
     if (!c->cap_stream) {
         e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
-        if (e == hipSuccess)
-            e = hipEventCreateWithFlags(&c->done, hipEventDisableTiming);
+        for (int k = 0; k < 2 && e == hipSuccess; ++k)
+            e = hipEventCreateWithFlags(&c->done[k], hipEventDisableTiming);
         if (e != hipSuccess)
             return fail(e);
     }
-    // The previous replay's copy reads h_desc: wait for it before rewriting.
-    if (c->pending) {
-        e = hipEventSynchronize(c->done);
+    // The replay that last used this buffer copies from it: wait for it
+    // before rewriting (normally it finished long ago).
+    const unsigned k = c->next;
+    if (c->pending[k]) {
+        e = hipEventSynchronize(c->done[k]);
         if (e != hipSuccess)
             return fail(e);
-        c->pending = false;
+        c->pending[k] = false;
     }
-    char *h = static_cast<char *>(c->h_desc);
+    char *h = static_cast<char *>(c->h_desc[k]);
     char *d = static_cast<char *>(c->d_desc);
     const size_t off_n = align_up(sizeof(BatchDesc), 64);
     const size_t off_o = off_n + c->arr_cap * 8;
@@ -794,12 +834,13 @@ int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
         if (st != ISP_OK)
             return st;
     }
-    e = hipGraphLaunch(c->exec, s);
+    e = hipGraphLaunch(c->exec[k], s);
     if (e == hipSuccess)
-        e = hipEventRecord(c->done, s);
+        e = hipEventRecord(c->done[k], s);
     if (e != hipSuccess)
         return fail(e);
-    c->pending = true;
+    c->pending[k] = true;
+    c->next = k ^ 1u;
     note_counts(dev, stream, c->ws, c->grid_c, c->grid1);
     return ISP_OK;
 }

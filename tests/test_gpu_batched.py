@@ -58,6 +58,34 @@ def test_batched_replays_and_eager_work_between(isp):
             assert np.array_equal(o.cpu().numpy().astype(np.uint8), e), rep
 
 
+def test_batched_back_to_back_calls(isp):
+    """Calls issued back to back with no synchronisation between them (the
+    library alternates two descriptor buffers and graphs): every call's
+    outputs are its own, for two input sets taken in turn and for a prepared
+    Batch run repeatedly."""
+    rng = np.random.default_rng(3)
+    sets = []
+    for _ in range(2):
+        arrays = [W.c3_mixed(int(L), start=int(st)) for L, st in
+                  zip(rng.integers(1, 5000, size=40), rng.integers(0, 1 << 30, size=40))]
+        sets.append(([to_dev(a) for a in arrays],
+                     [oracle.isprime_array(a, nthreads=NTHREADS, use_table=False)[0] for a in arrays]))
+    runs = []
+    for r in range(6):
+        dev, exp = sets[r % 2]
+        outs = [torch.full((d.numel(),), 7, dtype=torch.uint8, device="cuda") for d in dev]
+        isp.Batch(dev, outs).run()
+        runs.append((outs, exp))
+    prepared = isp.Batch(sets[0][0])
+    for _ in range(3):
+        prepared.run()
+    torch.cuda.synchronize()
+    runs.append((prepared.outs, sets[0][1]))
+    for r, (outs, exp) in enumerate(runs):
+        for o, e in zip(outs, exp):
+            assert np.array_equal(o.cpu().numpy().astype(np.uint8), e), r
+
+
 def test_batched_growing_and_empty_arrays(isp):
     rng = np.random.default_rng(2)
     for k in (1, 3, 1500, 5000):
