@@ -16,6 +16,7 @@ the per-stage times.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -282,33 +283,45 @@ def bench_batched(isp, W, torch, reps: int = 5) -> dict:
     return res
 
 
-def bench_served(isp, W, torch, num: int = 2100, warm: int = 100) -> dict:
+def bench_served(isp, W, torch, num: int = 2100, warm: int = 100, max_inflight: int = 6,
+                 max_batch_elems: int = 1 << 20, baseline: bool = True,
+                 loads=(0.25, 0.5, 0.7, 0.9)) -> dict:
     """Poisson request stream (lengths log-uniform in [1, 2^20], magnitude
-    class per request) served by the continuous-batching server, against the
-    same stream served FIFO by serial plain calls (copy in, isprime_u64, copy
-    out, synchronise).  Arrival rate: 0.7 x the server's measured capacity.
-    Latency = arrival to result in the caller's host array."""
+    class per request) served by the continuous-batching server at several
+    fractions of its measured capacity (the headline at 0.7), against the
+    same stream at 0.7 served FIFO by serial plain calls (copy in,
+    isprime_u64, copy out, synchronise).  Latency = arrival to result in the
+    caller's host array."""
     import threading
     reqs = W.c5_requests(num, qps=1.0)  # arrival times for rate 1; rescaled below
     arrays = [r for _, r, _ in reqs]
     unit_t = np.array([t for t, _, _ in reqs])
     elems = sum(a.size for a in arrays[warm:])
 
-    srv = isp.Server(max_inflight=3, max_batch_elems=1 << 22)
-    try:
-        # capacity: everything submitted at once
-        outs = [np.zeros(a.size, np.uint8) for a in arrays]
-        t0 = time.perf_counter()
-        tk = [srv.submit(a, o) for a, o in zip(arrays, outs)]
-        for t in tk:
-            srv.wait(t)
-        cap_s = time.perf_counter() - t0
-        capacity = num / cap_s
-        qps = 0.7 * capacity
-        arrive = unit_t / qps
+    def stats(lat, span):
+        m = lat[warm:] * 1e3
+        return {"p50_ms": float(np.percentile(m, 50)), "p99_ms": float(np.percentile(m, 99)),
+                "mean_ms": float(m.mean()), "tests_per_s": elems / span}
 
-        def run_served():
-            lat = np.zeros(num)
+    # Python's cyclic collector is paused and its thread switch interval
+    # shortened while requests are timed: a collection pass over the many
+    # request arrays, or a 5 ms wait for the interpreter lock, would delay
+    # the submitting and waiting threads, not the server
+    switch = sys.getswitchinterval()
+    srv = isp.Server(max_inflight=max_inflight, max_batch_elems=max_batch_elems)
+    try:
+        # capacity: everything submitted at once (after one untimed pass, so
+        # that the output pages and the server's buffers are already mapped)
+        outs = [np.full(a.size, 2, np.uint8) for a in arrays]
+        for rep in range(2):
+            t0 = time.perf_counter()
+            tk = [srv.submit(a, o) for a, o in zip(arrays, outs)]
+            for t in tk:
+                srv.wait(t)
+            cap_s = time.perf_counter() - t0
+        capacity = num / cap_s
+
+        def run_served(arrive):
             done_t = np.zeros(num)
             tickets = [None] * num
             ready = threading.Semaphore(0)
@@ -329,38 +342,53 @@ def bench_served(isp, W, torch, num: int = 2100, warm: int = 100) -> dict:
                 tickets[i] = srv.submit(arrays[i], outs[i])
                 ready.release()
             th.join()
-            lat[:] = done_t - arrive
-            return lat, done_t[-1] - arrive[warm]
+            return done_t - arrive, done_t[-1] - arrive[warm]
 
-        lat_s, span_s = run_served()
+        by_load = {}
+        gc.disable()
+        sys.setswitchinterval(1e-4)
+        try:
+            run_served(unit_t / (0.7 * capacity))  # untimed: threads and pages warm
+            for load in loads:
+                by_load[str(load)] = stats(*run_served(unit_t / (load * capacity)))
+        finally:
+            sys.setswitchinterval(switch)
+            gc.enable()
     finally:
         srv.close()
 
-    # baseline: serial plain calls in arrival order
-    stream = torch.cuda.current_stream()
-    lat_p = np.zeros(num)
-    base = time.perf_counter() + 0.01
-    t_free = 0.0
-    for i, a in enumerate(arrays):
-        now = time.perf_counter() - base
-        if now < arrive[i]:
-            time.sleep(arrive[i] - now)
-        d = torch.from_numpy(a.view(np.int64)).cuda()
-        o = torch.empty(a.size, dtype=torch.uint8, device="cuda")
-        isp.isprime_into(d, o, stream)
-        o.cpu()
-        t_free = time.perf_counter() - base
-        lat_p[i] = t_free - arrive[i]
-    span_p = t_free - arrive[warm]
-
-    def stats(lat, span):
-        m = lat[warm:] * 1e3
-        return {"p50_ms": float(np.percentile(m, 50)), "p99_ms": float(np.percentile(m, 99)),
-                "mean_ms": float(m.mean()), "tests_per_s": elems / span}
-
-    return {"requests": num - warm, "warmup_requests": warm, "elements": int(elems),
-            "capacity_req_per_s": capacity, "qps": qps,
-            "served": stats(lat_s, span_s), "serial_plain": stats(lat_p, span_p)}
+    qps = 0.7 * capacity
+    res = {"requests": num - warm, "warmup_requests": warm, "elements": int(elems),
+           "capacity_req_per_s": capacity, "qps": qps,
+           "server": {"max_inflight": max_inflight, "max_batch_elems": max_batch_elems},
+           "served": by_load.get("0.7"), "served_by_load": by_load}
+    if not baseline:
+        return res
+    # baseline: serial plain calls in arrival order, at 0.7 of the server's capacity
+    arrive = unit_t / qps
+    gc.disable()
+    sys.setswitchinterval(1e-4)
+    try:
+        stream = torch.cuda.current_stream()
+        lat_p = np.zeros(num)
+        base = time.perf_counter() + 0.01
+        t_free = 0.0
+        for i, a in enumerate(arrays):
+            now = time.perf_counter() - base
+            if now < arrive[i]:
+                time.sleep(arrive[i] - now)
+            d = torch.from_numpy(a.view(np.int64)).cuda()
+            o = torch.empty(a.size, dtype=torch.uint8, device="cuda")
+            isp.isprime_into(d, o, stream)
+            o.cpu()
+            t_free = time.perf_counter() - base
+            lat_p[i] = t_free - arrive[i]
+        span_p = t_free - arrive[warm]
+    finally:
+        sys.setswitchinterval(switch)
+        gc.enable()
+    res["serial_plain"] = stats(lat_p, span_p)
+    return res
 
 
 def main() -> int:

@@ -61,6 +61,113 @@ struct Piece {
     size_t len;
 };
 
+// Host copies of one batch (dst, src, bytes) split over a few persistent
+// threads and the calling thread.  One host thread copies about 10 GB/s into
+// pinned memory, well below what the host memory system and the PCIe link
+// carry, and staging each batch's inputs is the serving path's bottleneck.
+class CopyPool {
+public:
+    struct Seg {
+        void *dst;
+        const void *src;
+        size_t bytes;
+    };
+
+    explicit CopyPool(int workers)
+    {
+        for (int i = 0; i < workers; ++i)
+            th_.emplace_back([this, i] { loop(i + 1); });
+    }
+    ~CopyPool()
+    {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : th_)
+            t.join();
+    }
+    // Every segment copied when it returns.  Batches below a few hundred KB
+    // are copied by the caller alone.
+    void run(const std::vector<Seg> &segs)
+    {
+        size_t total = 0;
+        for (const Seg &x : segs)
+            total += x.bytes;
+        if (th_.empty() || total < ((size_t)256 << 10)) {
+            copy_range(segs, 0, total);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            job_ = &segs;
+            total_ = total;
+            parts_ = th_.size() + 1;
+            left_ = th_.size();
+            ++gen_;
+        }
+        cv_.notify_all();
+        copy_part(segs, total, 0, th_.size() + 1);
+        std::unique_lock<std::mutex> g(mu_);
+        cv_done_.wait(g, [&] { return left_ == 0; });
+        job_ = nullptr;
+    }
+
+private:
+    static void copy_range(const std::vector<Seg> &segs, size_t b0, size_t b1)
+    {
+        size_t at = 0;  // byte offset of the current segment in the batch
+        for (const Seg &x : segs) {
+            const size_t s0 = std::max(b0, at), s1 = std::min(b1, at + x.bytes);
+            if (s0 < s1)
+                std::memcpy(static_cast<char *>(x.dst) + (s0 - at),
+                            static_cast<const char *>(x.src) + (s0 - at), s1 - s0);
+            at += x.bytes;
+            if (at >= b1)
+                break;
+        }
+    }
+    static void copy_part(const std::vector<Seg> &segs, size_t total, size_t part, size_t parts)
+    {
+        // 4 KB-aligned cut points
+        auto cut = [&](size_t k) { return k >= parts ? total : std::min(total, (total / parts * k) & ~(size_t)4095); };
+        copy_range(segs, cut(part), cut(part + 1));
+    }
+    void loop(size_t part)
+    {
+        uint64_t seen = 0;
+        for (;;) {
+            const std::vector<Seg> *job;
+            size_t total, parts;
+            {
+                std::unique_lock<std::mutex> g(mu_);
+                cv_.wait(g, [&] { return stop_ || gen_ != seen; });
+                if (stop_)
+                    return;
+                seen = gen_;
+                job = job_;
+                total = total_;
+                parts = parts_;
+            }
+            copy_part(*job, total, part, parts);
+            {
+                std::lock_guard<std::mutex> g(mu_);
+                if (--left_ == 0)
+                    cv_done_.notify_all();
+            }
+        }
+    }
+
+    std::vector<std::thread> th_;
+    std::mutex mu_;
+    std::condition_variable cv_, cv_done_;
+    const std::vector<Seg> *job_ = nullptr;
+    size_t total_ = 0, parts_ = 0, left_ = 0;
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+};
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
@@ -92,12 +199,14 @@ struct isp_server {
     uint64_t batches = 0;
     bool stop = false;
     bool dispatcher_done = false;
+    std::unique_ptr<CopyPool> stage_pool;  // used by the dispatcher only
     std::thread dispatcher, completer;
 };
 
 namespace {
 
 constexpr size_t BYTES_PER_ELEM = sizeof(uint64_t) + sizeof(uint8_t);
+constexpr int SERVER_COPY_THREADS = 3;  // staging helpers next to the dispatcher
 
 void free_slot_resources(isp_server *s, Slot &sl)
 {
@@ -179,10 +288,15 @@ void dispatcher_main(isp_server *s)
         }
         // stage the inputs (outside the lock: the host arrays belong to the
         // requests until they complete)
-        size_t off = 0;
-        for (const Piece &p : sl->pieces) {
-            std::memcpy(sl->h_n + off, p.req->n + p.off, p.len * sizeof(uint64_t));
-            off += p.len;
+        {
+            std::vector<CopyPool::Seg> segs;
+            segs.reserve(sl->pieces.size());
+            size_t off = 0;
+            for (const Piece &p : sl->pieces) {
+                segs.push_back({sl->h_n + off, p.req->n + p.off, p.len * sizeof(uint64_t)});
+                off += p.len;
+            }
+            s->stage_pool->run(segs);
         }
         int st = ISP_OK;
         if (!s->cfg.test_mode) {
@@ -272,11 +386,11 @@ int isp_server_create(const isp_server_config *cfg, isp_server **srv)
     s->cfg = *cfg;
     isp_server_config &c = s->cfg;
     if (!c.max_inflight)
-        c.max_inflight = 3;
+        c.max_inflight = 6;
     if (!c.mem_budget_bytes)
         c.mem_budget_bytes = (uint64_t)1 << 30;
     if (!c.max_batch_elems)
-        c.max_batch_elems = (uint64_t)1 << 22;
+        c.max_batch_elems = (uint64_t)1 << 20;
     if (!c.max_batch_reqs)
         c.max_batch_reqs = 1024;
     if (c.max_inflight < 1 || c.max_inflight > 8 || c.max_batch_reqs < 1 ||
@@ -324,6 +438,7 @@ int isp_server_create(const isp_server_config *cfg, isp_server **srv)
         return st;
     }
     isp_server *raw = s.release();
+    raw->stage_pool.reset(new CopyPool(SERVER_COPY_THREADS));
     raw->dispatcher = std::thread(dispatcher_main, raw);
     raw->completer = std::thread(completer_main, raw);
     *srv = raw;

@@ -29,6 +29,22 @@ def test_results_routed_to_their_requests():
             assert np.array_equal(o, (r & np.uint64(1)).astype(np.uint8))
 
 
+def test_large_batches_staged_by_several_threads():
+    """Batches above a few hundred KB are staged by the server's copy
+    threads in byte ranges that cut across pieces: every request, split
+    over pieces and packed with others, still gets exactly its own bytes."""
+    rng = np.random.default_rng(4)
+    with isp.Server(test_mode=1, max_batch_elems=(1 << 20) + 12345, max_inflight=3) as srv:
+        lens = [int(k) for k in rng.integers(1, 700000, size=24)] + [3 << 20, 1, 999999]
+        reqs = [rand_req(rng, k) for k in lens]
+        outs = [np.full(r.size, 7, dtype=np.uint8) for r in reqs]
+        tickets = [srv.submit(r, o) for r, o in zip(reqs, outs)]
+        for t in tickets:
+            srv.wait(t)
+        for r, o in zip(reqs, outs):
+            assert np.array_equal(o, (r & np.uint64(1)).astype(np.uint8))
+
+
 def test_ticket_api():
     with isp.Server(test_mode=1, test_delay_us=20000) as srv:
         a = np.arange(10, dtype=np.uint64)
