@@ -219,18 +219,27 @@ def bench_paper_suite(isp, W, torch, reps: int = 7) -> dict:
     return res
 
 
-def bench_intervals(isp, torch, reps: int = 5) -> dict:
-    """The interval call above 2^32, where each workgroup sieves a segment in
-    LDS: one interval whose segments the sieve decides alone (below 2^40) and
-    one whose survivors go on to Miller-Rabin, each against the array call
+def bench_intervals(isp, torch, reps: int = 5, array_call: bool = True) -> dict:
+    """The interval call above 2^32, where each workgroup sieves a segment of
+    2^19 numbers in LDS, in each of its modes: segments decided by the primes
+    up to their square root (2^34, 2^44), the bucket sieve of the primes
+    above 2^19 (2^50, 2^63), and the primes below 2^22 followed by
+    Miller-Rabin on the survivors (2^64 - 2^28); each against the array call
     on the same values."""
     stream = torch.cuda.current_stream()
     res = {}
-    for name, lo in (("2^34+[0,2^28)", 1 << 34), ("2^50+[0,2^28)", 1 << 50),
-                     ("2^63+[0,2^28)", 1 << 63)):
+    for name, lo in (("2^34+[0,2^28)", 1 << 34), ("2^44+[0,2^28)", 1 << 44),
+                     ("2^50+[0,2^28)", 1 << 50), ("2^63+[0,2^28)", 1 << 63),
+                     ("2^64-2^28+[0,2^28)", (1 << 64) - (1 << 28))):
         length = 1 << 28
         rout = torch.empty(length, dtype=torch.bool, device="cuda")
         rms = _time_ms(torch, stream, lambda: isp.isprime_range(lo, length, rout, stream), reps)
+        if not array_call:
+            res[name] = {"elements": length, "interval_ms": rms,
+                         "interval_tests_per_s": length / (rms * 1e-3),
+                         "primes": int(rout.sum().item())}
+            del rout
+            continue
         # the same values as an array (int64 view of the uint64 values)
         base = lo if lo < (1 << 63) else lo - (1 << 64)
         dev = torch.arange(base, base + length, dtype=torch.int64, device="cuda")
@@ -399,6 +408,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched and served measurements")
+    ap.add_argument("--intervals-only", action="store_true",
+                    help="only time the interval call on its five cases (for profiling its kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters)")
@@ -425,6 +436,10 @@ def main() -> int:
     isp.init(0)
     torch.cuda.synchronize()
     sieve_ms = (time.perf_counter() - t0) * 1e3
+    if args.intervals_only:
+        print(json.dumps({"intervals": bench_intervals(isp, torch, reps=args.steps,
+                                                       array_call=False)}))
+        return 0
 
     from paper_2108_04791_amd import tune
     defaults = isp.get_config()

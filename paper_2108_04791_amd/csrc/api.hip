@@ -668,18 +668,26 @@ int isprime_range_u64(uint64_t lo, uint8_t *out, size_t len, void *stream)
         // per-segment loop over the primes up to the root costs more than the
         // bucket passes (measured: roots above 2^23), and while the passes'
         // cost is below Miller-Rabin's on the piece's survivors.  Measured on
-        // 2^28-number pieces: the bucket mode takes about 2.8 ps per number
-        // plus 15.5 ps per prime up to the root, Miller-Rabin about 12 ps per
-        // number, so buckets win while pi(root) < 0.6 len (pi(root) is taken
+        // 2^28-number pieces: the bucket mode takes about 2.5 ps per number
+        // plus 11 ps per prime up to the root, Miller-Rabin about 12 ps per
+        // number, so buckets win while pi(root) < 0.85 len (pi(root) is taken
         // as root / ln root, a few percent low).
         const double pi_root = (double)root / std::log((double)root + 2.0);
-        const bool bucket = root > ((uint64_t)1 << BUCKET_FROM_LOG2) && pi_root < 0.6 * (double)piece;
+        const bool bucket = root > ((uint64_t)1 << BUCKET_FROM_LOG2) && pi_root < 0.8 * (double)piece;
         hipError_t e = hipSuccess;
         if (bucket) {
             const unsigned grid = (unsigned)((piece + RANGE_SEG - 1) / RANGE_SEG);
             const uint64_t words = (root >> 6) + 1 - ((BUCKET_SMALL + 1) >> 6);
-            const unsigned groups = (unsigned)std::max<uint64_t>(
-                1, std::min<uint64_t>(MAX_BUCKET_GROUPS, words / 1024));
+            // groups of 1024 threads, two per CU (their LDS allows it): one
+            // per 1024 table words, at most MAX_BUCKET_GROUPS, and half of
+            // that for roots below 2^26 (fewer words per group do not pay
+            // for the longer count array and scans) and for pieces of more
+            // than 512 segments (whose count array grows with groups x
+            // segments); measured on 2^28 and 2^30 numbers at 2^48 .. 2^64
+            const uint64_t gmax = grid > 512 || words < ((uint64_t)1 << 20) ? MAX_BUCKET_GROUPS / 2
+                                                                            : MAX_BUCKET_GROUPS;
+            const unsigned groups =
+                (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(gmax, words / 1024));
             // counts (+ total) and the scan's tile sums (+ total)
             const uint64_t n = (uint64_t)grid * groups;
             st = ensure_range_ws(sw->rws, n + 1 + n / 8192 + 2, bucket_hit_bound(piece, root), s);
@@ -699,9 +707,12 @@ int isprime_range_u64(uint64_t lo, uint8_t *out, size_t len, void *stream)
             ma.grid_c = grid;
             e = launch_range_sieve(lo + off, out + off, piece, grid, classify_chunk(piece, grid),
                                    0, ds, sw->ws, sw->rws, s);
-            if (e == hipSuccess)
+            // every segment of a piece whose square root is below 2^25 is
+            // decided by the sieve alone: no survivors, no Miller-Rabin
+            const bool complete = root < ((uint64_t)1 << RANGE_PRIME_LOG2);
+            if (e == hipSuccess && !complete)
                 e = launch_mr1(ma, t.mr_block, s);
-            if (e == hipSuccess)
+            if (e == hipSuccess && !complete)
                 e = t.rest_test ? launch_lucas(ma, ds.cus, t.mr_blocks_per_cu, grid1, t.mr_block, s)
                                 : launch_mr2(ma, ds.cus, t.mr_blocks_per_cu, grid1, t.mr_block,
                                              t.mr_window, s);

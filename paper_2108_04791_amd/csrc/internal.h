@@ -40,7 +40,7 @@ constexpr int RANGE_LIST_GROUPS = 512;    // workgroups of the list build
 // segment of RANGE_SEG numbers)
 constexpr uint32_t BUCKET_SMALL = (uint32_t)1 << 19;
 constexpr int MAX_BUCKET_SEGS = (int)(RANGE_PIECE / RANGE_SEG);  // 2048
-constexpr int MAX_BUCKET_GROUPS = 256;
+constexpr int MAX_BUCKET_GROUPS = 512;
 constexpr int BUCKET_FROM_LOG2 = 23;  // bucket mode for pieces whose root exceeds 2^23
 
 // Device-resident descriptor of a batched call.  The arrays follow the

@@ -37,7 +37,7 @@ namespace isp {
 
 namespace {
 
-constexpr int RANGE_THREADS = 512;
+constexpr int RANGE_THREADS = 1024;
 constexpr uint32_t WAVE_PRIME_LIMIT = 8192;  // primes below this: wavefront per prime
 constexpr int PRESIEVED = 10;                 // 3 .. 31: index of 37 in the prime list
 constexpr uint32_t SMALL_PRIMES[PRESIEVED] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
@@ -528,11 +528,6 @@ constexpr int BUCKET_THREADS = 1024;
 // 2y / ln y primes (Montgomery and Vaughan, Mathematika 20, 1973): 985 for
 // y = 4096; a chunk that still had more would take the per-lane path.
 constexpr uint32_t BUCKET_PBUF = 1024;
-// Table words are loaded BUCKET_PREF chunks at a time per wavefront (into
-// LDS): the wait for a load also waits for the wavefront's earlier stores
-// (one counter covers both), so the fill pass waits once per BUCKET_PREF
-// chunks instead of once per chunk.
-constexpr uint32_t BUCKET_PREF = 16;
 
 // Every odd multiple of p in the piece, each counted in (FILL: written to)
 // the bucket of its segment.  The lanes of a wavefront hold consecutive
@@ -580,7 +575,6 @@ __global__ void __launch_bounds__(BUCKET_THREADS) range_bucket_kernel(BucketArgs
 {
     __shared__ uint32_t cnt[MAX_BUCKET_SEGS];
     __shared__ uint32_t pbuf[BUCKET_THREADS / 64][BUCKET_PBUF];
-    __shared__ uint32_t pref[BUCKET_THREADS / 64][64 * BUCKET_PREF];
     __shared__ uint64_t wrange[2];
     const uint32_t groups = gridDim.x;
     for (uint32_t g = threadIdx.x; g < a.nseg; g += blockDim.x)
@@ -603,7 +597,6 @@ __global__ void __launch_bounds__(BUCKET_THREADS) range_bucket_kernel(BucketArgs
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t nwaves = blockDim.x >> 6;
     uint32_t *buf = pbuf[wave];
-    uint32_t *words = pref[wave];
     auto take = [&](uint32_t p) {
         if (p > BUCKET_SMALL && p <= a.root)
             bucket_hits<FILL>(a, p, lane, cnt);
@@ -647,28 +640,10 @@ __global__ void __launch_bounds__(BUCKET_THREADS) range_bucket_kernel(BucketArgs
             }
         }
     };
-    // the wavefronts take the chunks in turn (wavefront v: chunks v, v +
-    // nwaves, ...), BUCKET_PREF of them at a time; lane l loads (and later
-    // reads) word l of each
     const uint64_t nch = we > wb ? (we - wb + 63) / 64 : 0;
-    for (uint64_t c0 = 0; c0 < nch; c0 += (uint64_t)BUCKET_PREF * nwaves) {
-        // (unconditional loads from clamped addresses, so all of them are
-        // in flight together)
-        uint32_t v[BUCKET_PREF];
-#pragma unroll
-        for (uint32_t c = 0; c < BUCKET_PREF; ++c) {
-            const uint64_t w = wb + 64 * (c0 + (uint64_t)c * nwaves + wave) + lane;
-            v[c] = a.table[w < we ? w : we - 1];
-        }
-#pragma unroll
-        for (uint32_t c = 0; c < BUCKET_PREF; ++c)
-            words[64 * c + lane] = wb + 64 * (c0 + (uint64_t)c * nwaves + wave) + lane < we ? v[c] : 0u;
-        for (uint32_t c = 0; c < BUCKET_PREF; ++c) {
-            const uint64_t ch = c0 + (uint64_t)c * nwaves + wave;
-            if (ch >= nch)
-                break;
-            chunk(wb + 64 * ch, words[64 * c + lane]);
-        }
+    for (uint64_t ch = wave; ch < nch; ch += nwaves) {
+        const uint64_t w = wb + 64 * ch + lane;
+        chunk(wb + 64 * ch, w < we ? a.table[w] : 0u);
     }
     if (!FILL) {
         __syncthreads();
