@@ -223,15 +223,16 @@ def bench_intervals(isp, torch, reps: int = 5, array_call: bool = True) -> dict:
     """The interval call above 2^32, where each workgroup sieves a segment of
     2^19 numbers in LDS, in each of its modes: segments decided by the primes
     up to their square root (2^34, 2^44), the bucket sieve of the primes
-    above 2^19 (2^50, 2^63), and the primes below 2^22 followed by
-    Miller-Rabin on the survivors (2^64 - 2^28); each against the array call
-    on the same values."""
+    above 2^19 (2^50, 2^63, 2^64 - 2^28), and, for an interval short next
+    to the number of primes up to its square root, the primes below 2^22
+    followed by Miller-Rabin on the survivors (2^24 numbers at 2^63); each
+    against the array call on the same values."""
     stream = torch.cuda.current_stream()
     res = {}
-    for name, lo in (("2^34+[0,2^28)", 1 << 34), ("2^44+[0,2^28)", 1 << 44),
-                     ("2^50+[0,2^28)", 1 << 50), ("2^63+[0,2^28)", 1 << 63),
-                     ("2^64-2^28+[0,2^28)", (1 << 64) - (1 << 28))):
-        length = 1 << 28
+    for name, lo, length in (("2^34+[0,2^28)", 1 << 34, 1 << 28), ("2^44+[0,2^28)", 1 << 44, 1 << 28),
+                             ("2^50+[0,2^28)", 1 << 50, 1 << 28), ("2^63+[0,2^28)", 1 << 63, 1 << 28),
+                             ("2^64-2^28+[0,2^28)", (1 << 64) - (1 << 28), 1 << 28),
+                             ("2^63+[0,2^24)", 1 << 63, 1 << 24)):
         rout = torch.empty(length, dtype=torch.bool, device="cuda")
         rms = _time_ms(torch, stream, lambda: isp.isprime_range(lo, length, rout, stream), reps)
         if not array_call:
