@@ -70,7 +70,11 @@ void isp_shutdown(void);
  *   out  device pointer to len bytes, each written 0 or 1
  *   len  0 returns ISP_OK without launching
  * n == NULL or out == NULL with len > 0 -> ISP_EINVAL.  n and out must not
- * overlap.  Uses the calling thread's current HIP device.
+ * overlap.  Uses the calling thread's current HIP device.  Calls of at most
+ * 65,536 elements run as one fused kernel (one element per thread, the
+ * seven bases in the element's own lane); larger calls, and calls with the
+ * Baillie-PSW alternative selected, as the classify / base-2 / remaining-
+ * bases kernels.  The bytes are the same either way.
  * Paper: section 1 (inputs and outputs of isprime_fast), sections 2-6. */
 int isprime_u64(const uint64_t *n, uint8_t *out, size_t len, void *stream);
 
@@ -151,7 +155,8 @@ int isp_table(int device, const uint32_t **table, size_t *words);
 
 /* Counters of the last isprime_u64 / batched call on `stream`, read back
  * synchronously (the stream is synchronised): survivors of the trial filter
- * and base-2 passers sent to the remaining six bases. */
+ * and base-2 passers sent to the remaining six bases.  A call that ran as
+ * the fused kernel keeps no counters: both read 0. */
 int isp_last_counts(void *stream, uint64_t *survivors, uint64_t *candidates);
 
 /* Per-stage timing with HIP events, for measurement.  While enabled, every

@@ -26,6 +26,7 @@
 // down to 33), so a wavefront of the Miller-Rabin kernels sees values of
 // (nearly) one bit length and its lanes run the same number of squarings.
 #include "internal.h"
+#include "mr_lane.h"
 
 namespace isp {
 
@@ -332,7 +333,74 @@ hipError_t launch_classify_t(const ClassifyArgs &a, unsigned grid, int block, in
     }
 }
 
+// A small array in one launch.  Each element gets a team of 8 consecutive
+// lanes (8 teams per wavefront): every lane classifies it as classify_pass
+// does (table lookup below 2^32, the trial filter above) and, for a survivor
+// of the filter, runs the strong test to base 2; lanes 0..5 of the team then
+// take one of the six other bases each.  The element is prime when all
+// eight lanes pass (one wavefront ballot).  The call costs one launch and
+// about two exponentiations of latency, where the three-kernel path costs
+// three launches; throughput is not the concern at these sizes.
+template <int NF>
+__global__ void __launch_bounds__(SMALL_BLOCK) small_kernel(const uint64_t *__restrict__ n,
+                                                         uint8_t *__restrict__ out, uint32_t len,
+                                                         const uint32_t *__restrict__ table)
+{
+    constexpr uint32_t BASES6[6] = {325u, 9375u, 28178u, 450775u, 9780504u, 1795265022u};
+    __shared__ uint64_t tbl[8 * SMALL_BLOCK];  // each lane's window table, by column
+    const uint32_t gid = blockIdx.x * SMALL_BLOCK + threadIdx.x;
+    const uint32_t i = gid / SMALL_TEAM, k = gid % SMALL_TEAM;
+    const uint64_t v = i < len ? n[i] : 0;  // 0: decided (not prime) at once
+    const int c = classify_one<NF>(v, table);
+    bool ok = true;
+    if (c == 2) {
+        const LaneMr m = lane_mr(v);
+        ok = sprp2_lane(m);
+        if (ok && k < 6)
+            ok = sprp_lane(m, r2_mod_n(m.c), BASES6[k], tbl, threadIdx.x, SMALL_BLOCK);
+    }
+    const uint64_t pass = __ballot(ok);
+    const unsigned first = (threadIdx.x & 63u) & ~(SMALL_TEAM - 1u);
+    if (k == 0 && i < len)
+        out[i] = (uint8_t)(c == 1 || (c == 2 && ((pass >> first) & 0xffu) == 0xffu));
+}
+
 }  // namespace
+
+hipError_t launch_small(const uint64_t *n, uint8_t *out, size_t len, const uint32_t *table,
+                        int nfilter, hipStream_t s)
+{
+    if (len == 0 || len > SMALL_MAX)
+        return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)((len * SMALL_TEAM + SMALL_BLOCK - 1) / SMALL_BLOCK);
+    const uint32_t m = (uint32_t)len;
+    switch (nfilter) {
+    case 0:
+        small_kernel<0><<<grid, SMALL_BLOCK, 0, s>>>(n, out, m, table);
+        break;
+    case 8:
+        small_kernel<8><<<grid, SMALL_BLOCK, 0, s>>>(n, out, m, table);
+        break;
+    case 16:
+        small_kernel<16><<<grid, SMALL_BLOCK, 0, s>>>(n, out, m, table);
+        break;
+    case 24:
+        small_kernel<24><<<grid, SMALL_BLOCK, 0, s>>>(n, out, m, table);
+        break;
+    case 32:
+        small_kernel<32><<<grid, SMALL_BLOCK, 0, s>>>(n, out, m, table);
+        break;
+    case 48:
+        small_kernel<48><<<grid, SMALL_BLOCK, 0, s>>>(n, out, m, table);
+        break;
+    case 64:
+        small_kernel<64><<<grid, SMALL_BLOCK, 0, s>>>(n, out, m, table);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_classify(const ClassifyArgs &a, unsigned grid, int block, int ept, hipStream_t s)
 {

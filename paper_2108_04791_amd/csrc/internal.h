@@ -26,6 +26,11 @@ struct Survivor {
 // Largest grid of the classify and Miller-Rabin kernels: their per-block
 // counts are scanned in LDS by the consumer.
 constexpr int MAX_GRID = 4096;
+// Plain calls of at most SMALL_MAX elements run as one fused kernel (a team
+// of SMALL_TEAM lanes per element, SMALL_BLOCK threads per workgroup).
+constexpr size_t SMALL_MAX = 65536;
+constexpr int SMALL_BLOCK = 256;
+constexpr unsigned SMALL_TEAM = 8;
 
 // Numbers per workgroup segment of the interval sieve (LDS holds the odd
 // ones: 2^18 bits), and numbers per piece of an interval call.
@@ -149,6 +154,8 @@ hipError_t launch_sieve(DeviceState &ds, hipStream_t s);
 
 hipError_t launch_classify(const ClassifyArgs &a, unsigned grid, int block, int ept,
                            hipStream_t s);
+hipError_t launch_small(const uint64_t *n, uint8_t *out, size_t len, const uint32_t *table,
+                        int nfilter, hipStream_t s);
 hipError_t launch_mr1(const MrArgs &a, int block, hipStream_t s);
 hipError_t launch_mr2(const MrArgs &a, int cus, int per_cu, unsigned max_grid, int block,
                       int window, hipStream_t s);

@@ -568,8 +568,10 @@ __device__ __forceinline__ void bucket_hits(const BucketArgs &a, uint32_t p, uin
 // Count pass (FILL false): cnt[g] counts this group's hits in segment g and
 // goes to counts[group * nseg + g] (group-major, so that each group's hits
 // land in one contiguous stretch of `hits`).  Fill pass: cnt[g] starts at the
-// scanned offset of (g, group), so each atomic increment yields the hit's
-// place in `hits` directly.
+// scanned offset of (group, g), so each atomic increment yields the hit's
+// place in `hits` directly.  The wavefront-scope fences below order LDS
+// accesses between the lanes of one wavefront (whose LDS operations complete
+// in order) without waiting for its global stores.
 template <bool FILL>
 __global__ void __launch_bounds__(BUCKET_THREADS) range_bucket_kernel(BucketArgs a)
 {

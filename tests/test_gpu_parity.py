@@ -177,8 +177,9 @@ def test_c3_full(isp, oracle_table):
 
 def test_counts_match_host_accounting(isp):
     """Survivors = odd elements >= 2^32 with no factor among the filter
-    primes; candidates = survivors passing the base-2 round."""
-    a = W.c2_mr64(1 << 16)
+    primes; candidates = survivors passing the base-2 round (a call above
+    the fused kernel's size, which keeps no counters)."""
+    a = W.c2_mr64((1 << 16) + 1)
     cfg = isp.get_config()
     gpu_isprime(isp, a)
     surv, cand = isp.last_counts()
@@ -206,7 +207,8 @@ def test_counts_match_host_accounting(isp):
     dict(mr_block=512, mr_blocks_per_cu=4, mr_window=2),
 ])
 def test_configs_do_not_change_bits(isp, cfg):
-    a = np.concatenate([np.array(EDGES, dtype=np.uint64), W.c3_mixed(30011, start=99),
+    # above the fused kernel's size, so every launch parameter is in play
+    a = np.concatenate([np.array(EDGES, dtype=np.uint64), W.c3_mixed(70011, start=99),
                         W.chernick_values()])
     prev = isp.set_config(**cfg)
     try:
@@ -222,6 +224,20 @@ def test_permutation_metamorphic(isp):
     g1 = gpu_isprime(isp, a)
     g2 = gpu_isprime(isp, a[perm])
     assert np.array_equal(g1[perm], g2)
+
+
+@pytest.mark.parametrize("size", [1, 64, 65535, 65536, 65537])
+def test_fused_and_three_kernel_paths(isp, size):
+    """Calls of up to 65,536 elements run as one fused kernel, larger ones as
+    the three kernels: both equal the oracle on base-2 pseudoprimes, primes
+    and composites of every length, at and around the size where the path
+    changes, and the smallest call reads no counters."""
+    base = np.concatenate([W.chernick_values(), np.array(EDGES, dtype=np.uint64),
+                           W.c2_mr64(70000, start=3), W.c3_mixed(70000, start=4)])
+    a = base[:size]
+    assert_same(a, gpu_isprime(isp, a), expect(a, use_table=False), "size %d" % size)
+    if size <= 65536:
+        assert isp.last_counts() == (0, 0)
 
 
 def test_two_streams(isp):
