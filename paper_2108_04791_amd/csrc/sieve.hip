@@ -15,10 +15,12 @@
 //                       in LDS and writes the 6541 odd primes in order.
 //   sieve_kernel        one workgroup per 32 KiB segment (2^18 odd numbers).
 //                       Multiples of 3..31 come from a periodic word mask
-//                       (pre-sieve); each larger base prime p is crossed off
-//                       from max(p^2, segment start) by a whole wavefront,
-//                       lane l taking the multiples l, l+64, l+128, ... of
-//                       the stride p (in bit units), with LDS atomic ANDs.
+//                       (pre-sieve); each base prime p below 8192 is crossed
+//                       off from max(p^2, segment start) by a whole
+//                       wavefront, lane l taking the multiples l, l+64,
+//                       l+128, ... of the stride p (in bit units), and each
+//                       larger one (at most 32 multiples per segment) by one
+//                       thread, with LDS atomic ANDs.
 #include "internal.h"
 #include "mont.h"
 
@@ -113,21 +115,39 @@ __global__ void __launch_bounds__(SIEVE_THREADS) sieve_kernel(uint32_t *__restri
     }
     __syncthreads();
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
+    // the wavefront index as a scalar, so the per-prime work of the
+    // wavefront loop runs on the scalar unit
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nwaves = blockDim.x >> 6;
     const int np = (int)*pcount;
     const uint64_t hi = (uint64_t)lo + 2ull * SEG_BITS;  // exclusive
-    for (int k = FIRST_CROSSED + wave; k < np; k += nwaves) {
+    // bit index of p's first odd multiple at or above max(p^2, lo), or
+    // SEG_BITS or more when none falls in the segment (lo + p - 1 < 2^32:
+    // lo <= 2^32 - 2^19 + 1 and p < 2^16)
+    auto first_bit = [&](uint32_t p) -> uint32_t {
+        const uint64_t pp = (uint64_t)p * p;
+        if (pp >= hi)
+            return (uint32_t)SEG_BITS;
+        uint64_t start = pp;
+        if (pp < lo)
+            start = (uint64_t)(((lo + p - 1) / p) | 1u) * p;  // odd multiples only
+        return (uint32_t)((start - lo) >> 1);
+    };
+    // primes 37 .. 8191 (the first 1027 odd primes): one wavefront per prime
+    constexpr int WAVE_PRIMES = 1027;
+    const int k_split = np < WAVE_PRIMES ? np : WAVE_PRIMES;
+    for (int k = FIRST_CROSSED + wave; k < k_split; k += nwaves) {
         const uint32_t p = primes[k];
-        uint64_t start = (uint64_t)p * p;
-        if (start >= hi)
+        if ((uint64_t)p * p >= hi)
             break;  // primes increase, so every later one starts beyond too
-        if (start < lo) {
-            uint32_t q = (uint32_t)(((uint64_t)lo + p - 1) / p);
-            q |= 1u;  // odd multiples only
-            start = (uint64_t)q * p;
-        }
-        for (uint32_t j = (uint32_t)((start - lo) >> 1) + (uint32_t)lane * p; j < (uint32_t)SEG_BITS;
-             j += 64u * p)
+        for (uint32_t j = first_bit(p) + (uint32_t)lane * p; j < (uint32_t)SEG_BITS; j += 64u * p)
+            atomicAnd(&seg[j >> 5], ~(1u << (j & 31)));
+    }
+    // larger primes: at most 32 multiples in the segment, one thread each
+    for (int k = k_split + (int)threadIdx.x; k < np; k += blockDim.x) {
+        const uint32_t p = primes[k];
+        for (uint32_t j = first_bit(p); j < (uint32_t)SEG_BITS; j += p)
             atomicAnd(&seg[j >> 5], ~(1u << (j & 31)));
     }
     __syncthreads();
