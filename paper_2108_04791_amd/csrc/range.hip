@@ -316,13 +316,13 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
     // first bit index of the odd multiples of p at or above max(o0, p^2), or
     // "none" (all offsets are taken from o0, so nothing wraps near 2^64)
     const uint64_t span = s_last - o0;  // valid only when nbits > 0
-    auto first_bit = [&](uint32_t k, uint32_t p) -> uint64_t {
+    auto first_bit = [&](uint32_t p, uint64_t inv) -> uint64_t {
         const uint64_t pp = (uint64_t)p * p;  // < 2^50, odd
         uint64_t off;
         if (pp >= o0) {
             off = pp - o0;
         } else {
-            const uint64_t r = mod_small(o0, p, a.inv[k]);
+            const uint64_t r = mod_small(o0, p, inv);
             off = r ? p - r : 0;  // o0 + off: first multiple of p at or above o0
             if (off & 1)
                 off += p;         // o0 is odd: an odd offset gives an even multiple
@@ -344,7 +344,7 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
     }
     for (uint32_t k = PRESIEVED + wave; k < k_split; k += nwaves) {
         const uint32_t p = a.primes[k];
-        const uint64_t j0 = first_bit(k, p);
+        const uint64_t j0 = first_bit(p, a.inv[k]);
         if (j0 >= nbits)
             continue;
         // bit indices below 2^18: 32-bit arithmetic
@@ -352,14 +352,33 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
         for (uint32_t j = (uint32_t)j0 + (uint32_t)lane * p; j < nbits; j += stride)
             atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
     }
-    // larger primes: one thread per prime
-    for (uint32_t k = k_split + tid; k < np; k += blockDim.x) {
-        const uint32_t p = a.primes[k];
-        const uint64_t j0 = first_bit(k, p);
-        if (j0 >= nbits)
-            continue;
-        for (uint32_t j = (uint32_t)j0; j < nbits; j += p)
-            atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
+    // larger primes: one thread per prime; the thread's next prime and its
+    // constant are loaded while the current one is crossed off (the loads'
+    // latency, not the arithmetic, bounds this loop)
+    {
+        uint32_t k = k_split + tid;
+        uint32_t p = 0;
+        uint64_t inv = 0;
+        if (k < np) {
+            p = a.primes[k];
+            inv = a.inv[k];
+        }
+        while (k < np) {
+            const uint32_t kn = k + blockDim.x;
+            uint32_t pn = 0;
+            uint64_t invn = 0;
+            if (kn < np) {
+                pn = a.primes[kn];
+                invn = a.inv[kn];
+            }
+            const uint64_t j0 = first_bit(p, inv);
+            if (j0 < nbits)
+                for (uint32_t j = (uint32_t)j0; j < nbits; j += p)
+                    atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
+            k = kn;
+            p = pn;
+            inv = invn;
+        }
     }
     // bucket mode: the hits of the primes above BUCKET_SMALL in this segment
     if (buckets) {
