@@ -304,6 +304,9 @@ int run_plain(const uint64_t *n, uint8_t *out, size_t len, const DeviceState &ds
     } else {
         if (e == hipSuccess)
             e = launch_classify(ca, grid_c, t.classify_block, t.classify_ept, s);
+        if (e == hipSuccess)
+            e = launch_filter2(ws.surv, ws.counts, grid_c, classify_chunk(len, grid_c),
+                               t.filter_primes, s);
         mark(1);
         if (e == hipSuccess)
             e = launch_mr1(ma, t.mr_block, s);

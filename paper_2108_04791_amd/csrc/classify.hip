@@ -37,6 +37,9 @@ typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(8)));
 // Compile-time table of the first odd primes with their inverses modulo 2^64
 // and the bound floor((2^64 - 1) / p), so the unrolled filter below uses
 // immediate constants and issues no memory load.
+constexpr int DENSE_TO = 64;  // the second stage ends at the 64th odd prime (313)
+constexpr int FILTER2_BLOCK = 256;
+
 constexpr bool ce_is_prime(uint64_t p)
 {
     for (uint64_t d = 3; d * d <= p; d += 2)
@@ -365,7 +368,86 @@ __global__ void __launch_bounds__(SMALL_BLOCK) small_kernel(const uint64_t *__re
         out[i] = (uint8_t)(c == 1 || (c == 2 && ((pass >> first) & 0xffu) == 0xffu));
 }
 
+// Second trial-filter stage, between classify and the base-2 round: one
+// workgroup per classify region compacts the region's survivors in place
+// (order kept, so the bit-length order survives) to those with no factor
+// among the odd primes nf .. DENSE_TO - 1, and rewrites its count.  Only the
+// survivors of the first stage (about a fifth of the elements) pay for these
+// primes, one thread per survivor, and a prime p removes 1/p of them, each of
+// which would otherwise cost a base-2 exponentiation of ~1,700
+// instructions: worth it up to p ~ 300.
+template <int NF>
+__global__ void __launch_bounds__(FILTER2_BLOCK) filter2_kernel(Survivor *__restrict__ surv,
+                                                               uint32_t *__restrict__ counts,
+                                                               uint64_t chunk)
+{
+    __shared__ uint32_t wave_cnt[FILTER2_BLOCK / 64];
+    const uint32_t g = blockIdx.x;
+    Survivor *region = surv + (uint64_t)g * chunk;
+    const uint32_t count = counts[g];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t kept = 0;  // entries kept so far (block-uniform)
+    for (uint32_t r0 = 0; r0 < count; r0 += FILTER2_BLOCK) {
+        const uint32_t i = r0 + threadIdx.x;
+        Survivor e;
+        e.n = 0;
+        e.out = nullptr;
+        bool keep = false;
+        if (i < count) {
+            e = region[i];
+            bool divisible = false;
+#pragma unroll
+            for (int k = NF; k < DENSE_TO; ++k)
+                divisible |= e.n * FILTER.inv[k] <= FILTER.lim[k];
+            keep = !divisible;
+        }
+        const uint64_t m = __ballot(keep);
+        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        if (lane == 0)
+            wave_cnt[wave] = (uint32_t)__popcll(m);
+        __syncthreads();  // every entry of this round is read; the counts are in
+        uint32_t before = 0, total = 0;
+        for (int w = 0; w < FILTER2_BLOCK / 64; ++w) {
+            const uint32_t c = wave_cnt[w];
+            before += w < wave ? c : 0u;
+            total += c;
+        }
+        // positions below this round's first entry: nothing unread is overwritten
+        if (keep)
+            region[kept + before + (uint32_t)__popcll(m & lt)] = e;
+        kept += total;
+        __syncthreads();  // wave_cnt is rewritten by the next round
+    }
+    if (threadIdx.x == 0)
+        counts[g] = kept;
+}
+
 }  // namespace
+
+hipError_t launch_filter2(Survivor *surv, uint32_t *counts, unsigned grid, uint64_t chunk, int nf,
+                          hipStream_t s)
+{
+    switch (nf) {
+    case 8:
+        filter2_kernel<8><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, chunk);
+        break;
+    case 16:
+        filter2_kernel<16><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, chunk);
+        break;
+    case 24:
+        filter2_kernel<24><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, chunk);
+        break;
+    case 32:
+        filter2_kernel<32><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, chunk);
+        break;
+    case 48:
+        filter2_kernel<48><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, chunk);
+        break;
+    default:
+        return hipSuccess;  // no first stage (0) or nothing left to test (64)
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_small(const uint64_t *n, uint8_t *out, size_t len, const uint32_t *table,
                         int nfilter, hipStream_t s)

@@ -22,7 +22,7 @@ import time
 
 import torch
 
-from . import get_config, isprime_batched, isprime_into, set_config
+from . import Batch, get_config, isprime_into, set_config
 
 SPACE = {
     "classify_ept": [2, 4, 8],
@@ -65,10 +65,11 @@ def tune(arrays, reps: int = 7, sweeps: int = 2, log=print) -> dict:
     """
     batched = len(arrays) > 1
     outs = [torch.empty(a.shape, dtype=torch.uint8, device=a.device) for a in arrays]
+    prepared = Batch(arrays, outs) if batched else None  # pointer arrays built once
 
     def run():
         if batched:
-            isprime_batched(arrays, outs)
+            prepared.run()
         else:
             isprime_into(arrays[0], outs[0])
 

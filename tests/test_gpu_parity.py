@@ -177,13 +177,17 @@ def test_c3_full(isp, oracle_table):
 
 def test_counts_match_host_accounting(isp):
     """Survivors = odd elements >= 2^32 with no factor among the filter
-    primes; candidates = survivors passing the base-2 round (a call above
-    the fused kernel's size, which keeps no counters)."""
+    primes (the first 64 odd primes when the filter is on); candidates =
+    survivors passing the base-2 round (a call above the fused kernel's
+    size, which keeps no counters)."""
     a = W.c2_mr64((1 << 16) + 1)
     cfg = isp.get_config()
     gpu_isprime(isp, a)
     surv, cand = isp.last_counts()
+    # the classify kernel tests the first filter_primes odd primes and the
+    # second stage the rest of the first 64
     F = cfg["filter_primes"]
+    F = 0 if F <= 0 else max(F, 64)
     primes = [p for p in range(3, 2000, 2) if oracle.trial_is_prime(p)][:F]
     big = a[(a >= np.uint64(1 << 32)) & ((a & np.uint64(1)) == 1)]
     keep = np.ones(big.size, dtype=bool)
