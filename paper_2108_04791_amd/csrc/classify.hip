@@ -25,6 +25,10 @@
 // decreasing bit length with an LDS counting sort (32 keys, bit lengths 64
 // down to 33), so a wavefront of the Miller-Rabin kernels sees values of
 // (nearly) one bit length and its lanes run the same number of squarings.
+//
+// Also here: filter2_kernel, the second filter stage over each region's
+// survivors (the rest of the first 64 odd primes), and small_kernel, which
+// decides a call of at most SMALL_MAX elements in one launch.
 #include "internal.h"
 #include "mr_lane.h"
 
