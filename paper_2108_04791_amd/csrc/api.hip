@@ -305,8 +305,7 @@ int run_plain(const uint64_t *n, uint8_t *out, size_t len, const DeviceState &ds
         if (e == hipSuccess)
             e = launch_classify(ca, grid_c, t.classify_block, t.classify_ept, s);
         if (e == hipSuccess)
-            e = launch_filter2(ws.surv, ws.counts, grid_c, classify_chunk(len, grid_c),
-                               t.filter_primes, s);
+            e = launch_filter2(ws.surv, ws.counts, grid_c, len, nullptr, t.filter_primes, s);
         mark(1);
         if (e == hipSuccess)
             e = launch_mr1(ma, t.mr_block, s);
@@ -438,6 +437,9 @@ int build_graph_one(BatchCtx &c, const DeviceState &ds, const Tuning &t, int k)
                                    c.cap_stream);
     if (ee == hipSuccess)
         ee = launch_classify(ca, grid_c, t.classify_block, t.classify_ept, c.cap_stream);
+    if (ee == hipSuccess)
+        ee = launch_filter2(c.ws.surv, c.ws.counts, grid_c, 0, &d->total, t.filter_primes,
+                            c.cap_stream);
     if (ee == hipSuccess)
         ee = launch_mr1(ma, t.mr_block, c.cap_stream);
     if (ee == hipSuccess)

@@ -383,10 +383,13 @@ __global__ void __launch_bounds__(SMALL_BLOCK) small_kernel(const uint64_t *__re
 template <int NF>
 __global__ void __launch_bounds__(FILTER2_BLOCK) filter2_kernel(Survivor *__restrict__ surv,
                                                                uint32_t *__restrict__ counts,
-                                                               uint64_t chunk)
+                                                               uint64_t total,
+                                                               const uint64_t *total_dev)
 {
     __shared__ uint32_t wave_cnt[FILTER2_BLOCK / 64];
     const uint32_t g = blockIdx.x;
+    // the regions of the classify grid (of the same size as this grid)
+    const uint64_t chunk = classify_chunk(total_dev ? *total_dev : total, gridDim.x);
     Survivor *region = surv + (uint64_t)g * chunk;
     const uint32_t count = counts[g];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -428,24 +431,24 @@ __global__ void __launch_bounds__(FILTER2_BLOCK) filter2_kernel(Survivor *__rest
 
 }  // namespace
 
-hipError_t launch_filter2(Survivor *surv, uint32_t *counts, unsigned grid, uint64_t chunk, int nf,
-                          hipStream_t s)
+hipError_t launch_filter2(Survivor *surv, uint32_t *counts, unsigned grid, uint64_t total,
+                          const uint64_t *total_dev, int nf, hipStream_t s)
 {
     switch (nf) {
     case 8:
-        filter2_kernel<8><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, chunk);
+        filter2_kernel<8><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, total, total_dev);
         break;
     case 16:
-        filter2_kernel<16><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, chunk);
+        filter2_kernel<16><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, total, total_dev);
         break;
     case 24:
-        filter2_kernel<24><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, chunk);
+        filter2_kernel<24><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, total, total_dev);
         break;
     case 32:
-        filter2_kernel<32><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, chunk);
+        filter2_kernel<32><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, total, total_dev);
         break;
     case 48:
-        filter2_kernel<48><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, chunk);
+        filter2_kernel<48><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, total, total_dev);
         break;
     default:
         return hipSuccess;  // no first stage (0) or nothing left to test (64)

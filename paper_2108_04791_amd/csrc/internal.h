@@ -156,8 +156,9 @@ hipError_t launch_classify(const ClassifyArgs &a, unsigned grid, int block, int 
                            hipStream_t s);
 hipError_t launch_small(const uint64_t *n, uint8_t *out, size_t len, const uint32_t *table,
                         int nfilter, hipStream_t s);
-hipError_t launch_filter2(Survivor *surv, uint32_t *counts, unsigned grid, uint64_t chunk, int nf,
-                          hipStream_t s);
+// total_dev: where to read the element count (batched calls), else total.
+hipError_t launch_filter2(Survivor *surv, uint32_t *counts, unsigned grid, uint64_t total,
+                          const uint64_t *total_dev, int nf, hipStream_t s);
 hipError_t launch_mr1(const MrArgs &a, int block, hipStream_t s);
 hipError_t launch_mr2(const MrArgs &a, int cus, int per_cu, unsigned max_grid, int block,
                       int window, hipStream_t s);
