@@ -44,6 +44,7 @@ VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 OPS_PER_MONTMUL = 22
 OPS_PER_DOUBLING = 5
 MR_BASES_AFTER_2 = 6
+FILTER_STAGES_TO = 64  # the two filter stages together: the first 64 odd primes
 
 
 # The sources of the array path's kernels (classify, both Miller-Rabin phases,
@@ -112,6 +113,9 @@ def mr_work(a: np.ndarray, prime: np.ndarray, filter_primes: int):
     """Algorithmic work (VALU instructions) of the two Miller-Rabin launches,
     counted for left-to-right binary exponentiation.
 
+    The trial filter is the first `filter_primes` odd primes per element and,
+    when that is on, the rest of the first 64 on its survivors (the second
+    stage), so a survivor here has no factor among the first 64 odd primes.
     Base 2 (every filter survivor): L - 2 Montgomery squarings for bit length
     L and popcount(n - 1) - 1 modular doublings.  Remaining six bases (every
     prime >= 2^32; base-2 pseudoprimes are negligible here): per base, L - 2
@@ -120,7 +124,8 @@ def mr_work(a: np.ndarray, prime: np.ndarray, filter_primes: int):
     """
     big = (a >= np.uint64(1 << 32)) & ((a & np.uint64(1)) == 1)
     keep = big.copy()
-    for p in small_odd_primes(filter_primes):
+    nf = 0 if filter_primes <= 0 else max(filter_primes, FILTER_STAGES_TO)
+    for p in small_odd_primes(nf):
         keep &= (a % np.uint64(p)) != 0
     L = bit_length(a)
     sq2 = int((L[keep] - 2).sum())
