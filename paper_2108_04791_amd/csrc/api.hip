@@ -31,6 +31,10 @@ constexpr int MAX_DEVICES = 64;
 // A plain call is split into pieces of at most this many elements, so the
 // 32-bit device counters never overflow and a workspace stays below 8 GiB.
 constexpr size_t PLAIN_PIECE = (size_t)1 << 28;
+// Interval pieces of fewer segments than this sieve by the primes below
+// 2^PARTIAL_SHORT_LOG2 where the sieve cannot be complete.
+constexpr unsigned PARTIAL_FULL_GRID = 256;
+constexpr int PARTIAL_SHORT_LOG2 = 18;
 // Elements per batched call (its survivors share one 32-bit counter).
 constexpr uint64_t BATCH_MAX_ELEMS = (uint64_t)1 << 30;
 // A plain call over len elements uses at most ceil(len / this) Miller-Rabin
@@ -726,8 +730,12 @@ int isprime_range_u64(uint64_t lo, uint8_t *out, size_t len, void *stream)
             make_args(ds, sw->ws, t, piece, ca, ma, grid_c, grid1);
             ma.total = piece;
             ma.grid_c = grid;
+            // a short piece has few segments, each visiting all the primes below
+            // the bound one after another: a lower bound there costs more
+            // Miller-Rabin on the extra survivors but far less sieve latency
+            const int partial = grid >= PARTIAL_FULL_GRID ? RANGE_PARTIAL_LOG2 : PARTIAL_SHORT_LOG2;
             e = launch_range_sieve(lo + off, out + off, piece, grid, classify_chunk(piece, grid),
-                                   0, ds, sw->ws, sw->rws, s);
+                                   0, ds, sw->ws, sw->rws, s, partial);
             // every segment of a piece whose square root is below 2^25 is
             // decided by the sieve alone: no survivors, no Miller-Rabin
             const bool complete = root < ((uint64_t)1 << RANGE_PRIME_LOG2);

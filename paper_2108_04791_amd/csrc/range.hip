@@ -10,10 +10,12 @@
 // the survivors are exactly the primes.  Above it, a long piece runs in
 // bucket mode (below): the primes above 2^19 up to the square root are
 // sorted into per-segment buckets first, and the segments are complete
-// again.  A short piece is sieved by the odd primes below 2^22 and the
-// survivors (about 3.4% of the numbers: those with no factor below 2^22) go
-// to the same two Miller-Rabin kernels as array inputs, through the same
-// per-workgroup regions and counts.
+// again.  A short piece is sieved by the odd primes below 2^22 (below 2^18
+// when it has fewer than 256 segments, which then run one wave of
+// workgroups and wait on the sieve's latency) and the survivors (about 3.4%
+// of the numbers with no factor below 2^22, 4.5% below 2^18) go to the same
+// two Miller-Rabin kernels as array inputs, through the same per-workgroup
+// regions and counts.
 //
 // Segment layout: workgroup g covers numbers [lo + g*chunk, lo + (g+1)*chunk)
 // with chunk = classify_chunk(len, grid) (a multiple of 64, at most
@@ -219,6 +221,7 @@ struct RangeArgs {
     const uint32_t *hits;       // bit indices within their segment
     uint64_t hit_cap;           // entries allocated in hits
     uint32_t groups;            // 0: no buckets
+    uint32_t partial_log2;      // where the sieve cannot be complete: primes below 2^this
 };
 
 // Integer square root of x < 2^64 (floor), from a double estimate.
@@ -292,14 +295,15 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
     // Crossing off every prime up to the root costs about one reduction per
     // prime and segment; below a root of 2^25 (2 million primes) that is
     // cheaper than Miller-Rabin on the survivors, and the sieve alone decides
-    // the segment.  Above it the segment is sieved by the primes below 2^22
-    // and its survivors (about 3.4% of the numbers) go to Miller-Rabin.
+    // the segment.  Above it the segment is sieved by the primes below
+    // 2^partial_log2 (2^22 for long pieces: about 3.4% of the numbers
+    // survive) and its survivors go to Miller-Rabin.
     // (in bucket mode the primes above BUCKET_SMALL arrive as hits, and every
     // segment is complete)
     const bool buckets = a.groups != 0;
     const bool complete = buckets || root < ((uint64_t)1 << RANGE_PRIME_LOG2);
     const uint64_t bound = buckets ? (root < BUCKET_SMALL ? root : BUCKET_SMALL)
-                           : complete ? root : ((uint64_t)1 << RANGE_PARTIAL_LOG2) - 1;
+                           : complete ? root : ((uint64_t)1 << a.partial_log2) - 1;
     // the list is sorted: use the primes up to `bound`
     uint32_t np = a.nprimes;
     {
@@ -841,9 +845,13 @@ hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsign
 
 hipError_t launch_range_sieve(uint64_t lo, uint8_t *out, uint64_t len, unsigned grid,
                               uint64_t chunk, unsigned groups, const DeviceState &ds,
-                              const Workspace &ws, const RangeWs &rw, hipStream_t s)
+                              const Workspace &ws, const RangeWs &rw, hipStream_t s,
+                              int partial_log2)
 {
+    if (partial_log2 < 17 || partial_log2 > RANGE_PARTIAL_LOG2)
+        return hipErrorInvalidValue;
     RangeArgs a;
+    a.partial_log2 = (uint32_t)partial_log2;
     a.lo = lo;
     a.len = len;
     a.chunk = chunk;
