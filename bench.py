@@ -50,7 +50,7 @@ FILTER_STAGES_TO = 64  # the two filter stages together: the first 64 odd primes
 # The sources of the array path's kernels (classify, both Miller-Rabin phases,
 # the Lucas alternative) and their argument structs: the counter summary is
 # valid while these are unchanged.
-ARRAY_PATH_SOURCES = ("classify.hip", "mr.hip", "mont.h", "internal.h")
+ARRAY_PATH_SOURCES = ("classify.hip", "compact.h", "mr.hip", "mont.h", "internal.h")
 
 
 def kernel_source_hash() -> str:
@@ -260,6 +260,35 @@ def bench_intervals(isp, torch, reps: int = 5, array_call: bool = True) -> dict:
     return res
 
 
+WHEEL_OCTAVES = (33, 34, 36, 38, 40)
+
+
+def bench_wheel(isp, W, torch, reps: int = 3, n: int = 1 << 20) -> dict:
+    """The paper's medium-integer method (trial division on the 2/3/5/7 wheel
+    up to the square root) against Miller-Rabin on the same filter
+    survivors: 2^20 odd values uniform in each octave [2^(b-1), 2^b), one
+    plain call with the wheel stage on (wheel_log2 = 40) and one without."""
+    stream = torch.cuda.current_stream()
+    res = {}
+    for bits in WHEEL_OCTAVES:
+        a = W.odd_band(n, bits)
+        dev = torch.from_numpy(a.view(np.int64)).cuda()
+        out_mr = torch.empty(n, dtype=torch.uint8, device="cuda")
+        out_wh = torch.empty(n, dtype=torch.uint8, device="cuda")
+        mr_ms = _time_ms(torch, stream, lambda: isp.isprime_into(dev, out_mr, stream), reps)
+        prev = isp.set_config(wheel_log2=40)
+        try:
+            wh_ms = _time_ms(torch, stream, lambda: isp.isprime_into(dev, out_wh, stream), reps)
+        finally:
+            isp.set_config(**prev)
+        res["2^%d" % bits] = {"elements": n, "miller_rabin_ms": mr_ms, "wheel_ms": wh_ms,
+                              "wheel_over_mr": wh_ms / mr_ms,
+                              "same_bytes": bool(torch.equal(out_mr, out_wh)),
+                              "primes": int(out_mr.sum().item())}
+        del dev, out_mr, out_wh
+    return res
+
+
 def bench_batched(isp, W, torch, reps: int = 5) -> dict:
     """4096 arrays of log-uniform length in [1, 2^16], magnitude class per
     array: one isprime_u64_batched call (graph replay; its host arrays of
@@ -416,6 +445,8 @@ def main() -> int:
                     help="skip the batched and served measurements")
     ap.add_argument("--intervals-only", action="store_true",
                     help="only time the interval call on its five cases (for profiling its kernels)")
+    ap.add_argument("--wheel-only", action="store_true",
+                    help="only time the wheel stage against Miller-Rabin per octave")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters)")
@@ -445,6 +476,9 @@ def main() -> int:
     if args.intervals_only:
         print(json.dumps({"intervals": bench_intervals(isp, torch, reps=args.steps,
                                                        array_call=False)}))
+        return 0
+    if args.wheel_only:
+        print(json.dumps({"wheel_vs_miller_rabin": bench_wheel(isp, W, torch, reps=args.steps)}))
         return 0
 
     from paper_2108_04791_amd import tune
@@ -541,6 +575,7 @@ def main() -> int:
         isp.set_config(**defaults)
         forms["paper_workloads"] = bench_paper_suite(isp, W, torch)
         forms["intervals"] = bench_intervals(isp, torch)
+        forms["wheel_vs_miller_rabin"] = bench_wheel(isp, W, torch)
 
     cpu = None
     bit_exact = None

@@ -134,6 +134,13 @@ typedef struct {
                                        the paper (default); 1 the strong Lucas test with
                                        Selfridge's parameters (Baillie-PSW, the paper's future
                                        work, section 10.1) -- the same verdicts below 2^64 */
+    int32_t wheel_log2;             /* -1 (default): off.  33..40: every filter survivor below
+                                       2^wheel_log2 is decided by trial division on the
+                                       2/3/5/7 wheel up to its square root (the paper's method
+                                       for medium integers, section 3, Eq. 5-6) instead of
+                                       Miller-Rabin; same verdicts, far more work (it exists to
+                                       measure that crossover).  Calls then skip the fused
+                                       small-array kernel. */
 } isp_config;
 
 /* Read / replace the process-wide configuration (ISP_EINVAL if out of range). */

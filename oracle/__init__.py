@@ -19,6 +19,8 @@ only loads it with ctypes and marshals arguments.  Function map:
 ``find_factor``        O6, Pollard rho (Brent), composite certificate
 ``pratt_certify``      O6, Pratt certificate for primes
 ``numdiv``             O7, Table NumDiv of section 6
+``wheel_is_prime``     O8, trial division on the 2/3/5/7 wheel, section 3
+``wheel_cycle``        the wheel's difference cycle, Eq. 5
 =====================  ====================================================
 """
 from __future__ import annotations
@@ -78,6 +80,9 @@ def _load():
             "oracle_find_factor": (u64, [u64]),
             "oracle_pratt_certify": (i32, [u64]),
             "oracle_numdiv": (u64, [u64]),
+            "oracle_wheel_cycle": (i32, [p]),
+            "oracle_wheel_is_prime": (i32, [u64]),
+            "oracle_wheel_array": (i32, [p, p, u64, i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -189,3 +194,22 @@ def pratt_certify(n: int) -> int:
 
 def numdiv(N: int) -> int:
     return _load().oracle_numdiv(N)
+
+
+def wheel_cycle() -> list:
+    """The 48 differences of the 2/3/5/7 wheel (Eq. 5)."""
+    buf = (ctypes.c_uint8 * 48)()
+    k = _load().oracle_wheel_cycle(buf)
+    return list(buf)[:k]
+
+
+def wheel_is_prime(n: int) -> int:
+    return _load().oracle_wheel_is_prime(n)
+
+
+def wheel_array(n: np.ndarray, nthreads: int | None = None) -> np.ndarray:
+    """O8 alone over an array (threaded)."""
+    n = np.ascontiguousarray(n, dtype=np.uint64)
+    out = np.empty(n.shape, dtype=np.uint8)
+    _load().oracle_wheel_array(n.ctypes.data, out.ctypes.data, n.size, nthreads or os.cpu_count() or 1)
+    return out

@@ -29,6 +29,11 @@
  *                                 relies on the seven-base claim.
  *   O7  oracle_numdiv          -- the division count of MATLAB's isprime on
  *                                 1:N (section 6, Table NumDiv).
+ *   O8  oracle_wheel_is_prime  -- trial division on the 2/3/5/7 wheel of
+ *                                 section 3: 2, 3, 5, 7, then 1 plus the
+ *                                 running sum of the period-210 difference
+ *                                 cycle of Eq. 5 (the Eq. 6 construction),
+ *                                 up to the square root.
  *
  * Readings of the paper taken here:
  *   - Eq. 1 prints "+-1"; Fermat's theorem gives 1.  Eq. 2-3 and the
@@ -200,8 +205,48 @@ int oracle_is_prime(uint64_t n, const uint32_t *table)
     return oracle_mr7(n);
 }
 
+/* ------------------------------------------------------------------ O8 */
+
+/* The difference cycle of the 2/3/5/7 wheel as the paper prints it (section
+ * 3, Eq. 5): 48 gaps between consecutive numbers coprime to 210, starting
+ * from 1, that repeat every 210. */
+static const uint8_t WHEEL_DIFF[48] = {
+    10, 2, 4, 2, 4, 6, 2, 6, 4, 2, 4, 6, 6, 2, 6, 4, 2, 6, 4, 6, 8, 4, 2, 4,
+    2, 4, 8, 6, 4, 6, 2, 4, 6, 2, 6, 6, 4, 2, 4, 6, 2, 6, 4, 2, 4, 2, 10, 2};
+
+/* Copies the cycle out (for the tests that pin it); returns its length. */
+int oracle_wheel_cycle(uint8_t *out)
+{
+    memcpy(out, WHEEL_DIFF, sizeof(WHEEL_DIFF));
+    return (int)sizeof(WHEEL_DIFF);
+}
+
+/* Section 3's medium-integer method: the removed primes 2, 3, 5, 7 are
+ * tried first; then the divisors are 1 + the running sum of the repeated
+ * cycle (11, 13, 17, ...), each tried while d <= floor(sqrt(n)). */
+int oracle_wheel_is_prime(uint64_t n)
+{
+    static const uint64_t removed[4] = {2, 3, 5, 7};
+    if (n < 2)
+        return 0;
+    for (int i = 0; i < 4; ++i) {
+        if (n == removed[i])
+            return 1;
+        if (n % removed[i] == 0)
+            return 0;
+    }
+    uint64_t d = 1;
+    for (int k = 0;; k = (k + 1) % 48) {
+        d += WHEEL_DIFF[k];
+        if (d > n / d)  /* d*d > n: no divisor up to the root */
+            return 1;
+        if (n % d == 0)
+            return 0;
+    }
+}
+
 /* Which per-element function an array call applies. */
-enum { APPLY_IS_PRIME = 0, APPLY_TRIAL = 1, APPLY_MR7 = 2 };
+enum { APPLY_IS_PRIME = 0, APPLY_TRIAL = 1, APPLY_MR7 = 2, APPLY_WHEEL = 3 };
 
 struct chunk {
     const uint64_t *n;
@@ -221,6 +266,8 @@ static void *chunk_worker(void *arg)
             r = oracle_trial_is_prime(v);
         else if (c->mode == APPLY_MR7)
             r = (v >= 3 && (v & 1)) ? oracle_mr7(v) : 0;
+        else if (c->mode == APPLY_WHEEL)
+            r = oracle_wheel_is_prime(v);
         else
             r = oracle_is_prime(v, c->table);
         c->out[i] = (uint8_t)r;
@@ -275,6 +322,12 @@ int oracle_trial_array(const uint64_t *n, uint8_t *out, uint64_t len, int nthrea
 int oracle_mr7_array(const uint64_t *n, uint8_t *out, uint64_t len, int nthreads)
 {
     return apply_array(n, out, len, NULL, nthreads, APPLY_MR7);
+}
+
+/* out[i] = oracle_wheel_is_prime(n[i]) (O8 alone), threaded as above. */
+int oracle_wheel_array(const uint64_t *n, uint8_t *out, uint64_t len, int nthreads)
+{
+    return apply_array(n, out, len, NULL, nthreads, APPLY_WHEEL);
 }
 
 /* ------------------------------------------------------------------ O6 */

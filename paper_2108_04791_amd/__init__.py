@@ -56,6 +56,7 @@ class Config(ctypes.Structure):
         ("mr_blocks_per_cu", ctypes.c_int32),
         ("mr_window", ctypes.c_int32),
         ("rest_test", ctypes.c_int32),
+        ("wheel_log2", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:

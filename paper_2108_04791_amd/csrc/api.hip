@@ -48,7 +48,7 @@ std::atomic<int> g_last_err{0};
 std::mutex g_cfg_mu;
 // The autotuner's choice for 2^24 64-bit values; other classes are in the
 // tuning database that paper_2108_04791_amd/tune.py writes.
-constexpr isp_config DEFAULT_CONFIG = {512, 8, 4, 24, 1, 1024, 2, 3, -1};
+constexpr isp_config DEFAULT_CONFIG = {512, 8, 4, 24, 1, 1024, 2, 3, -1, -1};
 isp_config g_cfg = DEFAULT_CONFIG;
 
 int fail(hipError_t e)
@@ -69,7 +69,9 @@ bool valid_config(const isp_config &c)
             c.filter_primes == 64) &&
            (c.sort_survivors == -1 || c.sort_survivors == 1) && blk(c.mr_block, MR_MAX_BLOCK) &&
            c.mr_blocks_per_cu >= 1 && c.mr_blocks_per_cu <= 16 && c.mr_window >= 1 &&
-           c.mr_window <= 4 && (c.rest_test == -1 || c.rest_test == 1);
+           c.mr_window <= 4 && (c.rest_test == -1 || c.rest_test == 1) &&
+           (c.wheel_log2 == -1 ||
+            (c.wheel_log2 >= WHEEL_MIN_LOG2 && c.wheel_log2 <= WHEEL_MAX_LOG2));
 }
 
 Tuning tuning_snapshot()
@@ -85,6 +87,7 @@ Tuning tuning_snapshot()
     t.mr_blocks_per_cu = g_cfg.mr_blocks_per_cu;
     t.mr_window = g_cfg.mr_window;
     t.rest_test = g_cfg.rest_test > 0;
+    t.wheel_log2 = g_cfg.wheel_log2 > 0 ? g_cfg.wheel_log2 : 0;
     return t;
 }
 
@@ -273,8 +276,12 @@ double g_prof_ms[ISP_NUM_STAGES];
 uint64_t g_prof_calls = 0;
 
 // A plain call small enough for the fused kernel (which runs the seven
-// Miller-Rabin bases; the Baillie-PSW alternative keeps the three kernels).
-bool small_call(size_t len, const Tuning &t) { return len <= SMALL_MAX && t.rest_test <= 0; }
+// Miller-Rabin bases; the Baillie-PSW alternative and the wheel stage keep
+// the separate kernels).
+bool small_call(size_t len, const Tuning &t)
+{
+    return len <= SMALL_MAX && t.rest_test <= 0 && t.wheel_log2 == 0;
+}
 
 // Enqueues the whole plain path.
 int run_plain(const uint64_t *n, uint8_t *out, size_t len, const DeviceState &ds,
@@ -310,6 +317,8 @@ int run_plain(const uint64_t *n, uint8_t *out, size_t len, const DeviceState &ds
             e = launch_classify(ca, grid_c, t.classify_block, t.classify_ept, s);
         if (e == hipSuccess)
             e = launch_filter2(ws.surv, ws.counts, grid_c, len, nullptr, t.filter_primes, s);
+        if (e == hipSuccess && t.wheel_log2)
+            e = launch_wheel(ws.surv, ws.counts, grid_c, len, nullptr, t.wheel_log2, s);
         mark(1);
         if (e == hipSuccess)
             e = launch_mr1(ma, t.mr_block, s);
@@ -444,6 +453,9 @@ int build_graph_one(BatchCtx &c, const DeviceState &ds, const Tuning &t, int k)
     if (ee == hipSuccess)
         ee = launch_filter2(c.ws.surv, c.ws.counts, grid_c, 0, &d->total, t.filter_primes,
                             c.cap_stream);
+    if (ee == hipSuccess && t.wheel_log2)
+        ee = launch_wheel(c.ws.surv, c.ws.counts, grid_c, 0, &d->total, t.wheel_log2,
+                          c.cap_stream);
     if (ee == hipSuccess)
         ee = launch_mr1(ma, t.mr_block, c.cap_stream);
     if (ee == hipSuccess)
@@ -942,6 +954,7 @@ int isp_set_config(const isp_config *cfg)
     if (!c.mr_blocks_per_cu) c.mr_blocks_per_cu = d.mr_blocks_per_cu;
     if (!c.mr_window) c.mr_window = d.mr_window;
     if (!c.rest_test) c.rest_test = -1;
+    if (!c.wheel_log2) c.wheel_log2 = -1;
     if (!valid_config(c))
         return ISP_EINVAL;
     std::lock_guard<std::mutex> g(g_cfg_mu);

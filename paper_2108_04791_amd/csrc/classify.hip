@@ -29,6 +29,7 @@
 // Also here: filter2_kernel, the second filter stage over each region's
 // survivors (the rest of the first 64 odd primes), and small_kernel, which
 // decides a call of at most SMALL_MAX elements in one launch.
+#include "compact.h"
 #include "internal.h"
 #include "mr_lane.h"
 
@@ -392,7 +393,6 @@ __global__ void __launch_bounds__(FILTER2_BLOCK) filter2_kernel(Survivor *__rest
     const uint64_t chunk = classify_chunk(total_dev ? *total_dev : total, gridDim.x);
     Survivor *region = surv + (uint64_t)g * chunk;
     const uint32_t count = counts[g];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t kept = 0;  // entries kept so far (block-uniform)
     for (uint32_t r0 = 0; r0 < count; r0 += FILTER2_BLOCK) {
         const uint32_t i = r0 + threadIdx.x;
@@ -408,22 +408,7 @@ __global__ void __launch_bounds__(FILTER2_BLOCK) filter2_kernel(Survivor *__rest
                 divisible |= e.n * FILTER.inv[k] <= FILTER.lim[k];
             keep = !divisible;
         }
-        const uint64_t m = __ballot(keep);
-        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-        if (lane == 0)
-            wave_cnt[wave] = (uint32_t)__popcll(m);
-        __syncthreads();  // every entry of this round is read; the counts are in
-        uint32_t before = 0, total = 0;
-        for (int w = 0; w < FILTER2_BLOCK / 64; ++w) {
-            const uint32_t c = wave_cnt[w];
-            before += w < wave ? c : 0u;
-            total += c;
-        }
-        // positions below this round's first entry: nothing unread is overwritten
-        if (keep)
-            region[kept + before + (uint32_t)__popcll(m & lt)] = e;
-        kept += total;
-        __syncthreads();  // wave_cnt is rewritten by the next round
+        compact_round<FILTER2_BLOCK>(region, e, keep, kept, wave_cnt);
     }
     if (threadIdx.x == 0)
         counts[g] = kept;

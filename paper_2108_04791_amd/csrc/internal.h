@@ -115,7 +115,13 @@ struct Tuning {
     int mr_blocks_per_cu;
     int mr_window;
     int rest_test;  // 0: the six remaining Miller-Rabin bases; 1: strong Lucas (Baillie-PSW)
+    int wheel_log2; // 0: off; else survivors below 2^wheel_log2 go to the wheel stage
 };
+
+// Bounds of the optional wheel stage (wheel.hip): survivors below 2^b, with
+// WHEEL_MIN_LOG2 <= b <= WHEEL_MAX_LOG2, are decided by trial division.
+constexpr int WHEEL_MIN_LOG2 = 33;
+constexpr int WHEEL_MAX_LOG2 = 40;
 
 struct DeviceState {
     int device = -1;
@@ -159,6 +165,10 @@ hipError_t launch_small(const uint64_t *n, uint8_t *out, size_t len, const uint3
 // total_dev: where to read the element count (batched calls), else total.
 hipError_t launch_filter2(Survivor *surv, uint32_t *counts, unsigned grid, uint64_t total,
                           const uint64_t *total_dev, int nf, hipStream_t s);
+// Decides the survivors below 2^log2_bound by wheel trial division and
+// compacts the others in place (grid: the classify grid).
+hipError_t launch_wheel(Survivor *surv, uint32_t *counts, unsigned grid, uint64_t total,
+                        const uint64_t *total_dev, int log2_bound, hipStream_t s);
 hipError_t launch_mr1(const MrArgs &a, int block, hipStream_t s);
 hipError_t launch_mr2(const MrArgs &a, int cus, int per_cu, unsigned max_grid, int block,
                       int window, hipStream_t s);

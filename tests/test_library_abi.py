@@ -56,11 +56,16 @@ def test_config_validation(isp):
         for bad in (dict(classify_block=100), dict(classify_ept=3), dict(filter_primes=300),
                     dict(filter_primes=12),
                     dict(mr_window=5), dict(sort_survivors=2), dict(classify_blocks_per_cu=17),
-                    dict(mr_block=2048), dict(mr_block=96), dict(mr_blocks_per_cu=0 - 1)):
+                    dict(mr_block=2048), dict(mr_block=96), dict(mr_blocks_per_cu=0 - 1),
+                    dict(wheel_log2=32), dict(wheel_log2=41), dict(wheel_log2=-2)):
             with pytest.raises(isp.IsprimeError):
                 isp.set_config(**bad)
         isp.set_config(mr_window=4)
         assert isp.get_config()["mr_window"] == 4
+        assert prev["wheel_log2"] == -1  # the wheel stage is off by default
+        for b in (33, 40):
+            isp.set_config(wheel_log2=b)
+            assert isp.get_config()["wheel_log2"] == b
     finally:
         isp.set_config(**prev)
     assert isp.get_config() == prev

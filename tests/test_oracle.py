@@ -2,6 +2,7 @@
 (values the paper prints, published constants, brute force, certificates,
 Python's own integers), so that a dropped term, a wrong index or a wrong
 constant anywhere in it fails at least one test."""
+import math
 import random
 
 import numpy as np
@@ -260,3 +261,58 @@ def test_isprime_array_threads_and_tables(oracle_table):
     assert np.array_equal(r1, r8)
     for v, r in zip(a.tolist()[:5000], r1.tolist()[:5000]):
         assert r == oracle.trial_is_prime(v)
+
+
+# -------------------------------------------------------------------- wheel
+
+
+def _coprime_gaps(modulus: int) -> list:
+    """Gaps between consecutive numbers coprime to `modulus` in [1, modulus + 1],
+    from the definition (math.gcd), not from any printed list."""
+    r = [v for v in range(1, modulus + 2) if math.gcd(v, modulus) == 1]
+    return [b - a for a, b in zip(r, r[1:])]
+
+
+def test_wheel_cycle_eq5_and_eq6():
+    """The wheel's difference cycle against its definition; the derivation is
+    itself checked on the two smaller cycles section 3 prints."""
+    assert _coprime_gaps(6) == [4, 2]
+    assert _coprime_gaps(30) == [6, 4, 2, 4, 2, 4, 6, 2]
+    c = oracle.wheel_cycle()
+    assert c == _coprime_gaps(210)
+    assert len(c) == 48 and sum(c) == 210
+    assert [int(v) for v in 1 + np.cumsum(c[:6])] == [11, 13, 17, 19, 23, 29]  # Eq. 6
+
+
+def _largest_primes_per_residue(limit: int) -> list:
+    """For each residue r coprime to 210, the largest prime p < limit with
+    p = r (mod 210), found by O1."""
+    out = []
+    for r in range(1, 210):
+        if math.gcd(r, 210) != 1:
+            continue
+        p = (limit - 1) - ((limit - 1 - r) % 210)
+        while not oracle.trial_is_prime(p):
+            p -= 210
+        out.append(p)
+    return out
+
+
+def test_wheel_trial_division_brute_force_and_hard_cases():
+    """O8 against the definition (O1) on every n < 2^20, then on squares and
+    near-square products of primes from every residue class of the wheel
+    near 2^20 (n just below 2^40: the last divisor tried is the factor)."""
+    a = np.arange(1 << 20, dtype=np.uint64)
+    w = oracle.wheel_array(a)
+    assert np.array_equal(w, oracle.trial_array(a))
+    assert int(w.sum()) == 82025  # pi(2^20)
+    ps = _largest_primes_per_residue(1 << 20)
+    assert len(ps) == 48
+    cases = [p * p for p in ps] + [p * q for p, q in zip(ps, ps[1:])]
+    cases += [p for p in ps] + [2, 3, 5, 7, 11, 121, 169, 221, 209 * 211]
+    cases += [n for n in SPSP + CARMICHAEL + PRIMES if n < 1 << 42]
+    for n in cases:
+        assert n < 1 << 42
+        assert oracle.wheel_is_prime(n) == oracle.trial_is_prime(n), n
+    assert all(oracle.wheel_is_prime(p * p) == 0 for p in ps)
+    assert all(oracle.wheel_is_prime(p) == 1 for p in ps)

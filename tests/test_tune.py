@@ -24,7 +24,7 @@ def test_length_bucket_and_lookup(tmp_path):
 def test_shipped_database_is_valid():
     db = tune.load()
     assert db["entries"], "the package ships a tuning database"
-    keys = set(tune.SPACE) | {"sort_survivors", "rest_test"}
+    keys = set(tune.SPACE) | {"sort_survivors", "rest_test", "wheel_log2"}
     for name, e in db["entries"].items():
         assert set(e["config"]) >= set(tune.SPACE), name
         assert set(e["config"]) <= keys, name

@@ -26,6 +26,9 @@ is measured on):
                      drawn from one magnitude class.
 * ``c5_requests``    a Poisson request stream of arrays, lengths log-uniform
                      in [1, 2^20], classes as in ``c4_batched``.
+* ``odd_band``       odd values uniform in one octave [2^(b-1), 2^b) (the
+                     wheel-against-Miller-Rabin comparison, one octave at a
+                     time).
 
 ``paper_arrays()`` rebuilds the array workloads of the paper's
 incrementing-sequence table (section 6.1.3) and array-performance table
@@ -56,6 +59,7 @@ SEED_C3 = 0x2108047900000003
 SEED_C4 = 0x2108047900000004
 SEED_C5 = 0x2108047900000005
 SEED_PAPER = 0x2108047900000006
+SEED_BAND = 0x2108047900000007
 
 # Magnitude classes of the batched and served workloads: [lo, hi) as
 # (shift, lo): a draw r gives r >> shift, accepted when >= lo.
@@ -116,6 +120,15 @@ def c2_mr64(n: int = 1 << 24, seed: int = SEED_C2, start: int = 0) -> np.ndarray
         coin = element_draws(seed, idx, 7) >> np.uint64(63)
         out[c0:c0 + idx.size] = v | coin
     return out
+
+
+def odd_band(n: int, bits: int, seed: int = SEED_BAND, start: int = 0) -> np.ndarray:
+    """n odd values uniform in [2^(bits-1), 2^bits), 2 <= bits <= 64."""
+    if not 2 <= bits <= 64:
+        raise ValueError("bits must be in [2, 64]")
+    idx = np.arange(start, start + n, dtype=np.uint64)
+    v = element_draws(seed ^ bits, idx, 0) >> np.uint64(65 - bits)
+    return v | np.uint64(1 << (bits - 1)) | np.uint64(1)
 
 
 def chernick_k() -> np.ndarray:
