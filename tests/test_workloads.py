@@ -57,3 +57,18 @@ def test_batched_and_requests_shapes():
     reqs = W.c5_requests(50, qps=100.0)
     ts = [t for t, _, _ in reqs]
     assert ts == sorted(ts) and all(1 <= r.size <= 1 << 20 for _, r, _ in reqs)
+
+
+def test_odd_band_octaves():
+    """Odd values inside one octave, spread over all of it, chunk independent."""
+    for bits in (2, 33, 40, 64):
+        a = W.odd_band(20000, bits)
+        lo, hi = 1 << (bits - 1), 1 << bits
+        assert int(a.min()) >= lo and int(a.max()) < hi, bits
+        assert bool(((a & np.uint64(1)) == 1).all()), bits
+    a = W.odd_band(20000, 40)
+    frac = (a.astype(np.float64) - 2.0 ** 39) / 2.0 ** 39
+    counts = np.histogram(frac, bins=16, range=(0, 1))[0]
+    assert counts.min() > 0.8 * counts.mean()
+    assert np.array_equal(a[500:900], W.odd_band(400, 40, start=500))
+    assert not np.array_equal(W.odd_band(100, 39), W.odd_band(100, 40) >> np.uint64(1))
