@@ -255,3 +255,27 @@ def test_two_streams(isp):
     torch.cuda.synchronize()
     assert_same(a, oa.cpu().numpy().astype(np.uint8), expect(a), "stream 1")
     assert_same(b, ob.cpu().numpy().astype(np.uint8), expect(b, use_table=False), "stream 2")
+
+
+def test_larger_than_one_piece(isp):
+    """A plain call of more than 2^28 elements runs in pieces of 2^28 (each
+    piece's survivors share 32-bit counters): every output byte is checked.
+    The bulk repeats 0 .. 2^20 - 1 (table lookups; the expected bytes are one
+    oracle period, repeated on the device); a window of hard values (C2, C3,
+    the edge values) straddles the piece boundary and is checked against the
+    oracle directly."""
+    piece, period = 1 << 28, 1 << 20
+    n = piece + period + 13
+    dev = torch.arange(n, dtype=torch.int64, device="cuda") % period
+    hard = np.concatenate([W.c2_mr64(8192, start=11), W.c3_mixed(8192, start=5),
+                           np.array(EDGES, dtype=np.uint64)])
+    lo = piece - hard.size // 2
+    dev[lo:lo + hard.size] = to_dev(hard)
+    out = isp.isprime(dev).to(torch.uint8)
+    torch.cuda.synchronize()
+    base = torch.from_numpy(expect(np.arange(period, dtype=np.uint64), use_table=False)).cuda()
+    exp = base.repeat(n // period + 1)[:n].clone()
+    exp[lo:lo + hard.size] = torch.from_numpy(expect(hard)).cuda()
+    bad = torch.nonzero(out != exp).flatten()
+    assert bad.numel() == 0, (bad[:10].tolist(), dev[bad[:10]].tolist())
+    assert int(out[lo:lo + hard.size].sum().item()) > 0
