@@ -778,10 +778,10 @@ int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
     for (size_t a = 0; a < num_arrays; ++a) {
         if (lens[a] && (!n_ptrs[a] || !out_ptrs[a]))
             return ISP_EINVAL;
+        if (lens[a] > BATCH_MAX_ELEMS - total)  // also keeps the sum from wrapping
+            return ISP_EINVAL;
         total += lens[a];
     }
-    if (total > BATCH_MAX_ELEMS)
-        return ISP_EINVAL;
     if (total == 0)
         return ISP_OK;
     int dev = 0;

@@ -450,6 +450,8 @@ int isp_submit(isp_server *s, const uint64_t *host_n, uint8_t *host_out, size_t 
 {
     if (!s || !ticket || (len && (!host_n || !host_out)))
         return ISP_EINVAL;
+    if (len > UINT64_MAX / BYTES_PER_ELEM)  // no such host array; keeps bytes exact
+        return ISP_EINVAL;
     const uint64_t bytes = (uint64_t)len * BYTES_PER_ELEM;
     std::unique_lock<std::mutex> g(s->mu);
     if (s->stop)

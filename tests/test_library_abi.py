@@ -46,6 +46,11 @@ def test_argument_errors_without_device(isp):
     assert L.isp_montmul_u64(None, None, None, None, 3, None) == isp.ISP_EINVAL
     assert L.isp_init(-1) == isp.ISP_EINVAL
     assert L.isprime_u64_batched(None, None, None, 0, None) == isp.ISP_OK
+    # more than 2^30 elements in one batched call, also through a wrapping sum
+    ptrs = (ctypes.c_void_p * 2)(8, 8)
+    for lens in ((1 << 30, 1), ((1 << 64) - 1, 2), (1 << 63, 1 << 63)):
+        ls = (ctypes.c_uint64 * 2)(*lens)
+        assert L.isprime_u64_batched(ptrs, ptrs, ls, 2, None) == isp.ISP_EINVAL, lens
     assert L.isp_strerror(isp.ISP_EBUSY).decode().startswith("busy")
     assert L.isp_workspace_bytes(1 << 20) >= 32 * (1 << 20)
 
