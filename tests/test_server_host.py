@@ -173,3 +173,19 @@ def test_bad_arguments():
         with pytest.raises(TypeError):
             srv.submit(np.zeros(3, np.int32), np.zeros(3, np.uint8))
         assert isp.lib().isp_submit(srv._h, None, None, 5, None) == isp.ISP_EINVAL
+
+
+def test_submit_rejects_impossible_lengths():
+    """A length whose byte count cannot be represented is refused before
+    anything is queued (the pointers are never read)."""
+    import ctypes
+    with isp.Server(test_mode=1, max_batch_elems=1000) as srv:
+        t = ctypes.c_uint64()
+        for n in (1 << 61, (1 << 64) - 1):
+            st = isp.lib().isp_submit(srv._h, ctypes.c_void_p(8), ctypes.c_void_p(8), n,
+                                      ctypes.byref(t))
+            assert st == isp.ISP_EINVAL, n
+        r = np.arange(5, dtype=np.uint64)
+        o = np.zeros(5, dtype=np.uint8)
+        srv.wait(srv.submit(r, o))
+        assert np.array_equal(o, (r & np.uint64(1)).astype(np.uint8))
