@@ -99,8 +99,8 @@ int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
  * workgroup sieves a segment of 2^19 numbers in LDS, in pieces of at most
  * 2^30 numbers.  A piece ending below 2^50 is sieved by every odd prime up
  * to the square root of its end, which decides it.  Above, a piece long
- * enough for the primes up to its square root (pi(sqrt) below 16 times its
- * length) also gets every such prime: those above 2^19 are sorted once into
+ * enough for the primes up to its square root (pi(sqrt) below 0.8 times its
+ * length) also gets every such prime: those above 2^20 are sorted once into
  * per-segment buckets (bucket sieve), and the segments are again complete.
  * Otherwise it is sieved by the odd primes below 2^22 and the survivors go
  * through the same Miller-Rabin kernels as isprime_u64.  The workspace kept

@@ -42,8 +42,11 @@ constexpr int RANGE_PARTIAL_LOG2 = 22;    // primes used where the sieve cannot 
 constexpr int RANGE_MAX_PRIMES = 2063689; // odd primes below 2^25: 2063688
 constexpr int RANGE_LIST_GROUPS = 512;    // workgroups of the list build
 // bucket mode: primes above this come as precomputed hits (at most one per
-// segment of RANGE_SEG numbers)
-constexpr uint32_t BUCKET_SMALL = (uint32_t)1 << 19;
+// segment of RANGE_SEG numbers); 2^20 rather than 2^19 leaves the primes
+// just above the segment length to the segment kernel, which is cheaper for
+// them than their scattered hits (6% at 2^48 .. 2^50, about 1% higher up;
+// 2^21 gains nothing more)
+constexpr uint32_t BUCKET_SMALL = (uint32_t)1 << 20;
 constexpr int MAX_BUCKET_SEGS = (int)(RANGE_PIECE / RANGE_SEG);  // 2048
 constexpr int MAX_BUCKET_GROUPS = 512;
 constexpr int BUCKET_FROM_LOG2 = 23;  // bucket mode for pieces whose root exceeds 2^23

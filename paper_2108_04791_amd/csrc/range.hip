@@ -8,7 +8,7 @@
 // one segment of the interval in LDS by the odd primes up to
 // sqrt(segment end) while that is below 2^25 (segment end below 2^50); then
 // the survivors are exactly the primes.  Above it, a long piece runs in
-// bucket mode (below): the primes above 2^19 up to the square root are
+// bucket mode (below): the primes above 2^20 up to the square root are
 // sorted into per-segment buckets first, and the segments are complete
 // again.  A short piece is sieved by the odd primes below 2^22 (below 2^18
 // when it has fewer than 256 segments, which then run one wave of
@@ -466,7 +466,7 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
 // ---- bucket mode: crossing off by the primes above BUCKET_SMALL ----------
 //
 // A prime p > 2^19 has at most one odd multiple in a segment of 2^19
-// numbers, so visiting every such prime in every segment costs one
+// numbers (BUCKET_SMALL is at least that), so visiting every such prime in every segment costs one
 // reduction per prime and segment.  Bucket mode inverts the loop (the
 // bucket sieve of segmented sieving): the odd primes in (BUCKET_SMALL,
 // sqrt(end)] are read from the device table, each prime's odd multiples at
