@@ -71,10 +71,11 @@ void isp_shutdown(void);
  *   len  0 returns ISP_OK without launching
  * n == NULL or out == NULL with len > 0 -> ISP_EINVAL.  n and out must not
  * overlap.  Uses the calling thread's current HIP device.  Calls of at most
- * 65,536 elements run as one fused kernel (one element per thread, the
- * seven bases in the element's own lane); larger calls, and calls with the
- * Baillie-PSW alternative selected, as the classify / base-2 / remaining-
- * bases kernels.  The bytes are the same either way.
+ * 65,536 elements run as one fused kernel (a team of 8 lanes per element:
+ * every lane runs base 2, six of them one other base each); larger calls,
+ * and calls with the Baillie-PSW alternative or the wheel stage selected,
+ * as the classify / second-filter / base-2 / remaining-bases kernels.  The
+ * bytes are the same either way.
  * Paper: section 1 (inputs and outputs of isprime_fast), sections 2-6. */
 int isprime_u64(const uint64_t *n, uint8_t *out, size_t len, void *stream);
 
@@ -102,8 +103,9 @@ int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
  * enough for the primes up to its square root (pi(sqrt) below 0.8 times its
  * length) also gets every such prime: those above 2^20 are sorted once into
  * per-segment buckets (bucket sieve), and the segments are again complete.
- * Otherwise it is sieved by the odd primes below 2^22 and the survivors go
- * through the same Miller-Rabin kernels as isprime_u64.  The workspace kept
+ * Otherwise it is sieved by the odd primes below 2^22 (below 2^18 for a
+ * piece of fewer than 256 segments) and the survivors go through the same
+ * Miller-Rabin kernels as isprime_u64.  The workspace kept
  * for the stream grows to the largest call seen.  Asynchronous on `stream`.
  * Paper: section 6.1.3 (sieve up to the maximum, then test membership),
  * section 1 (the sieve of Eratosthenes). */
@@ -162,7 +164,8 @@ int isp_table(int device, const uint32_t **table, size_t *words);
 
 /* Counters of the last isprime_u64 / batched call on `stream`, read back
  * synchronously (the stream is synchronised): survivors of the trial filter
- * and base-2 passers sent to the remaining six bases.  A call that ran as
+ * (both stages; with the wheel stage on, those it left to Miller-Rabin) and
+ * base-2 passers sent to the remaining six bases.  A call that ran as
  * the fused kernel keeps no counters: both read 0. */
 int isp_last_counts(void *stream, uint64_t *survivors, uint64_t *candidates);
 
@@ -174,7 +177,8 @@ int isp_last_counts(void *stream, uint64_t *survivors, uint64_t *candidates);
  * stops recording.  Meant for one measuring thread.
  * isp_profile_read: ms[ISP_NUM_STAGES] totals and the number of calls. */
 enum {
-    ISP_STAGE_CLASSIFY = 0, /* dispatch + table lookup + trial filter + compaction */
+    ISP_STAGE_CLASSIFY = 0, /* dispatch + table lookup + both trial-filter stages +
+                               compaction (+ the wheel stage when selected) */
     ISP_STAGE_MR_BASE2 = 1, /* Miller-Rabin base 2 over all survivors */
     ISP_STAGE_MR_REST = 2,  /* Miller-Rabin bases 325 .. 1795265022 over base-2 passers */
     ISP_NUM_STAGES = 3
@@ -210,7 +214,8 @@ int isp_server_create(const isp_server_config *cfg, isp_server **srv);
 /* Queue one request; `ticket` receives its id.  len may be 0.  The request
  * holds 9 * len bytes of the budget until it completes; one larger than the
  * whole budget is admitted when nothing else holds any.  Requests are split
- * into pieces of at most max_batch_elems. */
+ * into pieces of at most max_batch_elems.  A len above (2^64 - 1) / 9 (no
+ * such host array) is ISP_EINVAL. */
 int isp_submit(isp_server *srv, const uint64_t *host_n, uint8_t *host_out, size_t len,
                uint64_t *ticket);
 /* 1 done, 0 pending, <0 error (ISP_ENOENT for an unknown or consumed ticket). */
