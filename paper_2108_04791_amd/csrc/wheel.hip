@@ -13,18 +13,19 @@
 // in place, like the second filter stage.  All lanes of a wavefront test
 // the same divisor at the same time: lane j computes the inverse modulo 2^64
 // of divisor k0 + j once per 64 divisors and the wavefront reads them back
-// from LDS one at a time.  The wavefront stops at the largest square root
-// among its lanes still undecided.
+// from LDS one at a time.  The wavefront stops after the chunk that passes
+// the square root of every lane still undecided.
 //
 // The test: with q = n * d^-1 mod 2^64, d | n gives q = n / d < 2^40 / 3 <
 // 2^43; conversely q < 2^43 and d < 2^21 give q * d < 2^64, so q * d = n
 // exactly.  For n < 2^40 and d < 2^21, d | n holds iff the high 32 bits of q
 // are below 2^11: four VALU instructions per divisor and lane (their
 // running minimum is taken three at a time), no division.  Every tested
-// divisor is below 2^21: a chunk of 64 starts at or below the largest root
-// (< 2^20) plus one gap and spans less than 64 * 10.  A divisor above a
-// lane's own root that divides it still shows a composite (d < 2^21 < n),
-// so whole chunks are tested.
+// divisor is below 2^21: a chunk of 64 is entered only while some root
+// (< 2^20) lies beyond the previous chunk's last divisor, so it starts at
+// most one gap (10) above that root and spans less than 64 * 10.  A divisor
+// above a lane's own root that divides it still shows a composite (d < 2^21
+// < n), so whole chunks are tested.
 #include "compact.h"
 #include "internal.h"
 
@@ -54,17 +55,8 @@ struct WheelResidues {
                 r[k++] = v;
     }
 };
-__constant__ constexpr WheelResidues WHEEL{};
+constexpr WheelResidues WHEEL{};
 static_assert(WHEEL.r[0] == 11 && WHEEL.r[5] == 29 && WHEEL.r[47] == 211, "wheel residues");
-
-// Divisor number t of the sequence 3, 5, 7, 11, 13, 17, ... (increasing).
-__device__ __forceinline__ uint32_t wheel_divisor(uint32_t t)
-{
-    if (t < 3)
-        return 3 + 2 * t;
-    const uint32_t u = t - 3, q = u / 48;
-    return 210 * q + WHEEL.r[u - 48 * q];
-}
 
 // Inverse of an odd d modulo 2^64 by Newton's iteration (each step doubles
 // the correct low bits; (3d) xor 2 is correct to 5 bits).
@@ -90,15 +82,6 @@ __device__ __forceinline__ uint32_t isqrt40(uint64_t n)
     return r;
 }
 
-// Largest v over the wavefront (every lane active), wavefront-uniform.
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
 __device__ __forceinline__ void wave_sync_lds()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -121,6 +104,10 @@ __global__ void __launch_bounds__(WHEEL_BLOCK) wheel_kernel(Survivor *__restrict
                                                             uint64_t bound, uint32_t split)
 {
     __shared__ uint32_t inv_lds[WHEEL_WAVES][64][2];
+    __shared__ uint32_t res[48];
+    if (threadIdx.x < 48)
+        res[threadIdx.x] = WHEEL.r[threadIdx.x];
+    __syncthreads();
     const uint32_t regions = gridDim.x / split;  // the classify grid
     const uint32_t sub = blockIdx.x / regions, g = blockIdx.x - sub * regions;
     const uint64_t chunk = classify_chunk(total_dev ? *total_dev : total, regions);
@@ -142,14 +129,19 @@ __global__ void __launch_bounds__(WHEEL_BLOCK) wheel_kernel(Survivor *__restrict
         const uint32_t nl = (uint32_t)e.n, nh = (uint32_t)(e.n >> 32);
         const uint32_t root = mine ? isqrt40(e.n) : 0u;
         uint32_t hmin = ~0u;  // smallest high word of n * d^-1 so far
-        uint32_t rmax = wave_max_u32(root);
-        for (uint32_t k0 = 0; rmax != 0; k0 += 64) {
-            const uint32_t d = wheel_divisor(k0 + lane);
+        // chunks of 64 divisors (lane j: divisor k0 + j of 3, 5, 7, 11, ...)
+        // while some undecided lane's root lies beyond the last one tested
+        bool more = __ballot(mine) != 0;
+        for (uint32_t k0 = 0; more; k0 += 64) {
+            const uint32_t t = k0 + lane;
+            uint32_t d = 3 + 2 * t;
+            if (t >= 3) {
+                const uint32_t u = t - 3, q = u / 48;
+                d = 210 * q + res[u - 48 * q];
+            }
             const uint64_t y = inv64_of(d);
             inv[lane][0] = (uint32_t)y;
             inv[lane][1] = (uint32_t)(y >> 32);
-            // the divisors grow with the lane: the first `cnt` are <= rmax
-            const uint32_t cnt = (uint32_t)__popcll(__ballot(d <= rmax));
             wave_sync_lds();
             // a running minimum in a VGPR keeps the compares off the scalar unit
 #pragma unroll
@@ -158,9 +150,8 @@ __global__ void __launch_bounds__(WHEEL_BLOCK) wheel_kernel(Survivor *__restrict
                 hmin = min(hmin, __umulhi(nl, il) + nl * ih + nh * il);
             }
             wave_sync_lds();  // the next chunk rewrites inv
-            if (cnt < 64)
-                break;  // past the root of every lane
-            rmax = wave_max_u32(mine && hmin >= WHEEL_Q_HI ? root : 0u);
+            const uint32_t dlast = __builtin_amdgcn_readlane(d, 63);
+            more = __ballot(mine && hmin >= WHEEL_Q_HI && root > dlast) != 0;
         }
         if (mine) {
             *e.out = hmin < WHEEL_Q_HI ? 0 : 1;  // a divisor in [3, root] or none
