@@ -42,6 +42,8 @@ constexpr int WHEEL_WAVES = WHEEL_BLOCK / 64;
 constexpr uint32_t WHEEL_MIN_GROUPS = 2048;  // 8 wavefronts per SIMD
 constexpr uint32_t WHEEL_Q_HI = 1u << 11;  // d | n iff hi32(n * d^-1 mod 2^64) < this
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 constexpr uint32_t ce_gcd(uint32_t a, uint32_t b) { return b ? ce_gcd(b, a % b) : a; }
 
 // The 48 residues coprime to 210 in [11, 211], in increasing order.
@@ -103,7 +105,7 @@ __global__ void __launch_bounds__(WHEEL_BLOCK) wheel_kernel(Survivor *__restrict
                                                             const uint64_t *total_dev,
                                                             uint64_t bound, uint32_t split)
 {
-    __shared__ uint32_t inv_lds[WHEEL_WAVES][64][2];
+    __shared__ __attribute__((aligned(16))) uint32_t inv_lds[WHEEL_WAVES][64][2];
     __shared__ uint32_t res[48];
     if (threadIdx.x < 48)
         res[threadIdx.x] = WHEEL.r[threadIdx.x];
@@ -143,11 +145,30 @@ __global__ void __launch_bounds__(WHEEL_BLOCK) wheel_kernel(Survivor *__restrict
             inv[lane][0] = (uint32_t)y;
             inv[lane][1] = (uint32_t)(y >> 32);
             wave_sync_lds();
-            // a running minimum in a VGPR keeps the compares off the scalar unit
+            // a running minimum in a VGPR keeps the compares off the scalar
+            // unit; the inverses of the next 8 divisors are read while the
+            // current 8 are tested (4 x 16 bytes, two divisors per read)
+            const u32x4 *inv4 = reinterpret_cast<const u32x4 *>(&inv[0][0]);
+            u32x4 cur[4], nxt[4];
 #pragma unroll
-            for (int j = 0; j < 64; ++j) {
-                const uint32_t il = inv[j][0], ih = inv[j][1];
-                hmin = min(hmin, __umulhi(nl, il) + nl * ih + nh * il);
+            for (int q = 0; q < 4; ++q)
+                cur[q] = inv4[q];
+#pragma unroll
+            for (int blk = 0; blk < 8; ++blk) {
+                if (blk < 7) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        nxt[q] = inv4[4 * (blk + 1) + q];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t h0 = __umulhi(nl, cur[q].x) + nl * cur[q].y + nh * cur[q].x;
+                    const uint32_t h1 = __umulhi(nl, cur[q].z) + nl * cur[q].w + nh * cur[q].z;
+                    hmin = min(hmin, min(h0, h1));
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    cur[q] = nxt[q];
             }
             wave_sync_lds();  // the next chunk rewrites inv
             const uint32_t dlast = __builtin_amdgcn_readlane(d, 63);
