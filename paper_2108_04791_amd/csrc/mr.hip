@@ -423,6 +423,21 @@ __device__ __forceinline__ uint64_t call_total(const MrArgs &a)
     return a.total_dev ? *a.total_dev : a.total;
 }
 
+// Passers of one phase-1 workgroup, grouped before their constants are
+// written (when they fit the LDS stage): by bit-length class (64, 63, below)
+// and then by s, so that a phase-2 wavefront's tasks share the window count
+// of their d and the length of their -1 chain.
+constexpr uint32_t PASS_STAGE = 2048;
+constexpr int PASS_BINS = 15;
+
+__device__ __forceinline__ int pass_key(uint64_t n)
+{
+    const int L = 64 - __clzll(n);
+    const int lc = L == 64 ? 0 : L == 63 ? 1 : 2;
+    const int s = __ffsll((long long)(n - 1)) - 1;  // >= 1: n is odd
+    return lc * 5 + (s < 5 ? s : 5) - 1;
+}
+
 __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
 {
     extern __shared__ uint64_t dyn[];
@@ -485,8 +500,39 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
     const uint32_t npass = fill;
     if (a.prep) {
         MontPrep *prep = a.prep + (uint64_t)g * chunk_1;
-        for (uint32_t i = threadIdx.x; i < npass; i += blockDim.x)
-            prep[i] = mont_prep(region[i].n);
+        if (npass <= PASS_STAGE) {
+            // counting sort by pass_key through LDS (block-uniform branch)
+            __shared__ Survivor stage[PASS_STAGE];
+            __shared__ uint32_t bins[PASS_BINS];
+            if (threadIdx.x < PASS_BINS)
+                bins[threadIdx.x] = 0;
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < npass; i += blockDim.x)
+                atomicAdd(&bins[pass_key(region[i].n)], 1u);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint32_t run = 0;
+                for (int b = 0; b < PASS_BINS; ++b) {
+                    const uint32_t c = bins[b];
+                    bins[b] = run;
+                    run += c;
+                }
+            }
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < npass; i += blockDim.x) {
+                const Survivor e = region[i];
+                stage[atomicAdd(&bins[pass_key(e.n)], 1u)] = e;
+            }
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < npass; i += blockDim.x) {
+                const Survivor e = stage[i];
+                region[i] = e;
+                prep[i] = mont_prep(e.n);
+            }
+        } else {
+            for (uint32_t i = threadIdx.x; i < npass; i += blockDim.x)
+                prep[i] = mont_prep(region[i].n);
+        }
     }
     if (threadIdx.x == 0)
         a.counts1[g] = npass;
