@@ -279,3 +279,29 @@ def test_larger_than_one_piece(isp):
     bad = torch.nonzero(out != exp).flatten()
     assert bad.numel() == 0, (bad[:10].tolist(), dev[bad[:10]].tolist())
     assert int(out[lo:lo + hard.size].sum().item()) > 0
+
+
+
+def test_many_passers_per_workgroup(isp):
+    """More base-2 passers per workgroup than phase 1 groups in LDS (2,048,
+    whatever the tuned grid of at most 4096 workgroups): those workgroups
+    keep the order found.  2^24 draws from primes of every magnitude class of
+    the grouping (64-bit, 63-bit, shorter) and base-2 strong pseudoprimes;
+    each distinct value is checked by the oracle, and every byte against it."""
+    vals = []
+    for start in ((1 << 63) + 1, (1 << 62) + 1, (1 << 48) + 1, U64 - 4000):
+        n, got = start | 1, 0
+        while got < 64 and n < U64:
+            if oracle.mr7(n):
+                vals.append(n)
+                got += 1
+            n += 2
+    spsp = [3825123056546413051, 341550071728321, 2152302898747, 3474749660383]
+    uniq = np.array(sorted(set(vals + spsp)), dtype=np.uint64)
+    exp_u = expect(uniq, use_table=False)
+    assert int(exp_u.sum()) == len(set(vals))
+    a = uniq[np.random.default_rng(2048).integers(0, uniq.size, size=1 << 24)]
+    got = gpu_isprime(isp, a)
+    assert_same(a, got, exp_u[np.searchsorted(uniq, a)], "many passers")
+    _, passers = isp.last_counts()
+    assert passers > 2048 * 4096
