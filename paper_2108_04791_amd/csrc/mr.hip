@@ -424,10 +424,11 @@ __device__ __forceinline__ uint64_t call_total(const MrArgs &a)
 }
 
 // Passers of one phase-1 workgroup, grouped before their constants are
-// written (when they fit the LDS stage): by bit-length class (64, 63, below)
-// and then by s, so that a phase-2 wavefront's tasks share the window count
-// of their d and the length of their -1 chain.
-constexpr uint32_t PASS_STAGE = 2048;
+// written (when there are at most PASS_PER_THREAD per thread): by
+// bit-length class (64, 63, below) and then by s, so that a phase-2
+// wavefront's tasks share the window count of their d, the length of their
+// -1 chain and the form of their products.
+constexpr int PASS_PER_THREAD = 4;
 constexpr int PASS_BINS = 15;
 
 __device__ __forceinline__ int pass_key(uint64_t n)
@@ -500,9 +501,11 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
     const uint32_t npass = fill;
     if (a.prep) {
         MontPrep *prep = a.prep + (uint64_t)g * chunk_1;
-        if (npass <= PASS_STAGE) {
-            // counting sort by pass_key through LDS (block-uniform branch)
-            __shared__ Survivor stage[PASS_STAGE];
+        if (npass <= PASS_PER_THREAD * blockDim.x) {
+            // counting sort by pass_key (block-uniform branch): the sorted
+            // order as indices in LDS, then every thread reads its (at most
+            // PASS_PER_THREAD) entries into registers before any is rewritten
+            __shared__ uint16_t perm[PASS_PER_THREAD * MR_MAX_BLOCK];
             __shared__ uint32_t bins[PASS_BINS];
             if (threadIdx.x < PASS_BINS)
                 bins[threadIdx.x] = 0;
@@ -519,15 +522,24 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
                 }
             }
             __syncthreads();
-            for (uint32_t i = threadIdx.x; i < npass; i += blockDim.x) {
-                const Survivor e = region[i];
-                stage[atomicAdd(&bins[pass_key(e.n)], 1u)] = e;
-            }
+            for (uint32_t i = threadIdx.x; i < npass; i += blockDim.x)
+                perm[atomicAdd(&bins[pass_key(region[i].n)], 1u)] = (uint16_t)i;
             __syncthreads();
-            for (uint32_t i = threadIdx.x; i < npass; i += blockDim.x) {
-                const Survivor e = stage[i];
-                region[i] = e;
-                prep[i] = mont_prep(e.n);
+            Survivor mine[PASS_PER_THREAD];
+#pragma unroll
+            for (int k = 0; k < PASS_PER_THREAD; ++k) {
+                const uint32_t i = threadIdx.x + k * blockDim.x;
+                if (i < npass)
+                    mine[k] = region[perm[i]];
+            }
+            __syncthreads();  // every entry is read before any is rewritten
+#pragma unroll
+            for (int k = 0; k < PASS_PER_THREAD; ++k) {
+                const uint32_t i = threadIdx.x + k * blockDim.x;
+                if (i < npass) {
+                    region[i] = mine[k];
+                    prep[i] = mont_prep(mine[k].n);
+                }
             }
         } else {
             for (uint32_t i = threadIdx.x; i < npass; i += blockDim.x)
