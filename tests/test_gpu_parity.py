@@ -284,10 +284,11 @@ def test_larger_than_one_piece(isp):
 
 def test_many_passers_per_workgroup(isp):
     """More base-2 passers per workgroup than phase 1 groups (4 per thread,
-    at most 4,096, whatever the tuned grid of at most 4096 workgroups): those
-    workgroups keep the order found.  2^25 draws from primes of every magnitude class of
-    the grouping (64-bit, 63-bit, shorter) and base-2 strong pseudoprimes;
-    each distinct value is checked by the oracle, and every byte against it."""
+    at most 4,096), whatever the tuned grid of at most 4096 workgroups: those
+    workgroups keep the order found.  2^25 draws from primes of every
+    magnitude class of the grouping (64-bit, 63-bit, shorter) and base-2
+    strong pseudoprimes; each distinct value is checked by the oracle, and
+    every byte against it."""
     vals = []
     for start in ((1 << 63) + 1, (1 << 62) + 1, (1 << 48) + 1, U64 - 4000):
         n, got = start | 1, 0
