@@ -31,10 +31,13 @@ constexpr int MAX_DEVICES = 64;
 // A plain call is split into pieces of at most this many elements, so the
 // 32-bit device counters never overflow and a workspace stays below 8 GiB.
 constexpr size_t PLAIN_PIECE = (size_t)1 << 28;
-// Interval pieces of fewer segments than this sieve by the primes below
-// 2^PARTIAL_SHORT_LOG2 where the sieve cannot be complete.
+// Interval pieces of fewer full segments (RANGE_SEG numbers) than this, where
+// the sieve cannot be complete, sieve by the primes below
+// 2^PARTIAL_SHORT_LOG2, in up to this many segments of at least
+// RANGE_MIN_CHUNK numbers.
 constexpr unsigned PARTIAL_FULL_GRID = 256;
 constexpr int PARTIAL_SHORT_LOG2 = 18;
+constexpr uint64_t RANGE_MIN_CHUNK = 4096;
 // Elements per batched call (its survivors share one 32-bit counter).
 constexpr uint64_t BATCH_MAX_ELEMS = (uint64_t)1 << 30;
 // A plain call over len elements uses at most ceil(len / this) Miller-Rabin
@@ -735,7 +738,21 @@ int isprime_range_u64(uint64_t lo, uint8_t *out, size_t len, void *stream)
                 e = launch_range_sieve(lo + off, out + off, piece, grid, RANGE_SEG, groups, ds,
                                        sw->ws, sw->rws, s);
         } else {
-            const unsigned grid = (unsigned)((piece + RANGE_SEG - 1) / RANGE_SEG);
+            // every segment of a piece whose square root is below 2^25 is
+            // decided by the sieve alone: no survivors, no Miller-Rabin
+            const bool complete = root < ((uint64_t)1 << RANGE_PRIME_LOG2);
+            const unsigned full = (unsigned)((piece + RANGE_SEG - 1) / RANGE_SEG);
+            // a short piece in Miller-Rabin mode is cut into up to
+            // PARTIAL_FULL_GRID shorter segments (at least RANGE_MIN_CHUNK
+            // numbers each): its workgroups then share the crossings, while
+            // each still visits the few primes below the short-piece bound
+            // (in complete mode each segment visits every prime up to the
+            // root, so more segments would only repeat that work)
+            const unsigned grid =
+                complete || full >= PARTIAL_FULL_GRID
+                    ? full
+                    : (unsigned)std::max<uint64_t>(
+                          full, std::min<uint64_t>(PARTIAL_FULL_GRID, piece / RANGE_MIN_CHUNK));
             ClassifyArgs ca;
             MrArgs ma;
             unsigned grid_c, grid1;
@@ -745,12 +762,9 @@ int isprime_range_u64(uint64_t lo, uint8_t *out, size_t len, void *stream)
             // a short piece has few segments, each visiting all the primes below
             // the bound one after another: a lower bound there costs more
             // Miller-Rabin on the extra survivors but far less sieve latency
-            const int partial = grid >= PARTIAL_FULL_GRID ? RANGE_PARTIAL_LOG2 : PARTIAL_SHORT_LOG2;
+            const int partial = full >= PARTIAL_FULL_GRID ? RANGE_PARTIAL_LOG2 : PARTIAL_SHORT_LOG2;
             e = launch_range_sieve(lo + off, out + off, piece, grid, classify_chunk(piece, grid),
                                    0, ds, sw->ws, sw->rws, s, partial);
-            // every segment of a piece whose square root is below 2^25 is
-            // decided by the sieve alone: no survivors, no Miller-Rabin
-            const bool complete = root < ((uint64_t)1 << RANGE_PRIME_LOG2);
             if (e == hipSuccess && !complete)
                 e = launch_mr1(ma, t.mr_block, s);
             if (e == hipSuccess && !complete)
