@@ -104,8 +104,9 @@ int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
  * length) also gets every such prime: those above 2^20 are sorted once into
  * per-segment buckets (bucket sieve), and the segments are again complete.
  * Otherwise it is sieved by the odd primes below 2^22 (below 2^18 for a
- * piece of fewer than 256 segments) and the survivors go through the same
- * Miller-Rabin kernels as isprime_u64.  The workspace kept
+ * piece of fewer than 256 segments, which is then cut into up to 256
+ * shorter segments) and the survivors go through the same Miller-Rabin
+ * kernels as isprime_u64.  The workspace kept
  * for the stream grows to the largest call seen.  Asynchronous on `stream`.
  * Paper: section 6.1.3 (sieve up to the maximum, then test membership),
  * section 1 (the sieve of Eratosthenes). */

@@ -11,11 +11,11 @@
 // bucket mode (below): the primes above 2^20 up to the square root are
 // sorted into per-segment buckets first, and the segments are complete
 // again.  A short piece is sieved by the odd primes below 2^22 (below 2^18
-// when it has fewer than 256 segments, which then run one wave of
-// workgroups and wait on the sieve's latency) and the survivors (about 3.4%
-// of the numbers with no factor below 2^22, 4.5% below 2^18) go to the same
-// two Miller-Rabin kernels as array inputs, through the same per-workgroup
-// regions and counts.
+// when it has fewer than 256 full segments; it is then cut into up to 256
+// shorter ones, since so few workgroups would wait on the sieve's latency)
+// and the survivors (about 3.4% of the numbers with no factor below 2^22,
+// 4.5% below 2^18) go to the same two Miller-Rabin kernels as array inputs,
+// through the same per-workgroup regions and counts.
 //
 // Segment layout: workgroup g covers numbers [lo + g*chunk, lo + (g+1)*chunk)
 // with chunk = classify_chunk(len, grid) (a multiple of 64, at most
