@@ -738,10 +738,20 @@ int isprime_range_u64(uint64_t lo, uint8_t *out, size_t len, void *stream)
                 e = launch_range_sieve(lo + off, out + off, piece, grid, RANGE_SEG, groups, ds,
                                        sw->ws, sw->rws, s);
         } else {
-            // every segment of a piece whose square root is below 2^25 is
-            // decided by the sieve alone: no survivors, no Miller-Rabin
-            const bool complete = root < ((uint64_t)1 << RANGE_PRIME_LOG2);
             const unsigned full = (unsigned)((piece + RANGE_SEG - 1) / RANGE_SEG);
+            // every segment of a piece whose square root is below 2^25 is
+            // decided by the sieve alone (no survivors, no Miller-Rabin),
+            // unless the piece is short and the primes up to its root many:
+            // then its few segments would each wait on a pass over all of
+            // them, and the primes below 2^18 with Miller-Rabin on the 4.5%
+            // that survive cost less.  Measured: a segment pass costs about
+            // 0.45 ns per prime, Miller-Rabin on the survivors about 0.011 ns
+            // per number of the piece, over 0.03 ms more of fixed cost.
+            const bool short_piece = full < PARTIAL_FULL_GRID;
+            const bool force_partial = short_piece && root >= ((uint64_t)1 << PARTIAL_SHORT_LOG2) &&
+                                       pi_root > (double)piece / 40.0 + 65536.0;
+            const int complete_log2 = force_partial ? PARTIAL_SHORT_LOG2 : RANGE_PRIME_LOG2;
+            const bool complete = root < ((uint64_t)1 << complete_log2);
             // a short piece in Miller-Rabin mode is cut into up to
             // PARTIAL_FULL_GRID shorter segments (at least RANGE_MIN_CHUNK
             // numbers each): its workgroups then share the crossings, while
@@ -749,7 +759,7 @@ int isprime_range_u64(uint64_t lo, uint8_t *out, size_t len, void *stream)
             // (in complete mode each segment visits every prime up to the
             // root, so more segments would only repeat that work)
             const unsigned grid =
-                complete || full >= PARTIAL_FULL_GRID
+                complete || !short_piece
                     ? full
                     : (unsigned)std::max<uint64_t>(
                           full, std::min<uint64_t>(PARTIAL_FULL_GRID, piece / RANGE_MIN_CHUNK));
@@ -762,9 +772,9 @@ int isprime_range_u64(uint64_t lo, uint8_t *out, size_t len, void *stream)
             // a short piece has few segments, each visiting all the primes below
             // the bound one after another: a lower bound there costs more
             // Miller-Rabin on the extra survivors but far less sieve latency
-            const int partial = full >= PARTIAL_FULL_GRID ? RANGE_PARTIAL_LOG2 : PARTIAL_SHORT_LOG2;
+            const int partial = short_piece ? PARTIAL_SHORT_LOG2 : RANGE_PARTIAL_LOG2;
             e = launch_range_sieve(lo + off, out + off, piece, grid, classify_chunk(piece, grid),
-                                   0, ds, sw->ws, sw->rws, s, partial);
+                                   0, ds, sw->ws, sw->rws, s, partial, complete_log2);
             if (e == hipSuccess && !complete)
                 e = launch_mr1(ma, t.mr_block, s);
             if (e == hipSuccess && !complete)

@@ -183,12 +183,15 @@ hipError_t launch_range_table(uint64_t lo, uint8_t *out, uint64_t len, const Dev
                               hipStream_t s);
 hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsigned groups,
                                 const DeviceState &ds, const RangeWs &rw, hipStream_t s);
-// partial_log2: segments that the sieve cannot decide alone are sieved by the
-// primes below 2^partial_log2 (17 .. RANGE_PARTIAL_LOG2).
+// Without buckets, a segment whose square root is below 2^complete_log2
+// (partial_log2 .. RANGE_PRIME_LOG2) is decided by the sieve alone; the others
+// are sieved by the primes below 2^partial_log2 (17 .. RANGE_PARTIAL_LOG2)
+// and their survivors left to Miller-Rabin.
 hipError_t launch_range_sieve(uint64_t lo, uint8_t *out, uint64_t len, unsigned grid,
                               uint64_t chunk, unsigned groups, const DeviceState &ds,
                               const Workspace &ws, const RangeWs &rw, hipStream_t s,
-                              int partial_log2 = RANGE_PARTIAL_LOG2);
+                              int partial_log2 = RANGE_PARTIAL_LOG2,
+                              int complete_log2 = RANGE_PRIME_LOG2);
 
 hipError_t launch_montmul_test(const uint64_t *a, const uint64_t *b, const uint64_t *n,
                                uint64_t *out, uint64_t len, hipStream_t s);

@@ -222,6 +222,7 @@ struct RangeArgs {
     uint64_t hit_cap;           // entries allocated in hits
     uint32_t groups;            // 0: no buckets
     uint32_t partial_log2;      // where the sieve cannot be complete: primes below 2^this
+    uint32_t complete_log2;     // segments whose root is below 2^this are complete
 };
 
 // Integer square root of x < 2^64 (floor), from a double estimate.
@@ -301,7 +302,7 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
     // (in bucket mode the primes above BUCKET_SMALL arrive as hits, and every
     // segment is complete)
     const bool buckets = a.groups != 0;
-    const bool complete = buckets || root < ((uint64_t)1 << RANGE_PRIME_LOG2);
+    const bool complete = buckets || root < ((uint64_t)1 << a.complete_log2);
     const uint64_t bound = buckets ? (root < BUCKET_SMALL ? root : BUCKET_SMALL)
                            : complete ? root : ((uint64_t)1 << a.partial_log2) - 1;
     // the list is sorted: use the primes up to `bound`
@@ -846,12 +847,14 @@ hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsign
 hipError_t launch_range_sieve(uint64_t lo, uint8_t *out, uint64_t len, unsigned grid,
                               uint64_t chunk, unsigned groups, const DeviceState &ds,
                               const Workspace &ws, const RangeWs &rw, hipStream_t s,
-                              int partial_log2)
+                              int partial_log2, int complete_log2)
 {
-    if (partial_log2 < 17 || partial_log2 > RANGE_PARTIAL_LOG2)
+    if (partial_log2 < 17 || partial_log2 > RANGE_PARTIAL_LOG2 || complete_log2 < partial_log2 ||
+        complete_log2 > RANGE_PRIME_LOG2)
         return hipErrorInvalidValue;
     RangeArgs a;
     a.partial_log2 = (uint32_t)partial_log2;
+    a.complete_log2 = (uint32_t)complete_log2;
     a.lo = lo;
     a.len = len;
     a.chunk = chunk;

@@ -66,15 +66,18 @@ def test_across_table_bound(isp):
 
 
 def test_across_complete_bound(isp):
-    """Segments ending below 2^50 are decided by the sieve alone (the primes up
-    to the square root, below 2^25); above it the survivors of the primes below
-    2^22 go through Miller-Rabin.  This interval has both kinds."""
+    """Six segments around 2^50: too few for a pass over the primes up to
+    2^25 each, so the primes below 2^18 and Miller-Rabin decide them on both
+    sides of the bound (the long intervals below cover the complete sieve
+    next to Miller-Rabin in one call)."""
     check(isp, (1 << 50) - 3 * SEG - 17, 6 * SEG + 33)
 
 
 def test_complete_at_several_magnitudes(isp):
-    """Around 2^40, 2^44 and 2^48 every segment is complete, sieved by primes
-    past 2^20, 2^22 and 2^24."""
+    """Short intervals around 2^40, 2^44 and 2^48.  Around 2^40 every segment
+    is complete, sieved by the primes up to 2^20.  Around 2^44 and 2^48 the
+    primes up to the square root are too many for so few segments, so the
+    primes below 2^18 and Miller-Rabin decide them instead."""
     check(isp, (1 << 40) - SEG - 5, 2 * SEG + 11)
     check(isp, (1 << 44) + 1, SEG + 7)
     check(isp, (1 << 48) - SEG // 2, SEG)
@@ -131,6 +134,27 @@ def test_empty_and_invalid(isp):
     with pytest.raises(isp.IsprimeError):
         isp.isprime_range(U64, 2)
     assert gpu_range(isp, U64, 1)[0] == 0
+
+
+@pytest.mark.parametrize("lo,length", [((1 << 34) + 1, (1 << 27) + 5 * SEG + 3),
+                                       ((1 << 44) + 3, 1 << 27),
+                                       ((1 << 50) - (1 << 26) - 5, 1 << 27)])
+def test_long_complete_pieces(isp, lo, length):
+    """Intervals of at least 256 segments: below 2^50 every segment is
+    complete, crossed off by all the primes up to its square root (2^17,
+    2^22, 2^25); the last interval crosses 2^50, where the segments switch to
+    the primes below 2^22 and Miller-Rabin.  The whole interval equals the
+    array call, and a sample (both ends and 20,000 random positions) equals
+    the oracle."""
+    got = isp.isprime_range(lo, length)
+    arr = torch.arange(lo, lo + length, dtype=torch.int64, device="cuda")
+    assert torch.equal(isp.isprime(arr), got)
+    rng = np.random.default_rng(lo & 0xffff)
+    idx = np.unique(np.concatenate([np.arange(0, 3000), np.arange(length - 3000, length),
+                                    rng.integers(0, length, 20000)])).astype(np.int64)
+    a = np.uint64(lo) + idx.astype(np.uint64)
+    exp, _ = oracle.isprime_array(a, nthreads=NTHREADS, use_table=False)
+    assert np.array_equal(got[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.uint8), exp)
 
 
 @pytest.mark.parametrize("lo,length", [((1 << 56) + 12345, 1 << 26), ((1 << 62) - 3, 1 << 28),
