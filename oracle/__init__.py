@@ -72,7 +72,6 @@ def _load():
             "oracle_strong_probable_prime": (i32, [u64, u64]),
             "oracle_mr_base": (u64, [i32]),
             "oracle_mr7": (i32, [u64]),
-            "oracle_mr7_bases_run": (i32, [u64]),
             "oracle_is_prime": (i32, [u64, p]),
             "oracle_isprime_array": (i32, [p, p, u64, p, i32]),
             "oracle_trial_array": (i32, [p, p, u64, i32]),
@@ -132,10 +131,6 @@ def mr_bases() -> list:
 
 def mr7(n: int) -> int:
     return _load().oracle_mr7(n)
-
-
-def mr7_bases_run(n: int) -> int:
-    return _load().oracle_mr7_bases_run(n)
 
 
 def is_prime(n: int, use_table: bool = False) -> int:

@@ -170,22 +170,6 @@ int oracle_mr7(uint64_t n)
     return 1;
 }
 
-/* Number of bases evaluated by oracle_mr7 before it returns (the first
- * failing base counts); used to count work, never to decide primality. */
-int oracle_mr7_bases_run(uint64_t n)
-{
-    int run = 0;
-    for (int k = 0; k < 7; ++k) {
-        uint64_t a = MR_BASES[k] % n;
-        if (a == 0)
-            continue;
-        ++run;
-        if (!oracle_strong_probable_prime(n, a))
-            return run;
-    }
-    return run;
-}
-
 /* ------------------------------------------------------------------ O5 */
 
 #define TABLE_BOUND ((uint64_t)1 << 32)

@@ -229,6 +229,35 @@ def test_chernick_list_and_verdicts():
 
 # ------------------------------------------------------------- certificates
 
+# The ten largest primes below 2^64, as 2^64 minus these offsets (the
+# published list of primes just below powers of two).
+TOP_PRIME_OFFSETS = [59, 83, 95, 179, 189, 257, 279, 323, 353, 363]
+
+
+def test_pratt_is_two_sided():
+    """Section 2.1 (Eq. 4) is checked above 2^32 by certificates that do not
+    rest on the seven-base claim, so the Pratt certificate must never call a
+    composite prime.  Its dangerous inputs are composites that pass Fermat's
+    test to base 2 (the first witness it tries): strong pseudoprimes to base
+    2 above 2^32, composite Mersenne numbers, and Carmichael numbers
+    (Chernick's, which pass Fermat to every base coprime to them, some also
+    the strong test to base 2).  Each must come out 0 or -1, never 1; and
+    the published primes just below 2^64 must come out 1."""
+    fermat2 = [n for n in SPSP if n >= 1 << 32]
+    fermat2 += [(1 << p) - 1 for p in (37, 41, 43, 47, 53, 59)]
+    vals = workloads.chernick_values()
+    big = [int(n) for n in vals.tolist() if n >= 1 << 32]
+    strong2 = [n for n in big if _py_strong_test(n, 2)]
+    assert len(strong2) == 251
+    fermat2 += strong2[::10] + big[::60]
+    for n in fermat2:
+        assert pow(2, n - 1, n) == 1, n  # base 2 cannot tell them from primes
+        assert oracle.pratt_certify(n) != 1, n
+    for off in TOP_PRIME_OFFSETS:
+        assert oracle.pratt_certify((1 << 64) - off) == 1, off
+    for n in ((1 << 64) - 61, (1 << 64) - 1, (1 << 64) - 57):  # composites between them
+        assert oracle.pratt_certify(n) != 1, n
+
 
 @pytest.mark.parametrize("name", ["c2", "c3"])
 def test_certificates_on_sampled_elements(name):
@@ -244,6 +273,7 @@ def test_certificates_on_sampled_elements(name):
         if oracle.mr7(n):
             assert oracle.pratt_certify(n) == 1, n
         else:
+            assert oracle.pratt_certify(n) != 1, n
             f = oracle.find_factor(n)
             if f == 0:  # a Fermat witness is enough to show compositeness
                 assert pow(2, n - 1, n) != 1, n
