@@ -51,7 +51,9 @@ enum {
     ISP_EDEVICE = -3,   /* a HIP call failed; see isp_last_device_error() */
     ISP_EBUSY = -4,     /* server: request not admissible now (non-blocking) */
     ISP_ETIMEDOUT = -5, /* server: wait timed out */
-    ISP_ENOENT = -6     /* server: unknown ticket */
+    ISP_ENOENT = -6,    /* server: unknown ticket */
+    ISP_ERANGE = -7,    /* isprime_u64_noalloc: len above isp_noalloc_max_len() */
+    ISP_ENOINIT = -8    /* isprime_u64_noalloc: isp_init has not run for the device */
 };
 
 /* Build the odd-only sieve table for n < 2^32 on `device` (bit i of the
@@ -78,6 +80,29 @@ void isp_shutdown(void);
  * bytes are the same either way.
  * Paper: section 1 (inputs and outputs of isprime_fast), sections 2-6. */
 int isprime_u64(const uint64_t *n, uint8_t *out, size_t len, void *stream);
+
+/* isprime_u64 without any allocation on the call path, for callers that
+ * cannot allocate device memory while they call (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, kernels and bytes as isprime_u64; the workspace is one static
+ * device array per device, sized for isp_noalloc_max_len() = 1,048,576
+ * elements (about 60 MiB, held by each device the library runs on until the
+ * process ends).  It calls no hipMalloc, hipFree or other allocating
+ * routine:
+ *   - isp_init(device) must have run for the current device beforehand
+ *     (it builds the table and looks up the array's device address):
+ *     otherwise ISP_ENOINIT, with nothing enqueued;
+ *   - len > isp_noalloc_max_len() -> ISP_ERANGE, with nothing enqueued;
+ *   - len == 0 returns ISP_OK; NULL pointers with len > 0 -> ISP_EINVAL.
+ * Every call on a device shares that device's array and no part of it needs
+ * clearing between calls (each count is written before it is read).  Calls
+ * that overlap on one device -- on different streams, or from several host
+ * threads without ordering -- race on the array and may return wrong bytes:
+ * order them on one stream.  isp_last_counts does not report these calls. */
+int isprime_u64_noalloc(const uint64_t *n, uint8_t *out, size_t len, void *stream);
+
+/* The largest len isprime_u64_noalloc accepts. */
+size_t isp_noalloc_max_len(void);
 
 /* Many independent arrays in one call: for each a < num_arrays and
  * i < lens[a], out_ptrs[a][i] = primality of n_ptrs[a][i].

@@ -30,6 +30,8 @@ ISP_EDEVICE = -3
 ISP_EBUSY = -4
 ISP_ETIMEDOUT = -5
 ISP_ENOENT = -6
+ISP_ERANGE = -7
+ISP_ENOINIT = -8
 
 _lib = None
 _lock = threading.Lock()
@@ -84,6 +86,8 @@ SIGNATURES = {
     "isp_init": (_I, [_I]),
     "isp_shutdown": (None, []),
     "isprime_u64": (_I, [_P, _P, _SZ, _P]),
+    "isprime_u64_noalloc": (_I, [_P, _P, _SZ, _P]),
+    "isp_noalloc_max_len": (_SZ, []),
     "isprime_u64_batched": (_I, [_P, _P, _P, _SZ, _P]),
     "isprime_range_u64": (_I, [_U64, _P, _SZ, _P]),
     "isp_workspace_bytes": (_SZ, [_SZ]),
@@ -184,6 +188,27 @@ def isprime_into(n: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tenso
         _check(lib().isprime_u64(n.data_ptr(), out.data_ptr(), n.numel(), _stream_handle(stream)),
                "isprime_u64")
     return out
+
+
+def isprime_into_noalloc(n: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """isprime_into through the allocation-free entry point: the library
+    allocates nothing during the call (its workspace is a static device
+    array; init() must have run for the device).  n must already be a
+    contiguous uint64/int64 device tensor: no copy is made here either."""
+    if n.dtype not in (torch.uint64, torch.int64) or not n.is_cuda or not n.is_contiguous():
+        raise TypeError("n must be a contiguous uint64 (or int64-viewed) device tensor")
+    if out.dtype not in (torch.uint8, torch.bool) or not out.is_contiguous():
+        raise TypeError("out must be a contiguous uint8 or bool tensor")
+    if out.numel() != n.numel():
+        raise ValueError("out has %d elements, n has %d" % (out.numel(), n.numel()))
+    with torch.cuda.device(n.device):
+        _check(lib().isprime_u64_noalloc(n.data_ptr(), out.data_ptr(), n.numel(),
+                                         _stream_handle(stream)), "isprime_u64_noalloc")
+    return out
+
+
+def noalloc_max_len() -> int:
+    return lib().isp_noalloc_max_len()
 
 
 def isprime(n: torch.Tensor, stream=None) -> torch.Tensor:

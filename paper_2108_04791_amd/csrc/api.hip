@@ -44,6 +44,29 @@ constexpr uint64_t BATCH_MAX_ELEMS = (uint64_t)1 << 30;
 // workgroups.
 constexpr size_t SMALL_CALL_PER_BLOCK = 1024;
 
+// The allocation-free entry point (isprime_u64_noalloc) takes its workspace
+// from one static device array instead of hipMalloc: calls of up to
+// NOALLOC_MAX elements, laid out as the allocated workspace (survivor
+// regions, base-2 passer regions, their Montgomery constants, the per-block
+// counts).  Each device holds its own copy for the life of the process.
+constexpr size_t NOALLOC_MAX = (size_t)1 << 20;
+constexpr size_t NOALLOC_SURV_OFF = 0;
+constexpr size_t NOALLOC_CAND_OFF =
+    NOALLOC_SURV_OFF + (NOALLOC_MAX + 64 * (size_t)MAX_GRID) * sizeof(Survivor);
+constexpr size_t NOALLOC_PREP_OFF =
+    NOALLOC_CAND_OFF + (NOALLOC_MAX + (size_t)MAX_GRID) * sizeof(Survivor);
+constexpr size_t NOALLOC_COUNTS_OFF =
+    NOALLOC_PREP_OFF + (NOALLOC_MAX + (size_t)MAX_GRID) * sizeof(MontPrep);
+constexpr size_t NOALLOC_BYTES = NOALLOC_COUNTS_OFF + 2 * (size_t)MAX_GRID * sizeof(uint32_t);
+static_assert(NOALLOC_CAND_OFF % 256 == 0 && NOALLOC_PREP_OFF % 256 == 0 &&
+                  NOALLOC_COUNTS_OFF % 256 == 0,
+              "every part of the scratch array starts 256-byte aligned");
+
+// Host code never names this array directly (on the host the name is only a
+// stand-in for the symbol): isp_init looks up each device's address of it
+// once, and the entry point passes that address to the kernels.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
 std::mutex g_init_mu;
 DeviceState g_dev[MAX_DEVICES];
 std::atomic<int> g_last_err{0};
@@ -557,6 +580,18 @@ int isp_init(int device)
         return fail(e);
     }
     st.num_base_primes = (int)count;
+    // this device's copy of the allocation-free entry point's scratch array
+    // (the device is current here)
+    void *sp = nullptr;
+    e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !sp) {
+        (void)hipFree(st.table);
+        (void)hipFree(st.base_primes);
+        (void)hipFree(st.base_count);
+        (void)hipSetDevice(prev);
+        return fail(e != hipSuccess ? e : hipErrorInvalidSymbol);
+    }
+    st.scratch = static_cast<unsigned char *>(sp);
     ds = st;
     (void)hipSetDevice(prev);
     return ISP_OK;
@@ -632,6 +667,40 @@ int isprime_u64(const uint64_t *n, uint8_t *out, size_t len, void *stream)
     }
     return st;
 }
+
+int isprime_u64_noalloc(const uint64_t *n, uint8_t *out, size_t len, void *stream)
+{
+    if (len == 0)
+        return ISP_OK;
+    if (!n || !out)
+        return ISP_EINVAL;
+    if (len > NOALLOC_MAX)
+        return ISP_ERANGE;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(e);
+    if (dev < 0 || dev >= MAX_DEVICES)
+        return ISP_EINVAL;
+    DeviceState ds;
+    {
+        std::lock_guard<std::mutex> g(g_init_mu);
+        ds = g_dev[dev];
+    }
+    if (!ds.table || !ds.scratch)
+        return ISP_ENOINIT;  // isp_init allocates; this entry point must not
+    Workspace ws;
+    ws.surv = reinterpret_cast<Survivor *>(ds.scratch + NOALLOC_SURV_OFF);
+    ws.cand = reinterpret_cast<Survivor *>(ds.scratch + NOALLOC_CAND_OFF);
+    ws.prep = reinterpret_cast<MontPrep *>(ds.scratch + NOALLOC_PREP_OFF);
+    ws.counts = reinterpret_cast<uint32_t *>(ds.scratch + NOALLOC_COUNTS_OFF);
+    ws.cap = NOALLOC_MAX;
+    // nothing in the workspace needs to start at zero: every count is
+    // written by its producer kernel before its consumer reads it
+    return run_plain(n, out, len, ds, ws, tuning_snapshot(), (hipStream_t)stream);
+}
+
+size_t isp_noalloc_max_len(void) { return NOALLOC_MAX; }
 
 // Builds the interval sieve's prime list for `dev` on first use.
 static int ensure_range_primes(int dev)
@@ -949,6 +1018,10 @@ const char *isp_strerror(int status)
         return "timed out";
     case ISP_ENOENT:
         return "unknown ticket";
+    case ISP_ERANGE:
+        return "length above the allocation-free entry point's maximum (isp_noalloc_max_len)";
+    case ISP_ENOINIT:
+        return "device not initialised: call isp_init first";
     default:
         return "unknown status";
     }

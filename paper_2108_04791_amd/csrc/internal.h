@@ -139,6 +139,9 @@ struct DeviceState {
     uint64_t *range_inv = nullptr;
     uint32_t *range_count = nullptr;  // RANGE_LIST_GROUPS + 1 words
     int num_range_primes = 0;
+    // device address of this device's copy of the allocation-free entry
+    // point's static scratch array (hipGetSymbolAddress at isp_init)
+    unsigned char *scratch = nullptr;
 };
 
 // Per-call workspace (one per stream, or per batched context).

@@ -51,6 +51,13 @@ def test_argument_errors_without_device(isp):
     for lens in ((1 << 30, 1), ((1 << 64) - 1, 2), (1 << 63, 1 << 63)):
         ls = (ctypes.c_uint64 * 2)(*lens)
         assert L.isprime_u64_batched(ptrs, ptrs, ls, 2, None) == isp.ISP_EINVAL, lens
+    # the allocation-free entry point refuses before any HIP call
+    cap = L.isp_noalloc_max_len()
+    assert cap == 1 << 20
+    assert L.isprime_u64_noalloc(None, None, 0, None) == isp.ISP_OK
+    assert L.isprime_u64_noalloc(None, None, 5, None) == isp.ISP_EINVAL
+    assert L.isprime_u64_noalloc(8, 8, cap + 1, None) == isp.ISP_ERANGE
+    assert "isp_init" in L.isp_strerror(isp.ISP_ENOINIT).decode()
     assert L.isp_strerror(isp.ISP_EBUSY).decode().startswith("busy")
     assert L.isp_workspace_bytes(1 << 20) >= 32 * (1 << 20)
 
