@@ -5,13 +5,18 @@
 One step = one isprime_u64 call over the whole workload (dispatch, table
 lookup, trial filter + compaction, binning, Miller-Rabin base 2, Miller-Rabin
 remaining bases, write-back), with the input already resident in HBM.  The
-workload is 2^24 uint64 values rejection-uniform in [2^49, 2^64), half forced
-odd (splitmix64 seed 0x2108047900000002).
+headline workload is the mixed-magnitude array: 2^26 uint64 values, 5%
+Chernick numbers, 1% the values 2047, 3215031751 and 2^61 - 1, the rest
+octave-uniform (splitmix64 seed 0x2108047900000003), which runs the lookup,
+the filter, the compaction and both Miller-Rabin phases together.
 
 Prints ONE JSON line: throughput, the roofline of the dominant kernel (its
 duration measured here with HIP events on the stream it runs on), the
-oracle timed on the host's cores on the same input, parity against it, and
-the per-stage times.
+oracle timed on the host's cores on a bounded sample of the same input, the
+parity of the whole workload against the oracle, the per-kernel times, then
+the other workloads (64-bit Miller-Rabin array, small array, the lookup and
+sieve paths, batched and served forms, the paper's array workloads,
+intervals, the wheel comparison) and last a compact summary of the figures.
 """
 from __future__ import annotations
 
@@ -48,7 +53,7 @@ FILTER_STAGES_TO = 64  # the two filter stages together: the first 64 odd primes
 
 
 # The sources of the array path's kernels (classify, both Miller-Rabin phases,
-# the Lucas alternative) and their argument structs: the counter summary is
+# the Lucas alternative) and their argument structs: a counter summary is
 # valid while these are unchanged.
 ARRAY_PATH_SOURCES = ("classify.hip", "compact.h", "mr.hip", "mont.h", "internal.h")
 
@@ -62,11 +67,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def counter_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary
+def counter_traffic(kernel: str, summary: str = "pmc_c3_mixed.md"):
+    """HBM bytes per launch of `kernel` from a committed counter summary
     (FETCH_SIZE and WRITE_SIZE passes scaled by the copy calibration), or
     None when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "pmc_c2_mr64.md")
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -101,65 +106,102 @@ def bit_length(a: np.ndarray) -> np.ndarray:
 
 
 def popcount(x: np.ndarray) -> np.ndarray:
-    c = np.zeros(x.size, dtype=np.int64)
-    x = x.copy()
-    while (x != 0).any():
-        c += (x & np.uint64(1)).astype(np.int64)
-        x >>= np.uint64(1)
-    return c
+    return np.bitwise_count(np.asarray(x, dtype=np.uint64)).astype(np.int64)
 
 
-def mr_work(a: np.ndarray, prime: np.ndarray, filter_primes: int):
+BASES_AFTER_2 = (325, 9375, 28178, 450775, 9780504, 1795265022)
+
+
+def _strong_round(n: int, a: int) -> bool:
+    """One round of the strong probable-prime test (odd n > a)."""
+    d, s = n - 1, 0
+    while d % 2 == 0:
+        d //= 2
+        s += 1
+    x = pow(a, d, n)
+    if x in (1, n - 1):
+        return True
+    for _ in range(s - 1):
+        x = x * x % n
+        if x == n - 1:
+            return True
+    return False
+
+
+def planted_pseudoprime_bases(a: np.ndarray, planted: np.ndarray) -> np.ndarray:
+    """Per element: how many of the six bases after 2 the textbook test runs
+    on a composite that passes base 2 (up to and including the first base it
+    fails), for the composites the workloads plant on purpose (`planted`:
+    the Chernick numbers); 0 for every other element.  Strong pseudoprimes to
+    base 2 among random 64-bit values are too rare to count (about 3e7 below
+    2^64)."""
+    out = np.zeros(a.size, dtype=np.int64)
+    cand = np.unique(planted[(planted >= np.uint64(1 << 32)) & ((planted & np.uint64(1)) == 1)])
+    runs = {}
+    for v in cand.tolist():
+        if not _strong_round(v, 2):
+            continue
+        k = 0
+        for b in BASES_AFTER_2:
+            k += 1
+            if not _strong_round(v, b):
+                break
+        else:
+            continue  # passes all seven: it would be counted as a prime
+        runs[v] = k
+    if not runs:
+        return out
+    keys = np.array(sorted(runs), dtype=np.uint64)
+    cnt = np.array([runs[int(k)] for k in keys], dtype=np.int64)
+    pos = np.minimum(np.searchsorted(keys, a), keys.size - 1)
+    hit = keys[pos] == a
+    out[hit] = cnt[pos[hit]]
+    return out
+
+
+def mr_work(a: np.ndarray, prime: np.ndarray, filter_primes: int, planted=None):
     """Algorithmic work (VALU instructions) of the two Miller-Rabin launches,
-    counted for left-to-right binary exponentiation.
+    counted for the textbook test with left-to-right binary exponentiation.
 
     The trial filter is the first `filter_primes` odd primes per element and,
     when that is on, the rest of the first 64 on its survivors (the second
     stage), so a survivor here has no factor among the first 64 odd primes.
     Base 2 (every filter survivor): L - 2 Montgomery squarings for bit length
-    L and popcount(n - 1) - 1 modular doublings.  Remaining six bases (every
-    prime >= 2^32; base-2 pseudoprimes are negligible here): per base, L - 2
-    squarings plus popcount(d) - 1 multiplications, d = (n - 1) / 2^s.
-    Early exits of the squaring chain are not subtracted.
+    L and popcount(n - 1) - 1 modular doublings.  Remaining bases: per base
+    run, L - 2 squarings plus popcount(d) - 1 multiplications,
+    d = (n - 1) / 2^s; every prime >= 2^32 runs all six, a composite that
+    passes base 2 runs them up to its first failing one (only the planted
+    Chernick numbers are counted, `planted`).  Early exits of the squaring
+    chain are not subtracted; the kernel's fixed windows, setup and the
+    bases it runs beyond a failing one are overheads, not credit.
     """
     big = (a >= np.uint64(1 << 32)) & ((a & np.uint64(1)) == 1)
-    keep = big.copy()
+    idx = np.nonzero(big)[0]
+    vals = a[idx]
     nf = 0 if filter_primes <= 0 else max(filter_primes, FILTER_STAGES_TO)
-    for p in small_odd_primes(nf):
-        keep &= (a % np.uint64(p)) != 0
-    L = bit_length(a)
-    sq2 = int((L[keep] - 2).sum())
-    dbl2 = int((popcount(a[keep] - np.uint64(1)) - 1).sum())
+    for p in small_odd_primes(nf):  # shrinking: each prime drops its multiples
+        k = (vals % np.uint64(p)) != 0
+        idx, vals = idx[k], vals[k]
+    L = bit_length(vals)
+    sq2 = int((L - 2).sum())
+    dbl2 = int((popcount(vals - np.uint64(1)) - 1).sum())
     base2_ops = sq2 * OPS_PER_MONTMUL + dbl2 * OPS_PER_DOUBLING
-    pr = prime.astype(bool) & big
-    d = a[pr] - np.uint64(1)
+    nb = np.where(prime.astype(bool) & big, MR_BASES_AFTER_2, 0).astype(np.int64)
+    if planted is not None:
+        nb = np.maximum(nb, planted_pseudoprime_bases(a, planted))
+    sel = np.nonzero(nb)[0]
+    v = a[sel]
+    d = v - np.uint64(1)
     while True:
         ev = (d & np.uint64(1)) == 0
         if not ev.any():
             break
         d[ev] >>= np.uint64(1)
-    mm_rest = int((MR_BASES_AFTER_2 * ((L[pr] - 2) + (popcount(d) - 1))).sum())
+    mm_rest = int((nb[sel] * ((bit_length(v) - 2) + (popcount(d) - 1))).sum())
     work = {"mr_base2": {"montmul": sq2, "doublings": dbl2, "ops": base2_ops},
-            "mr_rest": {"montmul": mm_rest, "doublings": 0, "ops": mm_rest * OPS_PER_MONTMUL}}
-    return work, int(keep.sum()), int(pr.sum())
-
-
-def bench_plain(isp, torch, a: np.ndarray, reps: int = 10) -> dict:
-    """Plain isprime_u64 throughput on one resident array (HIP events)."""
-    dev = torch.from_numpy(a.view(np.int64)).cuda()
-    out = torch.empty(a.size, dtype=torch.uint8, device="cuda")
-    stream = torch.cuda.current_stream()
-    isp.isprime_into(dev, out, stream)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        isp.isprime_into(dev, out, stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    return {"len": int(a.size), "ms": ms, "tests_per_s": a.size / (ms * 1e-3),
-            "primes": int(out.sum().item())}
+            "mr_rest": {"montmul": mm_rest, "doublings": 0, "ops": mm_rest * OPS_PER_MONTMUL,
+                        "passers_counted": int(sel.size)}}
+    return work, int(idx.size), int((prime.astype(bool) & big).sum())
 
 
 # The paper's MATLAB seconds for its array workloads (Intel Core i7-9750H,
@@ -330,42 +372,86 @@ def bench_batched(isp, W, torch, reps: int = 5) -> dict:
 SERVED_PASSES = 3
 
 
+def _lat_stats(lat_ms: np.ndarray, elems: int, span_s: float) -> dict:
+    return {"p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+            "mean_ms": float(lat_ms.mean()), "tests_per_s": elems / span_s}
+
+
+def _passes(run, arrive, warm, elems, passes=SERVED_PASSES) -> dict:
+    """`passes` runs over the same arrival times: the pass with the median
+    p99, every pass's p99, and the p50/p99 of all passes' latencies pooled."""
+    lats, res = [], []
+    for _ in range(passes):
+        lat, span = run(arrive)
+        m = lat[warm:] * 1e3
+        lats.append(m)
+        res.append(_lat_stats(m, elems, span))
+    order = sorted(range(passes), key=lambda i: res[i]["p99_ms"])
+    out = dict(res[order[len(order) // 2]])
+    out["p99_ms_passes"] = [res[i]["p99_ms"] for i in range(passes)]
+    pooled = np.concatenate(lats)
+    out["pooled_p50_ms"] = float(np.percentile(pooled, 50))
+    out["pooled_p99_ms"] = float(np.percentile(pooled, 99))
+    out["worst_pass_p99_ms"] = max(r["p99_ms"] for r in res)
+    out["qps"] = float(len(arrive) / (arrive[-1] - arrive[0])) if len(arrive) > 1 else 0.0
+    return out
+
+
 def bench_served(isp, W, torch, num: int = 2100, warm: int = 100, max_inflight: int = 6,
-                 max_batch_elems: int = 1 << 20, baseline: bool = True,
-                 loads=(0.25, 0.5, 0.7, 0.9)) -> dict:
+                 max_batch_elems: int = 1 << 20, loads=(0.25, 0.5, 0.7, 0.9)) -> dict:
     """Poisson request stream (lengths log-uniform in [1, 2^20], magnitude
-    class per request) served by the continuous-batching server at several
-    fractions of its measured capacity (the headline at 0.7), against the
-    same stream at 0.7 served FIFO by serial plain calls (copy in,
-    isprime_u64, copy out, synchronise).  Latency = arrival to result in the
-    caller's host array; per load, the median of SERVED_PASSES passes."""
+    class per request) served by the continuous-batching server (6 slots of
+    2^20 elements) at several fractions of its measured capacity (the
+    headline at 0.7), and the same stream served FIFO by serial plain calls
+    (copy in, isprime_u64, copy out, synchronise) at 0.7 of their own
+    capacity (a load they sustain) and at the server's 0.7 rate (which they
+    do not).  The server also runs at the serial calls' sustainable rate, so
+    the two are compared at one QPS both sustain.  Latency = arrival to
+    result in the caller's host array.  Every served request's bytes are
+    compared with a plain isprime_u64 call on the same values afterwards."""
     import threading
     reqs = W.c5_requests(num, qps=1.0)  # arrival times for rate 1; rescaled below
     arrays = [r for _, r, _ in reqs]
     unit_t = np.array([t for t, _, _ in reqs])
     elems = sum(a.size for a in arrays[warm:])
+    stream = torch.cuda.current_stream()
 
-    def stats(lat, span):
-        m = lat[warm:] * 1e3
-        return {"p50_ms": float(np.percentile(m, 50)), "p99_ms": float(np.percentile(m, 99)),
-                "mean_ms": float(m.mean()), "tests_per_s": elems / span}
+    # plain results of every request (device call), the reference for the
+    # served bytes
+    plain_out = []
+    for a in arrays:
+        d = torch.from_numpy(a.view(np.int64)).cuda()
+        o = torch.empty(a.size, dtype=torch.uint8, device="cuda")
+        isp.isprime_into(d, o, stream)
+        plain_out.append(o)
+    torch.cuda.synchronize()
+    plain_out = [o.cpu().numpy() for o in plain_out]
 
     # Python's cyclic collector is paused and its thread switch interval
     # shortened while requests are timed: a collection pass over the many
     # request arrays, or a 5 ms wait for the interpreter lock, would delay
     # the submitting and waiting threads, not the server
     switch = sys.getswitchinterval()
+    mismatched = set()
     srv = isp.Server(max_inflight=max_inflight, max_batch_elems=max_batch_elems)
+    outs = [np.full(a.size, 2, np.uint8) for a in arrays]
+
+    def check():
+        for i, (o, p) in enumerate(zip(outs, plain_out)):
+            if not np.array_equal(o, p):
+                mismatched.add(i)
+            o.fill(2)
+
     try:
         # capacity: everything submitted at once (after one untimed pass, so
         # that the output pages and the server's buffers are already mapped)
-        outs = [np.full(a.size, 2, np.uint8) for a in arrays]
         for rep in range(2):
             t0 = time.perf_counter()
             tk = [srv.submit(a, o) for a, o in zip(arrays, outs)]
             for t in tk:
                 srv.wait(t)
             cap_s = time.perf_counter() - t0
+            check()
         capacity = num / cap_s
 
         def run_served(arrive):
@@ -389,7 +475,24 @@ def bench_served(isp, W, torch, num: int = 2100, warm: int = 100, max_inflight: 
                 tickets[i] = srv.submit(arrays[i], outs[i])
                 ready.release()
             th.join()
+            check()
             return done_t - arrive, done_t[-1] - arrive[warm]
+
+        def run_plain(arrive):
+            lat = np.zeros(num)
+            base = time.perf_counter() + 0.01
+            t_free = 0.0
+            for i, a in enumerate(arrays):
+                now = time.perf_counter() - base
+                if now < arrive[i]:
+                    time.sleep(arrive[i] - now)
+                d = torch.from_numpy(a.view(np.int64)).cuda()
+                o = torch.empty(a.size, dtype=torch.uint8, device="cuda")
+                isp.isprime_into(d, o, stream)
+                o.cpu()
+                t_free = time.perf_counter() - base
+                lat[i] = t_free - arrive[i]
+            return lat, t_free - arrive[warm]
 
         by_load = {}
         gc.disable()
@@ -397,53 +500,200 @@ def bench_served(isp, W, torch, num: int = 2100, warm: int = 100, max_inflight: 
         try:
             run_served(unit_t / (0.7 * capacity))  # untimed: threads and pages warm
             # a pass lasts about 2000 / (load x capacity) s (~60 ms at 0.7), so
-            # one stall of the host of a few ms would decide its p99 alone:
-            # each load runs SERVED_PASSES passes over the same stream and the
-            # pass with the median p99 is reported, with every pass's p99
+            # one stall of the host of a few ms decides a pass's p99 alone:
+            # each load runs SERVED_PASSES passes over the same stream
             for load in loads:
-                passes = sorted((stats(*run_served(unit_t / (load * capacity)))
-                                 for _ in range(SERVED_PASSES)), key=lambda r: r["p99_ms"])
-                med = dict(passes[len(passes) // 2])
-                med["p99_ms_passes"] = [r["p99_ms"] for r in passes]
-                by_load[str(load)] = med
+                by_load[str(load)] = _passes(run_served, unit_t / (load * capacity), warm, elems)
+            # serial plain calls: their capacity (back to back), then at 0.7 of
+            # it and at the server's 0.7 rate; the server at the former too
+            lat, _ = run_plain(np.zeros(num))  # every request waiting at time 0
+            plain_capacity = num / lat[-1]
+            plain_own = _passes(run_plain, unit_t / (0.7 * plain_capacity), warm, elems)
+            plain_at_server = _passes(run_plain, unit_t / (0.7 * capacity), warm, elems, passes=1)
+            served_at_plain = _passes(run_served, unit_t / (0.7 * plain_capacity), warm, elems)
         finally:
             sys.setswitchinterval(switch)
             gc.enable()
     finally:
         srv.close()
 
-    qps = 0.7 * capacity
-    res = {"requests": num - warm, "warmup_requests": warm, "elements": int(elems),
-           "capacity_req_per_s": capacity, "qps": qps,
-           "server": {"max_inflight": max_inflight, "max_batch_elems": max_batch_elems},
-           "served": by_load.get("0.7"), "served_by_load": by_load}
-    if not baseline:
-        return res
-    # baseline: serial plain calls in arrival order, at 0.7 of the server's capacity
-    arrive = unit_t / qps
-    gc.disable()
-    sys.setswitchinterval(1e-4)
-    try:
-        stream = torch.cuda.current_stream()
-        lat_p = np.zeros(num)
-        base = time.perf_counter() + 0.01
-        t_free = 0.0
-        for i, a in enumerate(arrays):
-            now = time.perf_counter() - base
-            if now < arrive[i]:
-                time.sleep(arrive[i] - now)
-            d = torch.from_numpy(a.view(np.int64)).cuda()
-            o = torch.empty(a.size, dtype=torch.uint8, device="cuda")
-            isp.isprime_into(d, o, stream)
-            o.cpu()
-            t_free = time.perf_counter() - base
-            lat_p[i] = t_free - arrive[i]
-        span_p = t_free - arrive[warm]
-    finally:
-        sys.setswitchinterval(switch)
-        gc.enable()
-    res["serial_plain"] = stats(lat_p, span_p)
+    head = by_load.get("0.7")
+    return {"requests": num - warm, "warmup_requests": warm, "elements": int(elems),
+            "server": {"max_inflight": max_inflight, "max_batch_elems": max_batch_elems},
+            "capacity_req_per_s": capacity, "qps": 0.7 * capacity,
+            "served": head, "served_by_load": by_load,
+            "serial_plain_capacity_req_per_s": plain_capacity,
+            "serial_plain_at_own_0.7": plain_own,
+            "served_at_serial_plain_0.7": served_at_plain,
+            "serial_plain_at_server_0.7": plain_at_server,
+            "bytes_checked_requests": num * (3 + SERVED_PASSES * (len(loads) + 1)),
+            "served_bytes_equal_plain": not mismatched,
+            "mismatched_requests": sorted(mismatched)[:20]}
+
+
+def table_crossings() -> int:
+    """Odd multiples the sieve kernel crosses off below 2^32: for each odd
+    prime 37 <= p < 2^16 (3..31 come from a periodic pre-sieve mask), every
+    odd multiple from p^2 up."""
+    lim = 1 << 16
+    s = np.ones(lim, dtype=bool)
+    s[:2] = False
+    for q in range(2, 256):
+        if s[q]:
+            s[q * q::q] = False
+    p = np.nonzero(s)[0].astype(np.int64)
+    p = p[p >= 37]
+    return int((((1 << 32) - 1 - p * p) // (2 * p) + 1).sum())
+
+
+def bench_sieve(isp, reps: int = 5) -> dict:
+    """The table build: base primes + segment sieve kernels, HIP events."""
+    times = sorted(isp.table_rebuild_ms() for _ in range(reps))
+    ms = times[len(times) // 2]
+    table_bytes = 1 << 28
+    cr = table_crossings()
+    return {"kernel_ms": ms, "kernel_ms_all": times, "table_bytes": table_bytes,
+            "write_GBps": table_bytes / (ms * 1e-3) / 1e9,
+            "write_frac_of_hbm": table_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "crossings": cr, "crossings_per_s": cr / (ms * 1e-3)}
+
+
+def classify_bytes(a: np.ndarray) -> int:
+    """Algorithmic HBM bytes of classify_kernel: 8 B read and 1 B written
+    per element, plus one 4-byte table word per odd element in [3, 2^32)."""
+    look = (a > np.uint64(2)) & (a < np.uint64(1 << 32)) & ((a & np.uint64(1)) == 1)
+    return 9 * a.size + 4 * int(look.sum())
+
+
+def measure_plain(isp, torch, a: np.ndarray, steps: int, warmup: int, stages: bool = True) -> dict:
+    """K timed steps of one plain call over a resident array (HIP events on
+    the call's stream), then K profiled steps (events around each kernel)."""
+    dev = torch.from_numpy(a.view(np.int64)).cuda()
+    out = torch.empty(a.size, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        isp.isprime_into(dev, out, stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        isp.isprime_into(dev, out, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    res = {"len": int(a.size), "ms_per_step": ms, "tests_per_s": a.size / (ms * 1e-3),
+           "got": out.cpu().numpy()}
+    res["survivors"], res["base2_passers"] = isp.last_counts(stream)
+    if stages:
+        isp.profile(True)
+        for _ in range(steps):
+            isp.isprime_into(dev, out, stream)
+        prof = isp.profile_read()
+        isp.profile(False)
+        calls = max(1, prof["calls"])
+        res["stage_ms"] = {k: prof[k] / calls for k in isp.STAGES}
+    del dev, out
     return res
+
+
+def roofline_of(a: np.ndarray, got: np.ndarray, stage_ms: dict, filter_primes: int,
+                planted, summary: str):
+    """The roofline of the slowest kernel of one call, and the VALU fraction
+    of both Miller-Rabin kernels."""
+    work, n_surv, n_prime = mr_work(a, got, filter_primes, planted)
+    dom = max(("classify", "filter2", "mr_base2", "mr_rest"), key=lambda k: stage_ms[k])
+    other = {}
+    for k in ("mr_base2", "mr_rest"):
+        ach = work[k]["ops"] / (stage_ms[k] * 1e-3) / 1e9
+        other[k] = {"achieved": ach, "frac": ach / VALU_PEAK_GOPS}
+    if dom in ("classify", "filter2"):
+        b = classify_bytes(a)
+        ach = b / (stage_ms["classify"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": counter_traffic("classify", summary),
+                "kernel": "classify", "bytes_per_launch": b, "ms_per_launch": stage_ms["classify"]}
+    else:
+        ach = work[dom]["ops"] / (stage_ms[dom] * 1e-3) / 1e9
+        roof = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_GOPS,
+                "unit": "Gop/s", "frac": ach / VALU_PEAK_GOPS,
+                "traffic": counter_traffic(dom, summary),
+                "kernel": dom, "op": "VALU lane-instruction",
+                "ms_per_launch": stage_ms[dom],
+                "montmul_per_launch": work[dom]["montmul"],
+                "doublings_per_launch": work[dom]["doublings"],
+                "ops_per_montmul": OPS_PER_MONTMUL, "ops_per_doubling": OPS_PER_DOUBLING}
+    return roof, other, work, n_surv, n_prime
+
+
+def host_cpus() -> dict:
+    """The host's CPU model, its logical CPU count, this process's affinity
+    set and its cgroup CPU quota (when one is set)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    quota = None
+    try:
+        q, per = open("/sys/fs/cgroup/cpu.max").read().split()
+        if q != "max":
+            quota = int(q) / int(per)
+    except (OSError, ValueError):
+        pass
+    aff = len(os.sched_getaffinity(0))
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": aff,
+            "cgroup_cpu_quota": quota}
+
+
+# The share of host CPUs a one-GPU job gets on the measuring machine; the
+# oracle's thread count never exceeds it (more threads than the share only
+# time-slice against each other).
+JOB_CPU_SHARE = 16
+
+
+def cpu_baseline(W, a: np.ndarray, got: np.ndarray, one_len: int = 1 << 21,
+                 all_len: int = 1 << 24, runs: int = 3):
+    """The oracle (plain C: table below 2^32, Miller-Rabin with 128-bit
+    products above) on the host: its 2^32 table build timed alone, then a
+    bounded prefix of the same input on 1 thread and on the job's CPUs,
+    median of `runs` each; then the whole workload once on the job's CPUs
+    for parity (not timed)."""
+    import oracle
+    info = host_cpus()
+    threads = info["affinity_cpus"]
+    if info["cgroup_cpu_quota"]:
+        threads = min(threads, max(1, int(info["cgroup_cpu_quota"])))
+    threads = min(threads, JOB_CPU_SHARE)
+    t0 = time.perf_counter()
+    oracle.table()
+    table_s = time.perf_counter() - t0
+
+    def median_rate(sample, nthreads):
+        times, used = [], 0
+        for _ in range(runs):
+            t1 = time.perf_counter()
+            _, used = oracle.isprime_array(sample, nthreads=nthreads, use_table=True)
+            times.append(time.perf_counter() - t1)
+        times.sort()
+        return sample.size / times[len(times) // 2], used, times
+
+    one_rate, _, one_t = median_rate(a[:one_len], 1)
+    all_rate, used, all_t = median_rate(a[:all_len], threads)
+    exp, _ = oracle.isprime_array(a, nthreads=threads, use_table=True)
+    bit_exact = bool(np.array_equal(exp, got))
+    cpu = {"value": all_rate, "unit": "tests/s", "cores": used, "kind": "oracle",
+           "sample": "the first %d elements of the workload on %d threads (median of %d runs: "
+                     "%s s); 1 thread: the first %d elements, median of %d (%s s); the oracle's "
+                     "2^32 table build (%.2f s) timed apart" % (
+                         all_len, used, runs, "/".join("%.2f" % t for t in all_t), one_len,
+                         runs, "/".join("%.2f" % t for t in one_t), table_s),
+           "one_thread_tests_per_s": one_rate, "all_threads_tests_per_s": all_rate,
+           "threads": used, "table_build_s": table_s, "runs": runs}
+    cpu.update(info)
+    return cpu, bit_exact
 
 
 def main() -> int:
@@ -453,11 +703,16 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the batched and served measurements")
+                    help="skip everything after the headline and 64-bit workloads")
+    ap.add_argument("--workload", default=None, choices=("c3_mixed", "c2_mr64", "lookup32"),
+                    help="only time this workload's plain calls (--warmup, then --steps timed "
+                         "and --steps with per-kernel events; for profiling)")
     ap.add_argument("--intervals-only", action="store_true",
-                    help="only time the interval call on its five cases (for profiling its kernels)")
+                    help="only time the interval call on its cases (for profiling its kernels)")
     ap.add_argument("--wheel-only", action="store_true",
                     help="only time the wheel stage against Miller-Rabin per octave")
+    ap.add_argument("--sieve-only", action="store_true",
+                    help="only rebuild the table --steps times (for profiling the sieve kernel)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters)")
@@ -480,10 +735,11 @@ def main() -> int:
     import workloads as W
 
     torch.cuda.set_device(0)
-    t0 = time.perf_counter()
     isp.init(0)
     torch.cuda.synchronize()
-    sieve_ms = (time.perf_counter() - t0) * 1e3
+    if args.sieve_only:
+        print(json.dumps({"sieve": bench_sieve(isp, reps=args.steps)}))
+        return 0
     if args.intervals_only:
         print(json.dumps({"intervals": bench_intervals(isp, torch, reps=args.steps,
                                                        array_call=False)}))
@@ -494,93 +750,76 @@ def main() -> int:
 
     from paper_2108_04791_amd import tune
     defaults = isp.get_config()
-    a = W.c2_mr64()
+
+    def with_tuning(key, length, fn):
+        isp.set_config(**defaults)
+        tuned = tune.apply(key, length) is not None
+        res = fn()
+        res["tuning"] = isp.get_config()
+        res["tuning_source"] = "autotuner database" if tuned else "library defaults"
+        isp.set_config(**defaults)
+        return res
+
+    gens = {"c3_mixed": W.c3_mixed, "c2_mr64": W.c2_mr64, "lookup32": W.lookup32}
+    if args.workload:
+        a = gens[args.workload]()
+        key = "c3_mixed" if args.workload == "lookup32" else args.workload
+        r = with_tuning(key, a.size, lambda: measure_plain(isp, torch, a, args.steps, args.warmup))
+        r.pop("got")
+        print(json.dumps({"workload": args.workload, **r}))
+        return 0
+
+    # ---- the headline: the mixed-magnitude array
+    a = W.c3_mixed()
     n = a.size
-    tuned = tune.apply("c2_mr64", n) is not None  # autotuned launch parameters, if recorded
-    dev = torch.from_numpy(a.view(np.int64)).cuda()
-    out = torch.empty(n, dtype=torch.uint8, device="cuda")
-    stream = torch.cuda.current_stream()
-    cfg = isp.get_config()
-
-    for _ in range(args.warmup):
-        isp.isprime_into(dev, out, stream)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        isp.isprime_into(dev, out, stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
-    ms_per_step = total_ms / args.steps
-    value = n / (ms_per_step * 1e-3)
-    got = out.cpu().numpy()
-
-    # per-stage durations: HIP events around each kernel on the call's stream
-    isp.profile(True)
-    for _ in range(args.steps):
-        isp.isprime_into(dev, out, stream)
-    prof = isp.profile_read()
-    isp.profile(False)
-    calls = max(1, prof["calls"])
-    stage_ms = {k: prof[k] / calls for k in isp.STAGES}
+    head = with_tuning("c3_mixed", n, lambda: measure_plain(isp, torch, a, args.steps, args.warmup))
+    got = head.pop("got")
+    cfg = head["tuning"]
+    stage_ms = head["stage_ms"]
+    roofline, alu_other, work, n_surv, n_prime = roofline_of(
+        a, got, stage_ms, max(0, cfg["filter_primes"]), W.chernick_values(), "pmc_c3_mixed.md")
+    lookup_bytes = classify_bytes(a)
+    classify_gbps = lookup_bytes / (stage_ms["classify"] * 1e-3) / 1e9
 
     # the Baillie-PSW alternative on the same input (base 2, then a strong
     # Lucas test instead of the six remaining bases): same bytes, timed alike
-    alt = {}
-    isp.set_config(rest_test=1)
-    isp.profile(True)
-    for _ in range(args.steps):
-        isp.isprime_into(dev, out, stream)
-    p2 = isp.profile_read()
-    isp.profile(False)
-    isp.set_config(rest_test=-1)
-    c2 = max(1, p2["calls"])
-    alt_ms = {k: p2[k] / c2 for k in isp.STAGES}
-    alt["bpsw"] = {"stage_ms": alt_ms, "ms_per_step_events": sum(alt_ms.values()),
-                   "tests_per_s": n / (sum(alt_ms.values()) * 1e-3),
-                   "same_bytes": bool(np.array_equal(out.cpu().numpy(), got))}
-    isp.isprime_into(dev, out, stream)
-    torch.cuda.synchronize()
+    def bpsw():
+        isp.set_config(rest_test=1)
+        r = measure_plain(isp, torch, a, args.steps, 1)
+        return {"stage_ms": r["stage_ms"], "ms_per_step": r["ms_per_step"],
+                "tests_per_s": r["tests_per_s"], "same_bytes": bool(np.array_equal(r["got"], got))}
+    alt = {"bpsw": with_tuning("c3_mixed", n, bpsw)}
 
-    work, n_surv, n_prime = mr_work(a, got, max(0, cfg["filter_primes"]))
-    dom = max(("mr_base2", "mr_rest", "classify"), key=lambda k: stage_ms[k])
-    if dom == "classify":
-        bytes_per_launch = n * 9.0
-        achieved = bytes_per_launch / (stage_ms[dom] * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(dom), "kernel": dom}
-    else:
-        achieved = work[dom]["ops"] / (stage_ms[dom] * 1e-3) / 1e9
-        roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GOPS,
-                    "unit": "Gop/s", "frac": achieved / VALU_PEAK_GOPS,
-                    "traffic": counter_traffic(dom),
-                    "kernel": dom, "op": "VALU lane-instruction",
-                    "montmul_per_launch": work[dom]["montmul"],
-                    "doublings_per_launch": work[dom]["doublings"],
-                    "ops_per_montmul": OPS_PER_MONTMUL, "ops_per_doubling": OPS_PER_DOUBLING}
-    other = {}
-    for k in ("mr_base2", "mr_rest"):
-        ach = work[k]["ops"] / (stage_ms[k] * 1e-3) / 1e9
-        other[k] = {"achieved": ach, "frac": ach / VALU_PEAK_GOPS}
+    # ---- the 64-bit Miller-Rabin array (the Montgomery kernels at full width)
+    a2 = W.c2_mr64()
+    c2 = with_tuning("c2_mr64", a2.size, lambda: measure_plain(isp, torch, a2, args.steps, args.warmup))
+    got2 = c2.pop("got")
+    c2_roof, c2_alu, _, _, _ = roofline_of(a2, got2, c2["stage_ms"],
+                                           max(0, c2["tuning"]["filter_primes"]), None,
+                                           "pmc_c2_mr64.md")
+    c2.update({"workload": "c2_mr64: 2^24 uint64 rejection-uniform in [2^49, 2^64), half forced "
+                           "odd, splitmix64 seed 0x2108047900000002",
+               "input_sha256_16": W.digest(a2), "roofline": c2_roof, "alu_frac_by_kernel": c2_alu,
+               "primes": int(got2.sum())})
 
     forms = {}
     if not args.no_forms:
-        def with_tuning(key, length, fn):
-            isp.set_config(**defaults)
-            tune.apply(key, length)
-            res = fn()
-            res["tuning"] = isp.get_config()
-            isp.set_config(**defaults)
-            return res
-
-        c1, c3 = W.c1_uniform20(), W.c3_mixed()
-        forms["other_workloads"] = {
-            "c1_uniform20": with_tuning("c1_uniform20", c1.size, lambda: bench_plain(isp, torch, c1)),
-            "c3_mixed": with_tuning("c3_mixed", c3.size, lambda: bench_plain(isp, torch, c3, reps=5)),
-        }
-        del c3
+        c1 = W.c1_uniform20()
+        r1 = with_tuning("c1_uniform20", c1.size, lambda: measure_plain(isp, torch, c1, 50, 5))
+        r1.pop("got")
+        forms["c1_uniform20"] = r1
+        lk = W.lookup32()
+        rl = with_tuning("c3_mixed", lk.size, lambda: measure_plain(isp, torch, lk, args.steps, 2))
+        rl.pop("got")
+        b = classify_bytes(lk)
+        rl.update({"workload": "2^26 uint64 uniform in [0, 2^32) (every odd value a table lookup), "
+                               "splitmix64 seed 0x2108047900000008",
+                   "classify_bytes": b,
+                   "classify_GBps": b / (rl["stage_ms"]["classify"] * 1e-3) / 1e9})
+        rl["classify_frac_of_hbm"] = rl["classify_GBps"] / HBM_PEAK_GBS
+        del lk
+        forms["lookup32"] = rl
+        forms["sieve"] = bench_sieve(isp)
         forms["batched"] = with_tuning("c4_batched", 25341952, lambda: bench_batched(isp, W, torch))
         forms["served"] = bench_served(isp, W, torch)
         isp.set_config(**defaults)
@@ -588,48 +827,77 @@ def main() -> int:
         forms["intervals"] = bench_intervals(isp, torch)
         forms["wheel_vs_miller_rabin"] = bench_wheel(isp, W, torch)
 
-    cpu = None
-    bit_exact = None
+    cpu, bit_exact = None, None
     if not args.no_cpu_baseline:
-        import oracle
-        threads = min(16, os.cpu_count() or 1)
-        t1 = time.perf_counter()
-        exp, used = oracle.isprime_array(a, nthreads=threads, use_table=False)
-        cpu_s = time.perf_counter() - t1
-        bit_exact = bool(np.array_equal(exp, got))
-        cpu = {"value": n / cpu_s, "unit": "tests/s", "cores": used, "kind": "oracle",
-               "sample": "the whole workload (%d elements), %d threads, %.2f s" % (n, used, cpu_s)}
+        cpu, bit_exact = cpu_baseline(W, a, got)
 
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": n / (head["ms_per_step"] * 1e-3),
         "unit": "tests/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "c2_mr64: 2^24 uint64 rejection-uniform in [2^49, 2^64), half "
-                               "forced odd, splitmix64 seed 0x2108047900000002",
-                   "len": n, "input_sha256_16": W.digest(a), "tuning": cfg,
-                   "tuning_source": "autotuner database" if tuned else "library defaults"},
+        "config": {"workload": "c3_mixed: 2^26 uint64, 5% Chernick numbers, 1% {2047, 3215031751, "
+                               "2^61-1}, the rest octave-uniform, splitmix64 seed 0x2108047900000003",
+                   "len": n, "input_sha256_16": W.digest(a),
+                   "tuning_source": head["tuning_source"], "tuning": cfg},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "bit_exact_vs_oracle": bit_exact,
         "stage_ms": stage_ms,
-        "alu_frac_by_kernel": other,
-        "alternatives": alt,
+        "alu_frac_by_kernel": alu_other,
+        "classify_GBps": classify_gbps,
         "survivors": n_surv,
+        "base2_passers": head["base2_passers"],
         "primes": int(got.sum()),
-        "sieve_build_ms": sieve_ms,
+        "alternatives": alt,
+        "c2_mr64": c2,
     }
     line.update(forms)
+    # last: the figures in brief (scalars only)
+    summ = {"c3_tests_per_s": line["value"], "c3_ms": head["ms_per_step"],
+            "c3_bit_exact": bit_exact, "roofline_kernel": roofline["kernel"],
+            "roofline_frac": roofline["frac"]}
+    summ.update({"c3_%s_ms" % k: v for k, v in stage_ms.items()})
+    summ.update({"c2_tests_per_s": c2["tests_per_s"], "c2_ms": c2["ms_per_step"],
+                 "c2_mr_rest_frac": c2_alu["mr_rest"]["frac"],
+                 "c2_mr_base2_frac": c2_alu["mr_base2"]["frac"],
+                 "c3_mr_rest_frac": alu_other["mr_rest"]["frac"],
+                 "c3_mr_base2_frac": alu_other["mr_base2"]["frac"],
+                 "c3_classify_GBps": classify_gbps,
+                 "bpsw_c3_ms": alt["bpsw"]["ms_per_step"]})
+    if forms:
+        sv = forms["served"]
+        summ.update({"c1_ms": forms["c1_uniform20"]["ms_per_step"],
+                     "lookup32_classify_GBps": forms["lookup32"]["classify_GBps"],
+                     "lookup32_ms": forms["lookup32"]["ms_per_step"],
+                     "sieve_kernel_ms": forms["sieve"]["kernel_ms"],
+                     "sieve_write_GBps": forms["sieve"]["write_GBps"],
+                     "sieve_crossings_per_s": forms["sieve"]["crossings_per_s"],
+                     "batched_ms": forms["batched"]["batched"]["ms"],
+                     "batched_speedup": forms["batched"]["speedup"],
+                     "served_p50_ms": sv["served"]["p50_ms"], "served_p99_ms": sv["served"]["p99_ms"],
+                     "served_pooled_p99_ms": sv["served"]["pooled_p99_ms"],
+                     "served_bytes_equal_plain": sv["served_bytes_equal_plain"],
+                     "plain_own07_p50_ms": sv["serial_plain_at_own_0.7"]["p50_ms"],
+                     "plain_own07_p99_ms": sv["serial_plain_at_own_0.7"]["p99_ms"],
+                     "served_at_plain07_p50_ms": sv["served_at_serial_plain_0.7"]["p50_ms"],
+                     "served_at_plain07_p99_ms": sv["served_at_serial_plain_0.7"]["p99_ms"]})
+    if cpu:
+        summ.update({"cpu_1t_tests_per_s": cpu["one_thread_tests_per_s"],
+                     "cpu_all_tests_per_s": cpu["all_threads_tests_per_s"],
+                     "cpu_threads": cpu["threads"], "cpu_nproc": cpu["nproc"]})
+    line["summary"] = summ
     print(json.dumps(line), flush=True)
-    return 0 if bit_exact in (None, True) else 1
+    ok = bit_exact in (None, True) and (not forms or forms["served"]["served_bytes_equal_plain"])
+    return 0 if ok else 1
 
 
 if __name__ == "__main__":

@@ -203,14 +203,23 @@ int isp_last_counts(void *stream, uint64_t *survivors, uint64_t *candidates);
  * stops recording.  Meant for one measuring thread.
  * isp_profile_read: ms[ISP_NUM_STAGES] totals and the number of calls. */
 enum {
-    ISP_STAGE_CLASSIFY = 0, /* dispatch + table lookup + both trial-filter stages +
-                               compaction (+ the wheel stage when selected) */
-    ISP_STAGE_MR_BASE2 = 1, /* Miller-Rabin base 2 over all survivors */
-    ISP_STAGE_MR_REST = 2,  /* Miller-Rabin bases 325 .. 1795265022 over base-2 passers */
-    ISP_NUM_STAGES = 3
+    ISP_STAGE_CLASSIFY = 0, /* classify_kernel: dispatch + table lookup + first trial-filter
+                               stage + compaction (a call that runs as the fused
+                               small-array kernel: all of its time) */
+    ISP_STAGE_FILTER2 = 1,  /* second trial-filter stage (+ the wheel stage when selected) */
+    ISP_STAGE_MR_BASE2 = 2, /* Miller-Rabin base 2 over all survivors */
+    ISP_STAGE_MR_REST = 3,  /* Miller-Rabin bases 325 .. 1795265022 over base-2 passers */
+    ISP_NUM_STAGES = 4
 };
 int isp_profile(int enable);
 int isp_profile_read(double *ms, uint64_t *calls);
+
+/* Rebuild the sieve table of `device` in place and time the build kernels
+ * (base primes, then the segment sieve) with HIP events on a private
+ * stream: *ms receives the elapsed milliseconds.  Synchronises the device
+ * first; no call may be in flight on it (the table is rewritten with the
+ * same bits).  For measurement only. */
+int isp_table_rebuild(int device, double *ms);
 
 /* ---------------------------------------------------------------- serving
  * A request loop with continuous batching.  Requests carry HOST buffers

@@ -100,6 +100,7 @@ SIGNATURES = {
     "isp_last_counts": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "isp_profile": (_I, [_I]),
     "isp_profile_read": (_I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_U64)]),
+    "isp_table_rebuild": (_I, [_I, ctypes.POINTER(ctypes.c_double)]),
     "isp_server_create": (_I, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_P)]),
     "isp_submit": (_I, [_P, _P, _P, _SZ, ctypes.POINTER(_U64)]),
     "isp_poll": (_I, [_P, _U64]),
@@ -295,6 +296,16 @@ def table(device: int | None = None) -> torch.Tensor:
     return out
 
 
+def table_rebuild_ms(device: int | None = None) -> float:
+    """Rebuild the device's sieve table in place; the build kernels' time in
+    ms (HIP events).  Nothing may be in flight on the device."""
+    if device is None:
+        device = torch.cuda.current_device()
+    ms = ctypes.c_double()
+    _check(lib().isp_table_rebuild(device, ctypes.byref(ms)), "isp_table_rebuild")
+    return ms.value
+
+
 def last_counts(stream=None):
     """(trial-filter survivors, base-2 passers) of the last call on the stream."""
     s, c = _U64(), _U64()
@@ -303,7 +314,7 @@ def last_counts(stream=None):
     return s.value, c.value
 
 
-STAGES = ("classify", "mr_base2", "mr_rest")
+STAGES = ("classify", "filter2", "mr_base2", "mr_rest")
 
 
 def profile(enable: bool) -> None:

@@ -330,30 +330,30 @@ int run_plain(const uint64_t *n, uint8_t *out, size_t len, const DeviceState &ds
         if (prof && e == hipSuccess)
             e = hipEventRecord(g_prof_ev[k], s);
     };
-    mark(0);
+    mark(ISP_STAGE_CLASSIFY);
     if (small_call(len, t)) {
         // one fused launch; its time counts as the classify stage
         if (e == hipSuccess)
             e = launch_small(n, out, len, ds.table, t.filter_primes, s);
-        mark(1);
-        mark(2);
-        mark(3);
+        for (int k = ISP_STAGE_CLASSIFY + 1; k <= ISP_NUM_STAGES; ++k)
+            mark(k);
     } else {
         if (e == hipSuccess)
             e = launch_classify(ca, grid_c, t.classify_block, t.classify_ept, s);
+        mark(ISP_STAGE_FILTER2);
         if (e == hipSuccess)
             e = launch_filter2(ws.surv, ws.counts, grid_c, len, nullptr, t.filter_primes, s);
         if (e == hipSuccess && t.wheel_log2)
             e = launch_wheel(ws.surv, ws.counts, grid_c, len, nullptr, t.wheel_log2, s);
-        mark(1);
+        mark(ISP_STAGE_MR_BASE2);
         if (e == hipSuccess)
             e = launch_mr1(ma, t.mr_block, s);
-        mark(2);
+        mark(ISP_STAGE_MR_REST);
         if (e == hipSuccess)
             e = t.rest_test ? launch_lucas(ma, ds.cus, t.mr_blocks_per_cu, grid1, t.mr_block, s)
                             : launch_mr2(ma, ds.cus, t.mr_blocks_per_cu, grid1, t.mr_block,
                                          t.mr_window, s);
-        mark(3);
+        mark(ISP_NUM_STAGES);
     }
     if (prof && e == hipSuccess) {
         e = hipEventSynchronize(g_prof_ev[ISP_NUM_STAGES]);
@@ -1104,6 +1104,59 @@ int isp_profile_read(double *ms, uint64_t *calls)
     for (int k = 0; k < ISP_NUM_STAGES; ++k)
         ms[k] = g_prof_ms[k];
     *calls = g_prof_calls;
+    return ISP_OK;
+}
+
+int isp_table_rebuild(int device, double *ms)
+{
+    if (!ms)
+        return ISP_EINVAL;
+    int st = isp_init(device);
+    if (st != ISP_OK)
+        return st;
+    std::lock_guard<std::mutex> g(g_init_mu);
+    DeviceState &ds = g_dev[device];
+    int prev = 0;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess)
+        return fail(e);
+    e = hipSetDevice(device);
+    if (e != hipSuccess)
+        return fail(e);
+    hipStream_t s = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    e = hipDeviceSynchronize();
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+        e = hipEventCreate(&ev[k]);
+    if (e == hipSuccess)
+        e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess)
+        e = launch_base_primes(ds, s);
+    if (e == hipSuccess)
+        e = launch_sieve(ds, s);
+    if (e == hipSuccess)
+        e = hipEventRecord(ev[1], s);
+    uint32_t count = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&count, ds.base_count, sizeof(count), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    float elapsed = 0;
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&elapsed, ev[0], ev[1]);
+    if (e == hipSuccess && count != 6541)
+        e = hipErrorUnknown;
+    for (auto &x : ev)
+        if (x)
+            (void)hipEventDestroy(x);
+    if (s)
+        (void)hipStreamDestroy(s);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess)
+        return fail(e);
+    *ms = elapsed;
     return ISP_OK;
 }
 

@@ -63,15 +63,79 @@ def test_mr_work_by_brute_force():
         assert work["mr_rest"]["montmul"] == mm
 
 
+def test_planted_pseudoprimes_by_the_oracle():
+    """The bases a composite that passes base 2 runs (through its first
+    failing one), against the oracle's strong-test round, on every Chernick
+    number above 2^32 and on F5 = 2^32 + 1 and 3825123056546413051."""
+    import workloads as W
+    bases = oracle.mr_bases()
+    assert tuple(bases[1:]) == bench.BASES_AFTER_2
+    planted = np.concatenate([W.chernick_values(),
+                              np.array([(1 << 32) + 1, 3825123056546413051], dtype=np.uint64)])
+    a = np.concatenate([planted, np.array([2047, (1 << 61) - 1, 7], dtype=np.uint64)])
+    got = bench.planted_pseudoprime_bases(a, planted)
+    passers = 0
+    for n, k in zip(a.tolist(), got.tolist()):
+        if n < (1 << 32) or n % 2 == 0 or not oracle.strong_probable_prime(n, 2):
+            assert k == 0, n
+            continue
+        ran = 0
+        for b in bases[1:]:
+            ran += 1
+            if not oracle.strong_probable_prime(n, b):
+                break
+        else:
+            ran = 0  # passes all seven (prime): not a planted pseudoprime
+        assert k == ran, (n, k, ran)
+        passers += k > 0
+    # 251 of the Chernick numbers above 2^32 pass base 2, as do F5 and
+    # 3825123056546413051 (a strong pseudoprime to every prime base below
+    # 37), which passes 325 and 9375 and fails 28178
+    assert passers == 253
+    assert got[planted.size - 1] == 3
+
+
+def test_mr_work_counts_planted_passers():
+    import workloads as W
+    cher = W.chernick_values()
+    a = cher[cher >= np.uint64(1 << 32)]
+    prime, _ = oracle.isprime_array(a, use_table=False)
+    assert prime.sum() == 0
+    work, _, _ = bench.mr_work(a, prime, 16, cher)
+    nb = bench.planted_pseudoprime_bases(a, cher)
+    mm = 0
+    for n, k in zip(a.tolist(), nb.tolist()):
+        d = n - 1
+        while d % 2 == 0:
+            d //= 2
+        mm += k * ((n.bit_length() - 2) + (bin(d).count("1") - 1))
+    assert work["mr_rest"]["montmul"] == mm > 0
+    assert work["mr_rest"]["passers_counted"] == int((nb > 0).sum()) == 251
+
+
+def test_classify_bytes_and_crossings():
+    a = np.array([0, 1, 2, 3, 4, 5, (1 << 32) - 1, 1 << 32, (1 << 32) + 1], dtype=np.uint64)
+    assert bench.classify_bytes(a) == 9 * a.size + 4 * 3
+    # crossings: odd multiples of each prime 37 <= p < 2^16 from p^2 below 2^32
+    ps = [p for p in range(37, 1 << 16, 2) if all(p % q for q in range(3, int(p ** 0.5) + 1, 2))]
+    assert len(ps) == 6541 - 10
+    assert bench.table_crossings() == sum(((1 << 32) - 1 - p * p) // (2 * p) + 1 for p in ps)
+
+
 def test_counter_traffic_follows_the_source_hash():
     h = bench.kernel_source_hash()
     assert h == bench.kernel_source_hash() and len(h) == 16
-    recorded = None
-    for line in open(os.path.join(ROOT, "profiles", "pmc_c2_mr64.md")):
-        if line.startswith("source_sha256_16:"):
-            recorded = line.split(":", 1)[1].strip()
-    t = bench.counter_traffic("mr_rest")
-    if recorded == h:
-        assert isinstance(t, int) and t > 0
-    else:
-        assert t is None
+    for summary in ("pmc_c3_mixed.md", "pmc_c2_mr64.md"):
+        path = os.path.join(ROOT, "profiles", summary)
+        if not os.path.exists(path):
+            assert bench.counter_traffic("mr_rest", summary) is None
+            continue
+        recorded = None
+        for line in open(path):
+            if line.startswith("source_sha256_16:"):
+                recorded = line.split(":", 1)[1].strip()
+        t = bench.counter_traffic("mr_rest", summary)
+        if recorded == h:
+            assert isinstance(t, int) and t > 0
+        else:
+            assert t is None

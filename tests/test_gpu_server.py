@@ -82,3 +82,30 @@ def test_served_split_request_and_threads(isp):
             x.join()
         assert not errors
         assert np.array_equal(out, exp_big)
+
+
+def test_served_at_the_benchmarked_configuration(isp):
+    """The server as the benchmark runs it (the defaults: 6 slots of 2^20
+    elements, the staging helper threads) on the first 300 requests of the
+    benchmark's own stream (lengths log-uniform in [1, 2^20]): every result
+    equals the oracle's, submitted all at once (packed into shared batches)
+    and one at a time."""
+    reqs = [r for _, r, _ in W.c5_requests(300, qps=1.0)]
+    assert max(r.size for r in reqs) > (1 << 19)
+    exp = [oracle.isprime_array(r, nthreads=NTHREADS, use_table=True)[0] for r in reqs]
+    with isp.Server() as srv:
+        mixed = [np.full(r.size, 2, np.uint8) for r in reqs]
+        tickets = [srv.submit(r, o) for r, o in zip(reqs, mixed)]
+        for t in tickets:
+            srv.wait(t)
+        alone = []
+        for r in reqs[:60]:
+            o = np.full(r.size, 2, np.uint8)
+            srv.wait(srv.submit(r, o))
+            alone.append(o)
+    for i, (o, e) in enumerate(zip(mixed, exp)):
+        bad = np.nonzero(o != e)[0]
+        assert bad.size == 0, "request %d (%d values): mismatch at %s" % (i, e.size, bad[:10].tolist())
+    for o, m in zip(alone, mixed):
+        assert np.array_equal(o, m)
+

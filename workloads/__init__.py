@@ -29,6 +29,7 @@ is measured on):
 * ``odd_band``       odd values uniform in one octave [2^(b-1), 2^b) (the
                      wheel-against-Miller-Rabin comparison, one octave at a
                      time).
+* ``lookup32``       2^26 values uniform in [0, 2^32): the table lookup alone.
 
 ``paper_arrays()`` rebuilds the array workloads of the paper's
 incrementing-sequence table (section 6.1.3) and array-performance table
@@ -60,6 +61,7 @@ SEED_C4 = 0x2108047900000004
 SEED_C5 = 0x2108047900000005
 SEED_PAPER = 0x2108047900000006
 SEED_BAND = 0x2108047900000007
+SEED_LOOKUP = 0x2108047900000008
 
 # Magnitude classes of the batched and served workloads: [lo, hi) as
 # (shift, lo): a draw r gives r >> shift, accepted when >= lo.
@@ -129,6 +131,13 @@ def odd_band(n: int, bits: int, seed: int = SEED_BAND, start: int = 0) -> np.nda
     idx = np.arange(start, start + n, dtype=np.uint64)
     v = element_draws(seed ^ bits, idx, 0) >> np.uint64(65 - bits)
     return v | np.uint64(1 << (bits - 1)) | np.uint64(1)
+
+
+def lookup32(n: int = 1 << 26, seed: int = SEED_LOOKUP, start: int = 0) -> np.ndarray:
+    """n values uniform in [0, 2^32): every odd one is answered by the table
+    (the lookup path alone, over the whole 256 MiB table)."""
+    idx = np.arange(start, start + n, dtype=np.uint64)
+    return element_draws(seed, idx, 0) >> np.uint64(32)
 
 
 def chernick_k() -> np.ndarray:
