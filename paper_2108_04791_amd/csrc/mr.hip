@@ -424,19 +424,18 @@ __device__ __forceinline__ uint64_t call_total(const MrArgs &a)
 }
 
 // Passers of one phase-1 workgroup, grouped before their constants are
-// written (when there are at most PASS_PER_THREAD per thread): by
-// bit-length class (64, 63, below) and then by s, so that a phase-2
+// written (when there are at most PASS_PER_THREAD per thread): by bit
+// length (64 down to 33) and then by s (1 .. 4, >= 5), so that a phase-2
 // wavefront's tasks share the window count of their d, the length of their
 // -1 chain and the form of their products.
 constexpr int PASS_PER_THREAD = 4;
-constexpr int PASS_BINS = 15;
+constexpr int PASS_S_KEYS = 5;
+constexpr int PASS_BINS = 32 * PASS_S_KEYS;
 
 __device__ __forceinline__ int pass_key(uint64_t n)
 {
-    const int L = 64 - __clzll(n);
-    const int lc = L == 64 ? 0 : L == 63 ? 1 : 2;
     const int s = __ffsll((long long)(n - 1)) - 1;  // >= 1: n is odd
-    return lc * 5 + (s < 5 ? s : 5) - 1;
+    return __clzll(n) * PASS_S_KEYS + (s < PASS_S_KEYS ? s : PASS_S_KEYS) - 1;
 }
 
 __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
@@ -507,18 +506,36 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
             // PASS_PER_THREAD) entries into registers before any is rewritten
             __shared__ uint16_t perm[PASS_PER_THREAD * MR_MAX_BLOCK];
             __shared__ uint32_t bins[PASS_BINS];
-            if (threadIdx.x < PASS_BINS)
-                bins[threadIdx.x] = 0;
+            for (int b = threadIdx.x; b < PASS_BINS; b += blockDim.x)
+                bins[b] = 0;
             __syncthreads();
             for (uint32_t i = threadIdx.x; i < npass; i += blockDim.x)
                 atomicAdd(&bins[pass_key(region[i].n)], 1u);
             __syncthreads();
-            if (threadIdx.x == 0) {
-                uint32_t run = 0;
-                for (int b = 0; b < PASS_BINS; ++b) {
-                    const uint32_t c = bins[b];
-                    bins[b] = run;
-                    run += c;
+            if (threadIdx.x < 64) {
+                // exclusive scan of the bins by the first wavefront, each
+                // lane summing a run of consecutive bins
+                constexpr int PER = (PASS_BINS + 63) / 64;
+                const int b0 = lane * PER;
+                uint32_t local = 0;
+#pragma unroll
+                for (int q = 0; q < PER; ++q)
+                    local += b0 + q < PASS_BINS ? bins[b0 + q] : 0u;
+                uint32_t incl = local;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t y = __shfl_up(incl, o, 64);
+                    if (lane >= o)
+                        incl += y;
+                }
+                uint32_t run = incl - local;
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    if (b0 + q < PASS_BINS) {
+                        const uint32_t c = bins[b0 + q];
+                        bins[b0 + q] = run;
+                        run += c;
+                    }
                 }
             }
             __syncthreads();
