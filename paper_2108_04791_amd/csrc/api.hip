@@ -291,6 +291,9 @@ void make_args(const DeviceState &ds, const Workspace &ws, const Tuning &t, size
     ma.cand = ws.cand;
     ma.prep = t.rest_test > 0 ? nullptr : ws.prep;
     ma.counts1 = ws.counts + MAX_GRID;
+    // phase 2's list of the candidates that pass base 325: the survivor
+    // regions, free once phase 1 has read them (at least 4 words per element)
+    ma.keep = reinterpret_cast<uint32_t *>(ws.surv);
 }
 
 // Per-stage event timing (isp_profile).  Used by one measuring thread.

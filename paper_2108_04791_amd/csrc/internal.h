@@ -105,6 +105,8 @@ struct MrArgs {
     MontPrep *prep;              // the passers' constants, indexed like cand (or null:
                                  // not needed by the Lucas test)
     uint32_t *counts1;           // [grid1]
+    uint32_t *keep;              // phase 2: one word per candidate (its list of the
+                                 // candidates that pass base 325); the survivor regions
 };
 
 // Resolved launch parameters (the public isp_config after defaults).

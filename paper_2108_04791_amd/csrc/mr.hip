@@ -17,13 +17,17 @@
 // workgroup's own region with out = 1, and the workgroup then computes each
 // passer's Montgomery constants once for phase 2.
 //
-// Phase 2 (base-2 passers, almost all prime): the six remaining bases as
-// six independent tasks per candidate, laid out densely over the lanes
-// (task 6j + b is base b of candidate j); a lane whose base fails stores
-// out = 0, so the verdict is the AND of the six without any cross-lane
-// step (several lanes may store the same 0).  a^d uses a fixed window of W
-// bits with the lane's table of a^0..a^(2^W - 1) in LDS, so all lanes
-// multiply at the same steps; then up to s - 1 squarings look for -1.
+// Phase 2 (base-2 passers): in two rounds per workgroup over its slice of
+// the candidates.  Round 1 tests base 325, one candidate per lane, and
+// lists the passers; round 2 runs the five other bases of those as five
+// independent tasks per candidate, laid out densely over the lanes.  A
+// composite that passes base 2 (a strong pseudoprime, e.g. a Carmichael
+// number) almost always fails 325, so it costs one base instead of six.  A
+// lane whose base fails stores out = 0, so the verdict is the AND of the
+// bases without any cross-lane step (several lanes may store the same 0).
+// a^d uses a fixed window of W bits with the lane's table of
+// a^0..a^(2^W - 1) in LDS, so all lanes multiply at the same steps; then up
+// to s - 1 squarings look for -1.
 //
 // Work split without global atomics (a single hot device-scope atomic
 // sustains only about 1e8 operations per second on this part): each
@@ -576,41 +580,77 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase2_kernel(MrArgs a)
     uint64_t *tbl = dyn;
     uint32_t *pre = reinterpret_cast<uint32_t *>(dyn + (1u << W) * blockDim.x);
     __shared__ uint32_t wsum[MR_MAX_BLOCK / 64];
-    __shared__ unsigned long long next;
+    __shared__ uint32_t next, kept, next2;
     constexpr uint32_t BASES[6] = {325u, 9375u, 28178u, 450775u, 9780504u, 1795265022u};
     const int lane = threadIdx.x & 63;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint64_t total = call_total(a);
     const uint64_t chunk_1 = cand_chunk(total, a.grid1);
     lds_prefix(a.counts1, a.grid1, pre, wsum);
-    // one task per (candidate, base): 6 per candidate, dense over all lanes
-    const uint64_t tasks = 6ull * pre[a.grid1];
-    const uint64_t g = blockIdx.x;
-    const uint64_t s0 = tasks * g / gridDim.x;
-    const uint64_t s1 = tasks * (g + 1) / gridDim.x;
-    if (threadIdx.x == 0)
-        next = s0;
+    // the workgroup's slice of the candidates (dense over all base-2 regions)
+    const uint32_t ncand = pre[a.grid1];
+    const uint32_t g = blockIdx.x;
+    const uint32_t c0 = (uint32_t)((uint64_t)ncand * g / gridDim.x);
+    const uint32_t c1 = (uint32_t)((uint64_t)ncand * (g + 1) / gridDim.x);
+    // round 2's list: the slots of the slice's candidates that pass base
+    // 325, at keep[c0 ...] (the survivor regions are free by now)
+    uint32_t *keep = a.keep + c0;
+    if (threadIdx.x == 0) {
+        next = c0;
+        kept = 0;
+        next2 = 0;
+    }
     __syncthreads();
+    // round 1: base 325, one candidate per lane
     uint32_t k = 0;
     for (;;) {
-        // the wavefront takes the next 64 tasks of the workgroup's slice
-        unsigned long long t0 = 0;
+        uint32_t j0 = 0;
         if (lane == 0)
-            t0 = atomicAdd(&next, 64ull);
-        t0 = __shfl(t0, 0, 64);
-        if (t0 >= s1)
+            j0 = atomicAdd(&next, 64u);
+        j0 = __shfl(j0, 0, 64);
+        if (j0 >= c1)
             break;
-        // idle lanes at the end of the slice repeat task t0 (lane 0's), so
-        // the whole wavefront runs the test together; only real tasks store
-        const bool real = t0 + lane < s1;
-        const uint64_t t = real ? t0 + lane : t0;
-        const uint32_t j = (uint32_t)(t / 6);
-        const uint32_t b = (uint32_t)(t - 6ull * j);
+        // idle lanes at the end of the slice repeat candidate j0 (lane 0's),
+        // so the whole wavefront runs the test together; only real ones count
+        const bool real = j0 + lane < c1;
+        const uint32_t j = real ? j0 + lane : j0;
         k = find_region(pre, a.grid1, k, j);
-        const uint64_t slot = (uint64_t)k * chunk_1 + (j - pre[k]);
+        const uint32_t slot = (uint32_t)((uint64_t)k * chunk_1 + (j - pre[k]));
+        const Survivor sv = a.cand[slot];
+        const MontPrep pr = a.prep[slot];
+        const bool ok = sprp_one_base<W>(sv.n, pr, BASES[0], tbl);
+        if (!ok && real)
+            *sv.out = 0;  // composite; the base-2 round had written 1
+        const uint64_t m = __ballot(ok && real);
+        if (m != 0) {
+            uint32_t at = 0;
+            if (lane == 0)
+                at = atomicAdd(&kept, (uint32_t)__popcll(m));
+            at = __shfl(at, 0, 64);
+            if (ok && real)
+                keep[at + __popcll(m & lt)] = slot;
+        }
+    }
+    __syncthreads();  // the slice's list is complete (and visible to the workgroup)
+    // round 2: the five other bases of the kept candidates, five independent
+    // tasks each, dense over the lanes (task 5i + b: base b + 1 of kept i)
+    const uint32_t tasks = 5u * kept;
+    for (;;) {
+        uint32_t t0 = 0;
+        if (lane == 0)
+            t0 = atomicAdd(&next2, 64u);
+        t0 = __shfl(t0, 0, 64);
+        if (t0 >= tasks)
+            break;
+        const bool real = t0 + lane < tasks;
+        const uint32_t t = real ? t0 + lane : t0;
+        const uint32_t i = t / 5u;
+        const uint32_t b = t - 5u * i + 1u;
+        const uint32_t slot = keep[i];
         const Survivor sv = a.cand[slot];
         const MontPrep pr = a.prep[slot];
         if (!sprp_one_base<W>(sv.n, pr, BASES[b], tbl) && real)
-            *sv.out = 0;  // composite; the base-2 round had written 1
+            *sv.out = 0;
     }
 }
 
