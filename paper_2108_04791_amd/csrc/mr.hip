@@ -138,10 +138,11 @@ __device__ __forceinline__ bool sprp_base2_run(uint64_t n, const MontCtx &c, uin
     return pass;
 }
 
-__device__ __forceinline__ bool sprp_base2(uint64_t n)
+// c receives n's Montgomery context (kept for the passers' constants).
+__device__ __forceinline__ bool sprp_base2(uint64_t n, MontCtx &c)
 {
     const int L = 64 - __clzll(n);
-    const MontCtx c = make_ctx(n, L);
+    c = make_ctx(n, L);
     const uint64_t e = n - 1;
     const int s = __ffsll((long long)e) - 1;
     const int Lmax = wave_max(L), smax = wave_max(s);
@@ -225,6 +226,17 @@ __device__ __forceinline__ bool sprp_one_base(uint64_t n, const MontPrep &pr, ui
     if (Lmax == 63)
         return sprp_window<W, 1>(am, e >> s, s, c, tbl);
     return sprp_window<W, 2>(am, e >> s, s, c, tbl);
+}
+
+// R^2 mod n from n's n^-1 and R mod n (the other two constants).
+__device__ __forceinline__ uint64_t r2_of(uint64_t n, const MontPrep &p)
+{
+    MontCtx c;
+    c.n = n;
+    c.ninv = p.ninv;
+    c.one = p.one;
+    c.mone = n - p.one;
+    return r2_mod_n(c);
 }
 
 // The Montgomery constants of odd n >= 2^32.
@@ -463,6 +475,7 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
     }
     __syncthreads();
     Survivor *region = a.cand + (uint64_t)g * chunk_1;
+    MontPrep *prep = a.prep ? a.prep + (uint64_t)g * chunk_1 : nullptr;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     uint32_t k = 0;
     for (;;) {
@@ -485,7 +498,8 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
         // wavefront runs sprp_base2 together
         const uint64_t act = __ballot(i < s1);
         const uint64_t nv = __shfl(sv.n, __ffsll((long long)act) - 1, 64);
-        const bool pass = sprp_base2(i < s1 ? sv.n : nv) && i < s1;
+        MontCtx c;
+        const bool pass = sprp_base2(i < s1 ? sv.n : nv, c) && i < s1;
         const uint64_t m = __ballot(pass);
         if (m != 0) {
             uint32_t at = 0;
@@ -493,7 +507,13 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
                 at = atomicAdd(&fill, (uint32_t)__popcll(m));
             at = __shfl(at, 0, 64);
             if (pass) {
-                region[at + __popcll(m & lt)] = sv;
+                const uint32_t pos = at + __popcll(m & lt);
+                region[pos] = sv;
+                if (prep) {
+                    // n^-1 and R mod n now; R^2 mod n below, once sorted
+                    prep[pos].ninv = c.ninv;
+                    prep[pos].one = c.one;
+                }
                 *sv.out = 1;  // provisional: a failing later base clears it
             }
         }
@@ -502,8 +522,7 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
     // the Montgomery constants of this workgroup's passers, once each, for
     // all the later tasks of each (dense over the workgroup's threads)
     const uint32_t npass = fill;
-    if (a.prep) {
-        MontPrep *prep = a.prep + (uint64_t)g * chunk_1;
+    if (prep) {
         if (npass <= PASS_PER_THREAD * blockDim.x) {
             // counting sort by pass_key (block-uniform branch): the sorted
             // order as indices in LDS, then every thread reads its (at most
@@ -547,11 +566,14 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
                 perm[atomicAdd(&bins[pass_key(region[i].n)], 1u)] = (uint16_t)i;
             __syncthreads();
             Survivor mine[PASS_PER_THREAD];
+            MontPrep mp[PASS_PER_THREAD];
 #pragma unroll
             for (int k = 0; k < PASS_PER_THREAD; ++k) {
                 const uint32_t i = threadIdx.x + k * blockDim.x;
-                if (i < npass)
+                if (i < npass) {
                     mine[k] = region[perm[i]];
+                    mp[k] = prep[perm[i]];
+                }
             }
             __syncthreads();  // every entry is read before any is rewritten
 #pragma unroll
@@ -559,12 +581,13 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
                 const uint32_t i = threadIdx.x + k * blockDim.x;
                 if (i < npass) {
                     region[i] = mine[k];
-                    prep[i] = mont_prep(mine[k].n);
+                    mp[k].r2 = r2_of(mine[k].n, mp[k]);
+                    prep[i] = mp[k];
                 }
             }
         } else {
             for (uint32_t i = threadIdx.x; i < npass; i += blockDim.x)
-                prep[i] = mont_prep(region[i].n);
+                prep[i].r2 = r2_of(region[i].n, prep[i]);
         }
     }
     if (threadIdx.x == 0)
