@@ -546,22 +546,34 @@ def table_crossings() -> int:
     return int((((1 << 32) - 1 - p * p) // (2 * p) + 1).sum())
 
 
+WHEEL_TABLE_BYTES = 30678339 * 4  # 48 bits per 210 numbers below 2^32
+
+
 def bench_sieve(isp, reps: int = 5) -> dict:
-    """The table build: base primes + segment sieve kernels, HIP events."""
-    times = sorted(isp.table_rebuild_ms() for _ in range(reps))
-    ms = times[len(times) // 2]
+    """The table build: base primes + segment sieve kernels, then the wheel
+    table derived from the sieve table, each timed by HIP events."""
+    runs = [isp.table_rebuild_ms() for _ in range(reps)]
+    times = sorted(r[0] for r in runs)
+    wtimes = sorted(r[1] for r in runs)
+    ms, wms = times[len(times) // 2], wtimes[len(wtimes) // 2]
     table_bytes = 1 << 28
     cr = table_crossings()
     return {"kernel_ms": ms, "kernel_ms_all": times, "table_bytes": table_bytes,
             "write_GBps": table_bytes / (ms * 1e-3) / 1e9,
             "write_frac_of_hbm": table_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "crossings": cr, "crossings_per_s": cr / (ms * 1e-3)}
+            "crossings": cr, "crossings_per_s": cr / (ms * 1e-3),
+            "wheel_table_ms": wms, "wheel_table_bytes": WHEEL_TABLE_BYTES,
+            "wheel_table_GBps": (table_bytes + WHEEL_TABLE_BYTES) / (wms * 1e-3) / 1e9}
 
 
 def classify_bytes(a: np.ndarray) -> int:
     """Algorithmic HBM bytes of classify_kernel: 8 B read and 1 B written
-    per element, plus one 4-byte table word per odd element in [3, 2^32)."""
+    per element, plus one 4-byte table word per element that needs a table
+    read: odd, in [3, 2^32) and coprime to 3, 5 and 7 (the others are
+    decided by their residue mod 210)."""
     look = (a > np.uint64(2)) & (a < np.uint64(1 << 32)) & ((a & np.uint64(1)) == 1)
+    for p in (3, 5, 7):
+        look &= (a % np.uint64(p)) != 0
     return 9 * a.size + 4 * int(look.sum())
 
 
@@ -763,8 +775,8 @@ def main() -> int:
     gens = {"c3_mixed": W.c3_mixed, "c2_mr64": W.c2_mr64, "lookup32": W.lookup32}
     if args.workload:
         a = gens[args.workload]()
-        key = "c3_mixed" if args.workload == "lookup32" else args.workload
-        r = with_tuning(key, a.size, lambda: measure_plain(isp, torch, a, args.steps, args.warmup))
+        r = with_tuning(args.workload, a.size,
+                        lambda: measure_plain(isp, torch, a, args.steps, args.warmup))
         r.pop("got")
         print(json.dumps({"workload": args.workload, **r}))
         return 0
@@ -809,7 +821,7 @@ def main() -> int:
         r1.pop("got")
         forms["c1_uniform20"] = r1
         lk = W.lookup32()
-        rl = with_tuning("c3_mixed", lk.size, lambda: measure_plain(isp, torch, lk, args.steps, 2))
+        rl = with_tuning("lookup32", lk.size, lambda: measure_plain(isp, torch, lk, args.steps, 2))
         rl.pop("got")
         b = classify_bytes(lk)
         rl.update({"workload": "2^26 uint64 uniform in [0, 2^32) (every odd value a table lookup), "

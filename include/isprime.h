@@ -8,9 +8,12 @@
  *
  * How each element is decided (all exact integer arithmetic):
  *   n < 2, even n > 2      -> 0;  n == 2 -> 1
- *   odd n < 2^32           -> one bit of a device-resident odd-only sieve
- *                             table (sections 1 and 6.1.3: sieve once, then
- *                             test membership; here an O(1) bit lookup)
+ *   odd n < 2^32           -> one bit of a device-resident sieve table
+ *                             (sections 1 and 6.1.3: sieve once, then test
+ *                             membership; here an O(1) bit lookup; arrays
+ *                             above 65,536 elements read its copy on the
+ *                             2*3*5*7 wheel of section 3, where a multiple
+ *                             of 3, 5 or 7 needs no read)
  *   odd n >= 2^32          -> exact divisibility by small odd primes
  *                             (section 6.1.2: shrink the array first), then
  *                             the strong probable-prime test of section 2.1
@@ -58,7 +61,8 @@ enum {
 
 /* Build the odd-only sieve table for n < 2^32 on `device` (bit i of the
  * table is 1 iff 2i+1 is prime; 2^31 bits = 256 MiB in HBM), together with
- * the base primes.  Blocking; idempotent; thread-safe.
+ * the base primes and the wheel table derived from it (isp_wheel_table,
+ * 122.7 MB).  Blocking; idempotent; thread-safe.
  * Every other entry point calls it lazily for the current device.
  * Paper: section 1 (sieve of Eratosthenes), section 4 (odd numbers only). */
 int isp_init(int device);
@@ -188,6 +192,14 @@ int isp_montmul_u64(const uint64_t *a, const uint64_t *b, const uint64_t *n, uin
  * isp_shutdown. */
 int isp_table(int device, const uint32_t **table, size_t *words);
 
+/* The same for the wheel table the array path reads: the bits of the sieve
+ * table for the numbers below 2^32 coprime to 210, 48 per block of 210
+ * numbers (bit 48 q + k stands for 210 q + r_k, r_k the k-th residue
+ * coprime to 210 in increasing order: 1, 11, 13, ..., 209; 0 for numbers
+ * at or above 2^32); 30,678,339 words, 122.7 MB.  Paper: section 3 (the
+ * 2, 3, 5, 7 wheel, Eq. 5). */
+int isp_wheel_table(int device, const uint32_t **table, size_t *words);
+
 /* Counters of the last isprime_u64 / batched call on `stream`, read back
  * synchronously (the stream is synchronised): survivors of the trial filter
  * (both stages; with the wheel stage on, those it left to Miller-Rabin) and
@@ -214,12 +226,13 @@ enum {
 int isp_profile(int enable);
 int isp_profile_read(double *ms, uint64_t *calls);
 
-/* Rebuild the sieve table of `device` in place and time the build kernels
- * (base primes, then the segment sieve) with HIP events on a private
- * stream: *ms receives the elapsed milliseconds.  Synchronises the device
- * first; no call may be in flight on it (the table is rewritten with the
- * same bits).  For measurement only. */
-int isp_table_rebuild(int device, double *ms);
+/* Rebuild the tables of `device` in place and time the build kernels with
+ * HIP events on a private stream: *ms receives the milliseconds of the
+ * sieve (base primes, then the segment sieve), *wheel_ms those of the wheel
+ * table derived from it.  Synchronises the device first; no call may be in
+ * flight on it (the tables are rewritten with the same bits).  For
+ * measurement only. */
+int isp_table_rebuild(int device, double *ms, double *wheel_ms);
 
 /* ---------------------------------------------------------------- serving
  * A request loop with continuous batching.  Requests carry HOST buffers

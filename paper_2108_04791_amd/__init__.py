@@ -100,7 +100,8 @@ SIGNATURES = {
     "isp_last_counts": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "isp_profile": (_I, [_I]),
     "isp_profile_read": (_I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_U64)]),
-    "isp_table_rebuild": (_I, [_I, ctypes.POINTER(ctypes.c_double)]),
+    "isp_table_rebuild": (_I, [_I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "isp_wheel_table": (_I, [_I, ctypes.POINTER(_P), ctypes.POINTER(_SZ)]),
     "isp_server_create": (_I, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_P)]),
     "isp_submit": (_I, [_P, _P, _P, _SZ, ctypes.POINTER(_U64)]),
     "isp_poll": (_I, [_P, _U64]),
@@ -296,14 +297,29 @@ def table(device: int | None = None) -> torch.Tensor:
     return out
 
 
-def table_rebuild_ms(device: int | None = None) -> float:
-    """Rebuild the device's sieve table in place; the build kernels' time in
-    ms (HIP events).  Nothing may be in flight on the device."""
+def table_rebuild_ms(device: int | None = None):
+    """Rebuild the device's tables in place; (sieve ms, wheel table ms) of
+    the build kernels (HIP events).  Nothing may be in flight on the device."""
     if device is None:
         device = torch.cuda.current_device()
-    ms = ctypes.c_double()
-    _check(lib().isp_table_rebuild(device, ctypes.byref(ms)), "isp_table_rebuild")
-    return ms.value
+    ms, wms = ctypes.c_double(), ctypes.c_double()
+    _check(lib().isp_table_rebuild(device, ctypes.byref(ms), ctypes.byref(wms)),
+           "isp_table_rebuild")
+    return ms.value, wms.value
+
+
+def wheel_table(device: int | None = None) -> torch.Tensor:
+    """A copy of the device's wheel table (uint32 words, 48 bits per 210 numbers)."""
+    if device is None:
+        device = torch.cuda.current_device()
+    ptr, words = _P(), _SZ()
+    _check(lib().isp_wheel_table(device, ctypes.byref(ptr), ctypes.byref(words)), "isp_wheel_table")
+    out = torch.empty(words.value, dtype=torch.int32, device="cuda:%d" % device)
+    torch.cuda.synchronize(device)
+    err = _hip().hipMemcpy(out.data_ptr(), ptr.value, words.value * 4, 3)  # device to device
+    if err != 0:
+        raise RuntimeError("wheel table copy failed: hipError %d" % err)
+    return out
 
 
 def last_counts(stream=None):

@@ -278,9 +278,8 @@ void make_args(const DeviceState &ds, const Workspace &ws, const Tuning &t, size
         grid1 = (unsigned)std::min<size_t>(grid1, (len + SMALL_CALL_PER_BLOCK - 1) / SMALL_CALL_PER_BLOCK);
     }
     ca = ClassifyArgs();
-    ca.table = ds.table;
+    ca.wtable = ds.wtable;
     ca.nfilter = t.filter_primes;
-    ca.sorted = t.sort_survivors;
     ca.surv = ws.surv;
     ca.counts = ws.counts;
     ma = MrArgs();
@@ -345,7 +344,8 @@ int run_plain(const uint64_t *n, uint8_t *out, size_t len, const DeviceState &ds
             e = launch_classify(ca, grid_c, t.classify_block, t.classify_ept, s);
         mark(ISP_STAGE_FILTER2);
         if (e == hipSuccess)
-            e = launch_filter2(ws.surv, ws.counts, grid_c, len, nullptr, t.filter_primes, s);
+            e = launch_filter2(ws.surv, ws.counts, grid_c, len, nullptr, t.filter_primes,
+                               t.sort_survivors, s);
         if (e == hipSuccess && t.wheel_log2)
             e = launch_wheel(ws.surv, ws.counts, grid_c, len, nullptr, t.wheel_log2, s);
         mark(ISP_STAGE_MR_BASE2);
@@ -481,7 +481,7 @@ int build_graph_one(BatchCtx &c, const DeviceState &ds, const Tuning &t, int k)
         ee = launch_classify(ca, grid_c, t.classify_block, t.classify_ept, c.cap_stream);
     if (ee == hipSuccess)
         ee = launch_filter2(c.ws.surv, c.ws.counts, grid_c, 0, &d->total, t.filter_primes,
-                            c.cap_stream);
+                            t.sort_survivors, c.cap_stream);
     if (ee == hipSuccess && t.wheel_log2)
         ee = launch_wheel(c.ws.surv, c.ws.counts, grid_c, 0, &d->total, t.wheel_log2,
                           c.cap_stream);
@@ -557,6 +557,8 @@ int isp_init(int device)
     if (e == hipSuccess)
         e = hipMalloc(&st.table, TABLE_WORDS * sizeof(uint32_t));
     if (e == hipSuccess)
+        e = hipMalloc(&st.wtable, WHEEL_WORDS * sizeof(uint32_t));
+    if (e == hipSuccess)
         e = hipMalloc(&st.base_primes, MAX_BASE_PRIMES * sizeof(uint32_t));
     if (e == hipSuccess)
         e = hipMalloc(&st.base_count, sizeof(uint32_t));
@@ -566,6 +568,8 @@ int isp_init(int device)
         e = launch_base_primes(st, s);
     if (e == hipSuccess)
         e = launch_sieve(st, s);
+    if (e == hipSuccess)
+        e = launch_wheel_table(st, s);
     uint32_t count = 0;
     if (e == hipSuccess)
         e = hipMemcpyAsync(&count, st.base_count, sizeof(count), hipMemcpyDeviceToHost, s);
@@ -577,6 +581,7 @@ int isp_init(int device)
         e = hipErrorUnknown;  // the base-prime sieve must find all 6541 odd primes < 2^16
     if (e != hipSuccess) {
         (void)hipFree(st.table);
+        (void)hipFree(st.wtable);
         (void)hipFree(st.base_primes);
         (void)hipFree(st.base_count);
         (void)hipSetDevice(prev);
@@ -589,6 +594,7 @@ int isp_init(int device)
     e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
     if (e != hipSuccess || !sp) {
         (void)hipFree(st.table);
+        (void)hipFree(st.wtable);
         (void)hipFree(st.base_primes);
         (void)hipFree(st.base_count);
         (void)hipSetDevice(prev);
@@ -626,6 +632,7 @@ void isp_shutdown(void)
         if (!ds.table)
             continue;
         (void)hipFree(ds.table);
+        (void)hipFree(ds.wtable);
         (void)hipFree(ds.base_primes);
         (void)hipFree(ds.base_count);
         if (ds.range_primes)
@@ -1110,9 +1117,9 @@ int isp_profile_read(double *ms, uint64_t *calls)
     return ISP_OK;
 }
 
-int isp_table_rebuild(int device, double *ms)
+int isp_table_rebuild(int device, double *ms, double *wheel_ms)
 {
-    if (!ms)
+    if (!ms || !wheel_ms)
         return ISP_EINVAL;
     int st = isp_init(device);
     if (st != ISP_OK)
@@ -1127,11 +1134,11 @@ int isp_table_rebuild(int device, double *ms)
     if (e != hipSuccess)
         return fail(e);
     hipStream_t s = nullptr;
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     e = hipDeviceSynchronize();
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+    for (int k = 0; k < 3 && e == hipSuccess; ++k)
         e = hipEventCreate(&ev[k]);
     if (e == hipSuccess)
         e = hipEventRecord(ev[0], s);
@@ -1141,14 +1148,20 @@ int isp_table_rebuild(int device, double *ms)
         e = launch_sieve(ds, s);
     if (e == hipSuccess)
         e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess)
+        e = launch_wheel_table(ds, s);
+    if (e == hipSuccess)
+        e = hipEventRecord(ev[2], s);
     uint32_t count = 0;
     if (e == hipSuccess)
         e = hipMemcpyAsync(&count, ds.base_count, sizeof(count), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
-    float elapsed = 0;
+    float elapsed = 0, welapsed = 0;
     if (e == hipSuccess)
         e = hipEventElapsedTime(&elapsed, ev[0], ev[1]);
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&welapsed, ev[1], ev[2]);
     if (e == hipSuccess && count != 6541)
         e = hipErrorUnknown;
     for (auto &x : ev)
@@ -1160,6 +1173,19 @@ int isp_table_rebuild(int device, double *ms)
     if (e != hipSuccess)
         return fail(e);
     *ms = elapsed;
+    *wheel_ms = welapsed;
+    return ISP_OK;
+}
+
+int isp_wheel_table(int device, const uint32_t **table, size_t *words)
+{
+    if (!table || !words)
+        return ISP_EINVAL;
+    int st = isp_init(device);
+    if (st != ISP_OK)
+        return st;
+    *table = g_dev[device].wtable;
+    *words = WHEEL_WORDS;
     return ISP_OK;
 }
 

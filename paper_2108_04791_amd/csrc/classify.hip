@@ -4,7 +4,9 @@
 // Per element (paper: the input classes of section 1, the membership test of
 // section 6.1.3, the array shrinking of section 6.1.2):
 //   n < 2 -> 0, n == 2 -> 1, even -> 0
-//   odd n < 2^32 -> bit (n >> 1) of the sieve table
+//   odd n < 2^32 -> its bit in the sieve table: for these arrays the copy
+//                   on the 2*3*5*7 wheel (48 bits per 210 numbers), where a
+//                   multiple of 3, 5 or 7 needs no read at all
 //   odd n >= 2^32 -> 0 if a small odd prime divides it, else a survivor
 // Every output byte is written here with coalesced stores (survivors get 0);
 // the Miller-Rabin kernels later store a 1 for each prime survivor.
@@ -21,14 +23,11 @@
 // atomic sustains only about 1e8 operations per second on this part, far
 // too few to append survivors one workgroup at a time.)
 //
-// Within each pass of blockDim * EPT elements the survivors are ordered by
-// decreasing bit length with an LDS counting sort (32 keys, bit lengths 64
-// down to 33), so a wavefront of the Miller-Rabin kernels sees values of
-// (nearly) one bit length and its lanes run the same number of squarings.
-//
 // Also here: filter2_kernel, the second filter stage over each region's
-// survivors (the rest of the first 64 odd primes), and small_kernel, which
-// decides a call of at most SMALL_MAX elements in one launch.
+// survivors (the rest of the first 64 odd primes), which also does the
+// magnitude binning (survivors ordered by bit length in windows of 2048),
+// and small_kernel, which decides a call of at most SMALL_MAX elements in
+// one launch.
 #include "compact.h"
 #include "internal.h"
 #include "mr_lane.h"
@@ -97,145 +96,164 @@ __device__ __forceinline__ int classify_one(uint64_t v, const uint32_t *__restri
     return divisible ? 0 : 2;
 }
 
-// Sort key: 0 for bit length 64 ... 31 for bit length 33 (v >= 2^32).
-__device__ __forceinline__ int sort_key(uint64_t v) { return __clzll(v); }
+// The same decision split in two, so that a thread issues the table reads
+// of all its elements before it waits for any.  The read: for odd
+// 3 <= v < 2^32 coprime to 210, the wheel-table word holding bit
+// 48 floor(v / 210) + pos[v mod 210] (pos: the residue's index, in LDS);
+// returns that bit's place in the word (widx: the word's index), or -1 when
+// v needs no read.  An odd v < 2^32 sharing a factor with 210 is then prime
+// only as 3, 5 or 7.  Branch-free, so that the caller can issue every
+// element's LDS and table reads back to back: for a v that needs no read it
+// computes a valid LDS index and returns widx = 0.
+__device__ __forceinline__ int wheel_slot(uint64_t v, const uint8_t *wpos, uint32_t &widx)
+{
+    const bool in = (v & 1) != 0 && v >= 3 && v < TABLE_BOUND;
+    const uint32_t n = (uint32_t)v | 1u;  // odd, so its residue indexes pos
+    const uint32_t q = div210_odd(n);
+    const uint32_t p = wpos[n - q * WHEEL_MOD];
+    const bool read = in && p != 0xffu;
+    const uint32_t b = q * WHEEL_RES + p;  // below 48 * 20452226 < 2^30 when read
+    widx = read ? b >> 5 : 0u;
+    return read ? (int)(b & 31u) : -1;
+}
+
+template <int NF>
+__device__ __forceinline__ int classify_with(uint64_t v, uint32_t word, int bit)
+{
+    if (v < 3)
+        return v == 2 ? 1 : 0;
+    if ((v & 1) == 0)
+        return 0;
+    if (v < TABLE_BOUND)
+        return bit >= 0 ? (int)((word >> bit) & 1u) : (v <= 7 ? 1 : 0);
+    bool divisible = false;
+#pragma unroll
+    for (int k = 0; k < NF; ++k)
+        divisible |= v * FILTER.inv[k] <= FILTER.lim[k];
+    return divisible ? 0 : 2;
+}
 
 struct ClassifyShared {
-    uint32_t hist[NUM_BINS];
-    uint32_t off[NUM_BINS];
+    uint8_t wpos[WHEEL_MOD + 2];  // residue mod 210 -> its index among the 48 (0xff: none)
     uint32_t wave_cnt[16];
     uint32_t pass_total;
 };
 
-// One pass: elements [base, base + EPT) of one array, those below `end`.
-// Writes the output bytes and appends the pass's survivors at
-// region[filled ...].  Called by every thread of the block.
+// One pass over the blockDim * EPT elements from p0 of one array, those
+// below `end`.  Thread t takes the element pairs p0 + k * 2 * blockDim + 2t
+// (k < EPT / 2; one element p0 + t when EPT is 1), so each load and store
+// instruction of a wavefront covers one contiguous stretch.  Writes the
+// output bytes and appends the pass's survivors at region[filled ...].
+// Called by every thread of the block.
 template <int EPT, int NF>
 __device__ __forceinline__ void classify_pass(const uint64_t *__restrict__ n,
-                                              uint8_t *__restrict__ out, uint64_t base,
-                                              uint64_t end, const uint32_t *__restrict__ table,
+                                              uint8_t *__restrict__ out, uint64_t p0,
+                                              uint64_t end, const uint32_t *__restrict__ wtable,
                                               Survivor *__restrict__ region, uint32_t &filled,
-                                              int sorted, ClassifyShared &sh)
+                                              ClassifyShared &sh)
 {
+    constexpr int PAIRS = EPT >= 2 ? EPT / 2 : 1;
+    constexpr int PER = EPT >= 2 ? 2 : 1;  // consecutive elements per thread and step
+    const uint64_t step = (uint64_t)blockDim.x * PER;
+    const uint64_t mine = p0 + (uint64_t)threadIdx.x * PER;
+    const bool full = p0 + step * PAIRS <= end;
     uint64_t v[EPT];
-    const bool full = base + EPT <= end;
     if (full) {
-        if constexpr (EPT >= 2) {
 #pragma unroll
-            for (int j = 0; j < EPT; j += 2) {
-                const u64x2 t = *reinterpret_cast<const u64x2 *>(n + base + j);
-                v[j] = t.x;
-                v[j + 1] = t.y;
+        for (int k = 0; k < PAIRS; ++k) {
+            if constexpr (PER == 2) {
+                const u64x2 t = *reinterpret_cast<const u64x2 *>(n + mine + k * step);
+                v[2 * k] = t.x;
+                v[2 * k + 1] = t.y;
+            } else {
+                v[k] = n[mine + k * step];
             }
-        } else {
-            v[0] = n[base];
         }
     } else {
 #pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const uint64_t i = mine + (j / PER) * step + (j % PER);
+            v[j] = i < end ? n[i] : 0;
+        }
+    }
+    // every table read first (a wavefront with no odd value below 2^32 in
+    // the pass skips them), then the verdicts
+    uint32_t word[EPT];
+    int bit[EPT];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        word[j] = 0;
+        bit[j] = -1;
+        any |= (v[j] & 1) != 0 && v[j] < TABLE_BOUND;
+    }
+    if (__ballot(any) != 0) {
+        uint32_t wi[EPT];
+#pragma unroll
         for (int j = 0; j < EPT; ++j)
-            v[j] = base + j < end ? n[base + j] : 0;
+            bit[j] = wheel_slot(v[j], sh.wpos, wi[j]);
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+            word[j] = wtable[wi[j]];
     }
     bool sv[EPT];
     uint8_t r[EPT];
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-        const int c = classify_one<NF>(v[j], table);
-        sv[j] = c == 2 && base + j < end;
+        const uint64_t i = mine + (j / PER) * step + (j % PER);
+        const int c = classify_with<NF>(v[j], word[j], bit[j]);
+        sv[j] = c == 2 && i < end;
         r[j] = (uint8_t)(c == 1);
     }
-    if (full) {
-        if constexpr (EPT == 4) {
-            typedef uint32_t u32u __attribute__((aligned(1)));
-            *reinterpret_cast<u32u *>(out + base) = (uint32_t)r[0] | ((uint32_t)r[1] << 8) |
-                                                    ((uint32_t)r[2] << 16) | ((uint32_t)r[3] << 24);
-        } else if constexpr (EPT == 8) {
-            typedef uint64_t u64u __attribute__((aligned(1)));
-            uint64_t p = 0;
+    if (full && PER == 2) {
+        typedef uint16_t u16u __attribute__((aligned(1)));
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                p |= (uint64_t)r[j] << (8 * j);
-            *reinterpret_cast<u64u *>(out + base) = p;
-        } else {
-#pragma unroll
-            for (int j = 0; j < EPT; ++j)
-                out[base + j] = r[j];
-        }
+        for (int k = 0; k < PAIRS; ++k)
+            *reinterpret_cast<u16u *>(out + mine + k * step) =
+                (uint16_t)(r[2 * k] | ((uint16_t)r[2 * k + 1] << 8));
     } else {
 #pragma unroll
-        for (int j = 0; j < EPT; ++j)
-            if (base + j < end)
-                out[base + j] = r[j];
+        for (int j = 0; j < EPT; ++j) {
+            const uint64_t i = mine + (j / PER) * step + (j % PER);
+            if (i < end)
+                out[i] = r[j];
+        }
     }
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    if (sorted) {
-        // counting sort by bit length: rank within its key from an LDS atomic
-        uint32_t rank[EPT];
+    // compaction in the pass's element order (per slot): ballot per
+    // slot, LDS scan over waves
+    uint64_t masks[EPT];
+    uint32_t wave_total = 0;
 #pragma unroll
-        for (int j = 0; j < EPT; ++j)
-            rank[j] = sv[j] ? atomicAdd(&sh.hist[sort_key(v[j])], 1u) : 0u;
-        __syncthreads();
-        if (threadIdx.x < 64) {
-            // exclusive scan of the 32 key counts by the first wavefront
-            const uint32_t h = lane < NUM_BINS ? sh.hist[lane] : 0u;
-            uint32_t incl = h;
+    for (int j = 0; j < EPT; ++j) {
+        masks[j] = __ballot(sv[j]);
+        wave_total += __popcll(masks[j]);
+    }
+    if (lane == 0)
+        sh.wave_cnt[wave] = wave_total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < nwaves; ++w) {
+            const uint32_t t = sh.wave_cnt[w];
+            sh.wave_cnt[w] = run;
+            run += t;
+        }
+        sh.pass_total = run;
+    }
+    __syncthreads();
+    uint32_t pos = filled + sh.wave_cnt[wave];
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-            for (int o = 1; o < NUM_BINS; o <<= 1) {
-                const uint32_t y = __shfl_up(incl, o, 64);
-                if (lane >= o)
-                    incl += y;
-            }
-            if (lane < NUM_BINS) {
-                sh.off[lane] = incl - h;
-                sh.hist[lane] = 0;  // ready for the next pass
-            }
-            if (lane == NUM_BINS - 1)
-                sh.pass_total = incl;
+    for (int j = 0; j < EPT; ++j) {
+        if (sv[j]) {
+            Survivor s;
+            s.n = v[j];
+            s.out = out + mine + (j / PER) * step + (j % PER);
+            region[pos + __popcll(masks[j] & lt)] = s;
         }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            if (sv[j]) {
-                Survivor s;
-                s.n = v[j];
-                s.out = out + base + j;
-                region[filled + sh.off[sort_key(v[j])] + rank[j]] = s;
-            }
-        }
-    } else {
-        // order-preserving compaction: ballot per slot, LDS scan over waves
-        uint64_t masks[EPT];
-        uint32_t wave_total = 0;
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            masks[j] = __ballot(sv[j]);
-            wave_total += __popcll(masks[j]);
-        }
-        if (lane == 0)
-            sh.wave_cnt[wave] = wave_total;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t run = 0;
-            for (int w = 0; w < nwaves; ++w) {
-                const uint32_t t = sh.wave_cnt[w];
-                sh.wave_cnt[w] = run;
-                run += t;
-            }
-            sh.pass_total = run;
-        }
-        __syncthreads();
-        uint32_t pos = filled + sh.wave_cnt[wave];
-        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            if (sv[j]) {
-                Survivor s;
-                s.n = v[j];
-                s.out = out + base + j;
-                region[pos + __popcll(masks[j] & lt)] = s;
-            }
-            pos += __popcll(masks[j]);
-        }
+        pos += __popcll(masks[j]);
     }
     filled += sh.pass_total;
     __syncthreads();  // sh is reused by the next pass
@@ -247,8 +265,8 @@ template <int EPT, bool BATCHED, int NF>
 __global__ void __launch_bounds__(1024) classify_kernel(ClassifyArgs a)
 {
     __shared__ ClassifyShared sh;
-    if (threadIdx.x < NUM_BINS)
-        sh.hist[threadIdx.x] = 0;
+    for (uint32_t r = threadIdx.x; r < WHEEL_MOD; r += blockDim.x)
+        sh.wpos[r] = WHEEL.pos[r];
     __syncthreads();
     const uint64_t g = blockIdx.x;
     const uint64_t total = BATCHED ? a.desc->total : a.total;
@@ -261,8 +279,7 @@ __global__ void __launch_bounds__(1024) classify_kernel(ClassifyArgs a)
     if (r0 < r1) {
         if constexpr (!BATCHED) {
             for (uint64_t p0 = r0; p0 < r1; p0 += per_pass)
-                classify_pass<EPT, NF>(a.n, a.out, p0 + (uint64_t)threadIdx.x * EPT, r1, a.table,
-                                       region, filled, a.sorted, sh);
+                classify_pass<EPT, NF>(a.n, a.out, p0, r1, a.wtable, region, filled, sh);
         } else {
             const BatchDesc *d = a.desc;
             // first array overlapping r0: prefix[lo] <= r0 < prefix[hi]
@@ -283,8 +300,7 @@ __global__ void __launch_bounds__(1024) classify_kernel(ClassifyArgs a)
                 const uint64_t *nv = d->n_ptrs[k];
                 uint8_t *ov = d->out_ptrs[k];
                 for (uint64_t p0 = b0; p0 < b1; p0 += per_pass)
-                    classify_pass<EPT, NF>(nv, ov, p0 + (uint64_t)threadIdx.x * EPT, b1, a.table,
-                                           region, filled, a.sorted, sh);
+                    classify_pass<EPT, NF>(nv, ov, p0, b1, a.wtable, region, filled, sh);
             }
         }
     }
@@ -374,41 +390,110 @@ __global__ void __launch_bounds__(SMALL_BLOCK) small_kernel(const uint64_t *__re
 }
 
 // Second trial-filter stage, between classify and the base-2 round: one
-// workgroup per classify region compacts the region's survivors in place
-// (order kept, so the bit-length order survives) to those with no factor
-// among the odd primes nf .. DENSE_TO - 1, and rewrites its count.  Only the
-// survivors of the first stage (about a fifth of the elements) pay for these
-// primes, one thread per survivor, and a prime p removes 1/p of them, each of
-// which would otherwise cost a base-2 exponentiation of ~1,700
-// instructions: worth it up to p ~ 300.
+// workgroup per classify region compacts the region's survivors in place to
+// those with no factor among the odd primes nf .. DENSE_TO - 1, and
+// rewrites its count.  Only the survivors of the first stage (about a fifth
+// of the elements) pay for these primes, one thread per survivor, and a
+// prime p removes 1/p of them, each of which would otherwise cost a base-2
+// exponentiation of ~1,700 instructions: worth it up to p ~ 300.
+//
+// With SORT (magnitude binning), the kept survivors of each window of
+// F2_WINDOW entries are also ordered by decreasing bit length (a counting
+// sort over the 32 lengths 64 .. 33, ranks from LDS atomics), so that a
+// wavefront of the base-2 round gets values of (nearly) one bit length and
+// its lanes run the same number of squarings.  A window is a few thousand
+// survivors, i.e. tens of thousands of input elements.  Every entry of a
+// window is read into registers before the first barrier, and it is written
+// back at most at its own position, so the sort is in place.  Without SORT
+// the survivors keep their order.
+constexpr int F2_PER_THREAD = 8;
+constexpr uint32_t F2_WINDOW = FILTER2_BLOCK * F2_PER_THREAD;
+
 template <int NF>
+__device__ __forceinline__ bool filter2_keep(uint64_t n)
+{
+    bool divisible = false;
+#pragma unroll
+    for (int k = NF; k < DENSE_TO; ++k)
+        divisible |= n * FILTER.inv[k] <= FILTER.lim[k];
+    return !divisible;
+}
+
+template <int NF, bool SORT>
 __global__ void __launch_bounds__(FILTER2_BLOCK) filter2_kernel(Survivor *__restrict__ surv,
                                                                uint32_t *__restrict__ counts,
                                                                uint64_t total,
                                                                const uint64_t *total_dev)
 {
     __shared__ uint32_t wave_cnt[FILTER2_BLOCK / 64];
+    __shared__ uint32_t hist[NUM_BINS], off[NUM_BINS + 1];
     const uint32_t g = blockIdx.x;
     // the regions of the classify grid (of the same size as this grid)
     const uint64_t chunk = classify_chunk(total_dev ? *total_dev : total, gridDim.x);
     Survivor *region = surv + (uint64_t)g * chunk;
     const uint32_t count = counts[g];
     uint32_t kept = 0;  // entries kept so far (block-uniform)
-    for (uint32_t r0 = 0; r0 < count; r0 += FILTER2_BLOCK) {
-        const uint32_t i = r0 + threadIdx.x;
-        Survivor e;
-        e.n = 0;
-        e.out = nullptr;
-        bool keep = false;
-        if (i < count) {
-            e = region[i];
-            bool divisible = false;
-#pragma unroll
-            for (int k = NF; k < DENSE_TO; ++k)
-                divisible |= e.n * FILTER.inv[k] <= FILTER.lim[k];
-            keep = !divisible;
+    if constexpr (!SORT) {
+        for (uint32_t r0 = 0; r0 < count; r0 += FILTER2_BLOCK) {
+            const uint32_t i = r0 + threadIdx.x;
+            Survivor e;
+            e.n = 0;
+            e.out = nullptr;
+            bool keep = false;
+            if (i < count) {
+                e = region[i];
+                keep = filter2_keep<NF>(e.n);
+            }
+            compact_round<FILTER2_BLOCK>(region, e, keep, kept, wave_cnt);
         }
-        compact_round<FILTER2_BLOCK>(region, e, keep, kept, wave_cnt);
+    } else {
+        const int lane = threadIdx.x & 63;
+        if (threadIdx.x < NUM_BINS)
+            hist[threadIdx.x] = 0;
+        __syncthreads();
+        for (uint32_t w0 = 0; w0 < count; w0 += F2_WINDOW) {
+            Survivor e[F2_PER_THREAD];
+            uint32_t rank[F2_PER_THREAD];
+            int key[F2_PER_THREAD];
+            bool keep[F2_PER_THREAD];
+#pragma unroll
+            for (int k = 0; k < F2_PER_THREAD; ++k) {
+                const uint32_t i = w0 + k * FILTER2_BLOCK + threadIdx.x;
+                keep[k] = false;
+                if (i < count) {
+                    e[k] = region[i];
+                    keep[k] = filter2_keep<NF>(e[k].n);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < F2_PER_THREAD; ++k) {
+                key[k] = keep[k] ? __clzll(e[k].n) : 0;  // 0 (64 bits) .. 31 (33 bits)
+                rank[k] = keep[k] ? atomicAdd(&hist[key[k]], 1u) : 0u;
+            }
+            __syncthreads();  // every entry of the window is read and counted
+            if (threadIdx.x < 64) {
+                const uint32_t h = lane < NUM_BINS ? hist[lane] : 0u;
+                uint32_t incl = h;
+#pragma unroll
+                for (int o = 1; o < NUM_BINS; o <<= 1) {
+                    const uint32_t y = __shfl_up(incl, o, 64);
+                    if (lane >= o)
+                        incl += y;
+                }
+                if (lane < NUM_BINS) {
+                    off[lane] = incl - h;
+                    hist[lane] = 0;  // ready for the next window
+                }
+                if (lane == NUM_BINS - 1)
+                    off[NUM_BINS] = incl;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < F2_PER_THREAD; ++k)
+                if (keep[k])
+                    region[kept + off[key[k]] + rank[k]] = e[k];
+            kept += off[NUM_BINS];
+        }
     }
     if (threadIdx.x == 0)
         counts[g] = kept;
@@ -417,27 +502,33 @@ __global__ void __launch_bounds__(FILTER2_BLOCK) filter2_kernel(Survivor *__rest
 }  // namespace
 
 hipError_t launch_filter2(Survivor *surv, uint32_t *counts, unsigned grid, uint64_t total,
-                          const uint64_t *total_dev, int nf, hipStream_t s)
+                          const uint64_t *total_dev, int nf, int sorted, hipStream_t s)
 {
+#define F2(N, S) filter2_kernel<N, S><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, total, total_dev)
     switch (nf) {
     case 8:
-        filter2_kernel<8><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, total, total_dev);
+        sorted ? F2(8, true) : F2(8, false);
         break;
     case 16:
-        filter2_kernel<16><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, total, total_dev);
+        sorted ? F2(16, true) : F2(16, false);
         break;
     case 24:
-        filter2_kernel<24><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, total, total_dev);
+        sorted ? F2(24, true) : F2(24, false);
         break;
     case 32:
-        filter2_kernel<32><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, total, total_dev);
+        sorted ? F2(32, true) : F2(32, false);
         break;
     case 48:
-        filter2_kernel<48><<<grid, FILTER2_BLOCK, 0, s>>>(surv, counts, total, total_dev);
+        sorted ? F2(48, true) : F2(48, false);
         break;
     default:
-        return hipSuccess;  // no first stage (0) or nothing left to test (64)
+        // no first stage (0) or nothing left to test (64): only the sort
+        if (!sorted)
+            return hipSuccess;
+        F2(DENSE_TO, true);
+        break;
     }
+#undef F2
     return hipGetLastError();
 }
 

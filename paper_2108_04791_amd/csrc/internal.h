@@ -13,6 +13,44 @@ namespace isp {
 constexpr uint64_t TABLE_BOUND = (uint64_t)1 << 32;
 constexpr uint64_t TABLE_WORDS = (uint64_t)1 << 26;  // 2^31 odd numbers / 32
 constexpr int MAX_BASE_PRIMES = 6542;                // odd primes below 2^16: 6541
+// The lookup table for n < 2^32 on the 2*3*5*7 wheel: block q of 48 bits
+// for the numbers 210 q + r with r coprime to 210 (48 residues in [1, 209]),
+// bit 48 q + (index of r); the multiples of 3, 5 and 7 need no bit.
+constexpr uint32_t WHEEL_MOD = 210;
+constexpr uint32_t WHEEL_RES = 48;
+constexpr uint64_t WHEEL_BLOCKS = (TABLE_BOUND + WHEEL_MOD - 1) / WHEEL_MOD;  // 20452226
+constexpr uint64_t WHEEL_WORDS = (WHEEL_BLOCKS * WHEEL_RES + 31) / 32;          // 30678339
+static_assert(WHEEL_WORDS == 30678339, "122.7 MB wheel table");
+
+// The residues of the wheel: res[k], the k-th residue coprime to 210 in
+// increasing order, and pos[r], the k with res[k] = r (0xff when r shares a
+// factor with 210).
+struct WheelResidues {
+    uint8_t res[WHEEL_RES];
+    uint8_t pos[WHEEL_MOD];
+    constexpr WheelResidues() : res(), pos()
+    {
+        int k = 0;
+        for (uint32_t r = 0; r < WHEEL_MOD; ++r) {
+            const bool coprime = r % 2 != 0 && r % 3 != 0 && r % 5 != 0 && r % 7 != 0;
+            pos[r] = coprime ? (uint8_t)k : (uint8_t)0xff;
+            if (coprime)
+                res[k++] = (uint8_t)r;
+        }
+    }
+};
+constexpr WheelResidues WHEEL{};
+static_assert(WHEEL.res[0] == 1 && WHEEL.res[1] == 11 && WHEEL.res[WHEEL_RES - 1] == 209 &&
+                  WHEEL.pos[209] == WHEEL_RES - 1 && WHEEL.pos[3] == 0xff,
+              "48 residues coprime to 210");
+
+// floor(n / 210) for odd n < 2^32: floor((n >> 1) / 105), by the
+// multiplier ceil(2^38 / 105) = 2617884829, exact for every value below
+// 2^31 (its excess 2617884829 * 105 - 2^38 = 101 is below 2^7).
+__host__ __device__ inline uint32_t div210_odd(uint32_t n)
+{
+    return (uint32_t)(((uint64_t)(n >> 1) * 2617884829u) >> 38);
+}
 constexpr int MAX_FILTER_PRIMES = 128;
 constexpr int NUM_BINS = 32;                         // bit lengths 33..64
 constexpr int MR_MAX_BLOCK = 1024;                   // launch bound of the Miller-Rabin kernels
@@ -79,9 +117,8 @@ struct ClassifyArgs {
     uint8_t *out;           // ... and its output
     const BatchDesc *desc;  // batched call (n, out unused); nullptr for plain
     uint64_t total;         // plain call: elements (batched: desc->total)
-    const uint32_t *table;
+    const uint32_t *wtable; // the sieve table's bits on the 210-wheel
     int nfilter;            // odd primes in the trial filter: 0, 8, 16, 24, 32, 48 or 64
-    int sorted;             // order survivors by bit length within a pass
     Survivor *surv;         // grid regions of classify_chunk() entries
     uint32_t *counts;       // [grid] survivors per region
 };
@@ -132,6 +169,7 @@ struct DeviceState {
     int device = -1;
     int cus = 0;
     uint32_t *table = nullptr;       // TABLE_WORDS words
+    uint32_t *wtable = nullptr;      // WHEEL_WORDS words, derived from table
     uint32_t *base_primes = nullptr; // odd primes < 2^16
     uint32_t *base_count = nullptr;  // device word: how many
     int num_base_primes = 0;
@@ -165,14 +203,16 @@ struct Workspace {
 // ---- launchers (each enqueues on `stream` and returns hipError_t) ----
 hipError_t launch_base_primes(DeviceState &ds, hipStream_t s);
 hipError_t launch_sieve(DeviceState &ds, hipStream_t s);
+hipError_t launch_wheel_table(DeviceState &ds, hipStream_t s);
 
 hipError_t launch_classify(const ClassifyArgs &a, unsigned grid, int block, int ept,
                            hipStream_t s);
 hipError_t launch_small(const uint64_t *n, uint8_t *out, size_t len, const uint32_t *table,
                         int nfilter, hipStream_t s);
 // total_dev: where to read the element count (batched calls), else total.
+// sorted: also order each window of the kept survivors by bit length.
 hipError_t launch_filter2(Survivor *surv, uint32_t *counts, unsigned grid, uint64_t total,
-                          const uint64_t *total_dev, int nf, hipStream_t s);
+                          const uint64_t *total_dev, int nf, int sorted, hipStream_t s);
 // Decides the survivors below 2^log2_bound by wheel trial division and
 // compacts the others in place (grid: the classify grid).
 hipError_t launch_wheel(Survivor *surv, uint32_t *counts, unsigned grid, uint64_t total,

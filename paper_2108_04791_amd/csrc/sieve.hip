@@ -13,6 +13,11 @@
 // Kernels:
 //   base_primes_kernel  one workgroup sieves the 32768 odd numbers below 2^16
 //                       in LDS and writes the 6541 odd primes in order.
+//   wheel_table_kernel  the same bits again on the 2*3*5*7 wheel (48 bits per
+//                       210 numbers, 122.7 MB): the copy the array path reads,
+//                       half the size of the odd-only table, which on a
+//                       random lookup also leaves out the multiples of 3, 5
+//                       and 7 (54% of the odd numbers).
 //   sieve_kernel        one workgroup per 32 KiB segment (2^18 odd numbers).
 //                       Multiples of 3..31 come from a periodic word mask
 //                       (pre-sieve); each base prime p below 8192 is crossed
@@ -155,7 +160,37 @@ __global__ void __launch_bounds__(SIEVE_THREADS) sieve_kernel(uint32_t *__restri
         table[w0 + k] = seg[k];
 }
 
+// The wheel table, one thread per 32-bit word: bit b stands for the number
+// 210 floor(b / 48) + res[b mod 48], whose bit is read from the odd-only
+// table (0 for the numbers of the last block at or above 2^32).
+__global__ void __launch_bounds__(256) wheel_table_kernel(uint32_t *__restrict__ wtable,
+                                                          const uint32_t *__restrict__ table)
+{
+    __shared__ uint8_t res[WHEEL_RES];
+    if (threadIdx.x < WHEEL_RES)
+        res[threadIdx.x] = WHEEL.res[threadIdx.x];
+    __syncthreads();
+    const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= WHEEL_WORDS)
+        return;
+    uint32_t word = 0;
+    for (uint32_t j = 0; j < 32; ++j) {
+        const uint64_t b = w * 32 + j;
+        const uint64_t q = b / WHEEL_RES;
+        const uint64_t v = q * WHEEL_MOD + res[b - q * WHEEL_RES];
+        if (v < TABLE_BOUND)
+            word |= ((table[v >> 6] >> ((v >> 1) & 31)) & 1u) << j;
+    }
+    wtable[w] = word;
+}
+
 }  // namespace
+
+hipError_t launch_wheel_table(DeviceState &ds, hipStream_t s)
+{
+    wheel_table_kernel<<<(unsigned)((WHEEL_WORDS + 255) / 256), 256, 0, s>>>(ds.wtable, ds.table);
+    return hipGetLastError();
+}
 
 hipError_t launch_base_primes(DeviceState &ds, hipStream_t s)
 {

@@ -2,7 +2,8 @@
 
 The parameters (isp_config) never change an output bit, only speed: the
 classify block size, elements per thread and grid; the trial-filter size;
-the Miller-Rabin block size, grid and window width.  The tuner times
+the magnitude binning (survivors ordered by bit length, or not); the
+Miller-Rabin block size, grid and window width.  The tuner times
 configurations on a sample of a workload class by coordinate descent (one
 parameter at a time, two sweeps), rejects any configuration whose output
 bytes differ from the default configuration's, and records the fastest in a
@@ -27,8 +28,9 @@ from . import Batch, get_config, isprime_into, set_config
 SPACE = {
     "classify_ept": [2, 4, 8],
     "classify_block": [256, 512, 1024],
-    "classify_blocks_per_cu": [1, 2, 4, 8],
-    "filter_primes": [16, 24, 32, 48],
+    "classify_blocks_per_cu": [1, 2, 4, 8, 16],
+    "filter_primes": [8, 16, 24, 32, 48],
+    "sort_survivors": [1, -1],
     "mr_block": [256, 512, 1024],
     "mr_blocks_per_cu": [1, 2, 4, 8],
     "mr_window": [2, 3, 4],
@@ -149,14 +151,15 @@ def _workload(name: str):
     import workloads as W
     if name == "c4_batched":
         return [torch.from_numpy(a.view(np.int64)).cuda() for a, _ in W.c4_batched()]
-    gen = {"c1_uniform20": W.c1_uniform20, "c2_mr64": W.c2_mr64, "c3_mixed": W.c3_mixed}[name]
+    gen = {"c1_uniform20": W.c1_uniform20, "c2_mr64": W.c2_mr64, "c3_mixed": W.c3_mixed,
+           "lookup32": W.lookup32}[name]
     return [torch.from_numpy(gen().view(np.int64)).cuda()]
 
 
 def main() -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", action="append", required=True,
-                    help="c1_uniform20, c2_mr64, c3_mixed or c4_batched (repeatable)")
+                    help="c1_uniform20, c2_mr64, c3_mixed, lookup32 or c4_batched (repeatable)")
     ap.add_argument("--db", default=DEFAULT_DB)
     ap.add_argument("--reps", type=int, default=7)
     args = ap.parse_args()

@@ -114,7 +114,9 @@ def test_mr_work_counts_planted_passers():
 
 
 def test_classify_bytes_and_crossings():
-    a = np.array([0, 1, 2, 3, 4, 5, (1 << 32) - 1, 1 << 32, (1 << 32) + 1], dtype=np.uint64)
+    # table reads: odd values in [3, 2^32) coprime to 105 (11, 13, 2^32 - 5)
+    a = np.array([0, 1, 2, 3, 4, 5, 9, 11, 13, 15, 21, 35, (1 << 32) - 5, (1 << 32) - 1,
+                  1 << 32, (1 << 32) + 1], dtype=np.uint64)
     assert bench.classify_bytes(a) == 9 * a.size + 4 * 3
     # crossings: odd multiples of each prime 37 <= p < 2^16 from p^2 below 2^32
     ps = [p for p in range(37, 1 << 16, 2) if all(p % q for q in range(3, int(p ** 0.5) + 1, 2))]

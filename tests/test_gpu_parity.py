@@ -47,7 +47,8 @@ def assert_same(a, got, exp, what):
             what, bad.size, i.tolist(), a[i].tolist(), got[i].tolist(), exp[i].tolist()))
 
 
-EDGES = [0, 1, 2, 3, 4, 5, 9, 15, 25, 49, 121, 2047, 65521, 65535, 65537, (1 << 31) - 1,
+EDGES = [0, 1, 2, 3, 4, 5, 7, 9, 11, 15, 21, 25, 35, 49, 121, 209, 211, 221, 2047, 65521,
+         65535, 65537, (1 << 31) - 1, 4294967250, 4294967251, 4294967279,
          (1 << 32) - 5, (1 << 32) - 3, (1 << 32) - 1, 1 << 32, (1 << 32) + 1, (1 << 32) + 15,
          (1 << 32) + 17, 4294967291 * 4294967279, (1 << 61) - 1, (1 << 62) + 135,
          (1 << 63) - 25, (1 << 63) + 29, (1 << 63) + 1, U64 - 58, U64 - 2, U64 - 1, U64,
@@ -70,6 +71,25 @@ def test_table_equals_oracle(isp, oracle_table):
     assert int(tab[0]) == 0x64B4CB6E
     neq = np.nonzero(tab != oracle_table)[0]
     assert neq.size == 0, "table words differ at %s" % neq[:10].tolist()
+
+
+def test_wheel_table_equals_oracle(isp, oracle_table):
+    """The table the array path reads, on the 2*3*5*7 wheel (section 3):
+    bit 48 q + k stands for 210 q + r_k, r_k the k-th residue coprime to
+    210; every word against the oracle's odd-only table (bit i <-> 2i + 1,
+    so 210 q + r is bit 105 q + (r >> 1)), 0 at and above 2^32."""
+    wt = isp.wheel_table().cpu().numpy().view(np.uint32)
+    assert wt.size == 30678339
+    res = np.array([r for r in range(210) if np.gcd(r, 210) == 1])
+    assert res.size == 48 and res[1] == 11
+    blocks = -(-(1 << 32) // 210)
+    bits = np.unpackbits(oracle_table.view(np.uint8), bitorder="little")
+    assert bits.size == 1 << 31
+    bits = np.concatenate([bits, np.zeros(105 * blocks - bits.size, dtype=np.uint8)])
+    exp = np.packbits(bits.reshape(blocks, 105)[:, res >> 1].reshape(-1),
+                      bitorder="little").view(np.uint32)
+    neq = np.nonzero(wt != exp)[0]
+    assert neq.size == 0, "wheel table words differ at %s" % neq[:10].tolist()
 
 
 def test_montmul_against_python(isp):
@@ -105,6 +125,13 @@ def test_edge_values(isp):
 def test_all_below_2_20(isp):
     a = np.arange(1 << 20, dtype=np.uint64)
     assert_same(a, gpu_isprime(isp, a), expect(a, use_table=False), "0..2^20")
+
+
+def test_lookups_over_the_whole_table(isp, oracle_table):
+    """2^22 values uniform in [0, 2^32) (the lookup workload's first ones),
+    each an odd one read from the wheel table, against the oracle's table."""
+    a = W.lookup32(1 << 22)
+    assert_same(a, gpu_isprime(isp, a), expect(a, use_table=True), "lookups below 2^32")
 
 
 def test_window_around_table_bound(isp):
