@@ -434,6 +434,7 @@ def bench_served(isp, W, torch, num: int = 2100, warm: int = 100, max_inflight: 
     switch = sys.getswitchinterval()
     mismatched = set()
     srv = isp.Server(max_inflight=max_inflight, max_batch_elems=max_batch_elems)
+    footprint = srv.footprint()
     outs = [np.full(a.size, 2, np.uint8) for a in arrays]
 
     def check():
@@ -519,7 +520,9 @@ def bench_served(isp, W, torch, num: int = 2100, warm: int = 100, max_inflight: 
 
     head = by_load.get("0.7")
     return {"requests": num - warm, "warmup_requests": warm, "elements": int(elems),
-            "server": {"max_inflight": max_inflight, "max_batch_elems": max_batch_elems},
+            "server": {"max_inflight": max_inflight, "max_batch_elems": max_batch_elems,
+                       "footprint_device_bytes": footprint[0],
+                       "footprint_pinned_bytes": footprint[1]},
             "capacity_req_per_s": capacity, "qps": 0.7 * capacity,
             "served": head, "served_by_load": by_load,
             "serial_plain_capacity_req_per_s": plain_capacity,

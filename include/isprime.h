@@ -237,17 +237,23 @@ int isp_table_rebuild(int device, double *ms, double *wheel_ms);
 /* ---------------------------------------------------------------- serving
  * A request loop with continuous batching.  Requests carry HOST buffers
  * that the caller owns until isp_wait/isp_poll reports completion.  The
- * server admits a request when an in-flight slot and `mem_budget_bytes` of
- * device memory allow it; requests that arrive while others run are packed
- * into the next batch as soon as capacity frees up, and batches on
- * different streams overlap on the device.  Every result equals the plain
- * isprime_u64 result for the same input. */
+ * server admits a request while the bytes of admitted, unfinished requests
+ * (9 per element) stay within `mem_budget_bytes`; the memory it works in
+ * (max_inflight slots, each with a device workspace and pinned staging for
+ * max_batch_elems elements) is a fixed footprint reserved at creation
+ * (isp_server_footprint), so admission never allocates.  Requests that
+ * arrive while others run are packed into the next batch as soon as a slot
+ * frees up, each slot has its own stream and worker thread, and batches
+ * overlap on the device.  Every result equals the plain isprime_u64 result
+ * for the same input.  Paper: no section (the paper has no serving loop;
+ * the arithmetic is that of isprime_u64, sections 1-6). */
 typedef struct isp_server isp_server;
 
 typedef struct {
     int32_t device;            /* HIP device ordinal */
     int32_t max_inflight;      /* batches on the device at once: 1..8 (0 = 6) */
-    uint64_t mem_budget_bytes; /* bytes of admitted requests, 9 per element (0 = 1 GiB) */
+    uint64_t mem_budget_bytes; /* bytes of admitted, unfinished requests, 9 per element
+                                  (0 = 1 GiB); the slots' footprint is on top of it */
     uint64_t max_batch_elems;  /* elements per batch, at most 2^28 (0 = 1,048,576) */
     int32_t max_batch_reqs;    /* request pieces per batch (0 = 1024) */
     int32_t block_on_full;     /* 1: isp_submit waits for budget; 0: ISP_EBUSY */
@@ -271,6 +277,15 @@ int isp_poll(isp_server *srv, uint64_t ticket);
 /* Block until the request is done (timeout_us < 0: no limit).  Consumes the
  * ticket on success. */
 int isp_wait(isp_server *srv, uint64_t ticket, int64_t timeout_us);
+/* The memory the server holds for its lifetime, reserved at creation so
+ * that serving allocates nothing: *device_bytes, the slots' device
+ * workspaces (max_inflight x isp_workspace_bytes(max_batch_elems)), and
+ * *pinned_bytes, the slots' pinned, mapped staging buffers (9 bytes per
+ * element of max_batch_elems each, which the kernels read and write
+ * directly).  Admitted requests count against mem_budget_bytes on top of
+ * this fixed footprint. */
+int isp_server_footprint(const isp_server *srv, uint64_t *device_bytes, uint64_t *pinned_bytes);
+
 /* Finish every queued request, stop the worker threads, free the server.
  * No other call on this server may be in progress or follow. */
 int isp_server_destroy(isp_server *srv);

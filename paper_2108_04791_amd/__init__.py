@@ -106,6 +106,7 @@ SIGNATURES = {
     "isp_submit": (_I, [_P, _P, _P, _SZ, ctypes.POINTER(_U64)]),
     "isp_poll": (_I, [_P, _U64]),
     "isp_wait": (_I, [_P, _U64, ctypes.c_int64]),
+    "isp_server_footprint": (_I, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "isp_server_destroy": (_I, [_P]),
 }
 
@@ -403,6 +404,13 @@ class Server:
     def wait(self, ticket: int, timeout_us: int = -1) -> None:
         _check(lib().isp_wait(self._h, ticket, timeout_us), "isp_wait")
         self._keep.pop(ticket, None)
+
+    def footprint(self):
+        """(device bytes, pinned host bytes) reserved for the server's slots."""
+        d, p = _U64(), _U64()
+        _check(lib().isp_server_footprint(self._h, ctypes.byref(d), ctypes.byref(p)),
+               "isp_server_footprint")
+        return d.value, p.value
 
     def close(self) -> None:
         if self._h:

@@ -72,9 +72,9 @@ DeviceState g_dev[MAX_DEVICES];
 std::atomic<int> g_last_err{0};
 
 std::mutex g_cfg_mu;
-// The autotuner's choice for 2^24 64-bit values; other classes are in the
-// tuning database that paper_2108_04791_amd/tune.py writes.
-constexpr isp_config DEFAULT_CONFIG = {512, 8, 4, 24, 1, 1024, 2, 3, -1, -1};
+// The autotuner's choice for 2^26 values of mixed magnitude; other classes
+// are in the tuning database that paper_2108_04791_amd/tune.py writes.
+constexpr isp_config DEFAULT_CONFIG = {512, 8, 8, 8, 1, 1024, 2, 3, -1, -1};
 isp_config g_cfg = DEFAULT_CONFIG;
 
 int fail(hipError_t e)
@@ -523,6 +523,44 @@ int build_graph(BatchCtx &c, const DeviceState &ds, const Tuning &t)
 
 }  // namespace
 
+namespace isp {
+
+// The workspace of `stream` on `dev`, grown now to serve plain calls of up
+// to `len` elements (the request server reserves its slots' workspaces at
+// creation, so serving allocates nothing).  Returns its size in bytes.
+int reserve_stream_ws(int dev, void *stream, size_t len, uint64_t *bytes)
+{
+    StreamWs *sw = stream_ws(dev, stream);
+    std::lock_guard<std::mutex> g(sw->mu);
+    const int st = ensure_ws(sw->ws, std::min(len, PLAIN_PIECE), (hipStream_t)stream);
+    if (st == ISP_OK && bytes)
+        *bytes = isp_workspace_bytes(sw->ws.cap);
+    return st;
+}
+
+// Frees the workspaces kept for `stream` on `dev` (the stream is about to be
+// destroyed; nothing may be in flight on it).
+void release_stream_ws(int dev, void *stream)
+{
+    std::unique_ptr<StreamWs> sw;
+    {
+        std::lock_guard<std::mutex> g(g_ws_mu);
+        auto it = g_ws.find({dev, stream});
+        if (it != g_ws.end()) {
+            sw = std::move(it->second);
+            g_ws.erase(it);
+        }
+        g_last.erase({dev, stream});
+    }
+    if (sw) {
+        std::lock_guard<std::mutex> g(sw->mu);
+        free_ws(sw->ws);
+        free_range_ws(sw->rws);
+    }
+}
+
+}  // namespace isp
+
 // =================================================================== C ABI
 
 extern "C" {
@@ -711,6 +749,7 @@ int isprime_u64_noalloc(const uint64_t *n, uint8_t *out, size_t len, void *strea
 }
 
 size_t isp_noalloc_max_len(void) { return NOALLOC_MAX; }
+
 
 // Builds the interval sieve's prime list for `dev` on first use.
 static int ensure_range_primes(int dev)

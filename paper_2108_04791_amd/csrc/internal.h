@@ -238,6 +238,12 @@ hipError_t launch_range_sieve(uint64_t lo, uint8_t *out, uint64_t len, unsigned 
                               int partial_log2 = RANGE_PARTIAL_LOG2,
                               int complete_log2 = RANGE_PRIME_LOG2);
 
+// (api.hip) Grows the workspace of `stream` on `dev` for plain calls of up
+// to len elements; *bytes receives its size.  ISP_* status.
+int reserve_stream_ws(int dev, void *stream, size_t len, uint64_t *bytes);
+// (api.hip) Frees those workspaces (before the stream is destroyed).
+void release_stream_ws(int dev, void *stream);
+
 hipError_t launch_montmul_test(const uint64_t *a, const uint64_t *b, const uint64_t *n,
                                uint64_t *out, uint64_t len, hipStream_t s);
 

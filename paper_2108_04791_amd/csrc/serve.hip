@@ -8,20 +8,23 @@
 //
 // The dispatcher thread keeps up to max_inflight batches on the device: as
 // soon as a slot is free it packs the queued pieces (in arrival order) into
-// that slot's pinned staging buffer, and enqueues on the slot's own stream
-// the host-to-device copy, the isprime_u64 kernels over the whole packed
-// buffer (elements are independent, so one call classifies every piece),
-// the device-to-host copy and an event.  Requests that arrive while other
-// batches run are therefore packed into the next batch as capacity frees
-// up, and batches on different streams overlap on the device.
+// that slot's batch and hands it to the slot's own worker thread.  The
+// worker stages the inputs into the slot's pinned buffer, enqueues on the
+// slot's own stream the isprime_u64 kernels over the whole packed buffer
+// (elements are independent, so one call classifies every piece) and an
+// event, waits for the event, scatters the results to the requests' output
+// arrays and completes each request whose last piece has arrived.  The
+// pinned buffers are mapped and coherent: the kernels read the values and
+// write the verdicts there directly, so no copy engine is on the path
+// (asynchronous copies from pinned memory were measured to stall every
+// slot for 7-9 ms now and then, a few times a second).  Requests that
+// arrive while other batches run are packed into the next batch as
+// capacity frees up, batches on different streams overlap on the device,
+// and staging, launching and completing run in parallel across slots.  A
+// failed batch fails exactly the requests that had pieces in it.
 //
-// The completer thread waits for the oldest in-flight batch, scatters its
-// results to the requests' output arrays, and completes each request whose
-// last piece has arrived.  A failed batch fails exactly the requests that
-// had pieces in it.
-//
-// Test mode (cfg.test_mode = 1): no device at all; a batch "runs" on the
-// completer thread and writes n & 1 for every element, optionally after a
+// Test mode (cfg.test_mode = 1): no device at all; a batch "runs" on its
+// slot's worker thread and writes n & 1 for every element, optionally after a
 // delay and with every k-th batch failing, so the queueing, admission,
 // splitting and error paths can be checked on a machine without a GPU.
 #include <hip/hip_runtime.h>
@@ -171,14 +174,15 @@ private:
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    uint64_t *d_n = nullptr;
-    uint8_t *d_out = nullptr;
-    uint64_t *h_n = nullptr;  // pinned (plain heap in test mode)
+    uint64_t *h_n = nullptr;  // pinned, mapped, coherent (plain heap in test mode)
     uint8_t *h_out = nullptr;
+    const uint64_t *dev_n = nullptr;  // the device's addresses of h_n and h_out
+    uint8_t *dev_out = nullptr;
     std::vector<Piece> pieces;
     size_t elems = 0;
     int status = ISP_OK;
-    bool busy = false;
+    bool busy = false;  // a batch is assigned (until it completes)
+    std::thread worker;
 };
 
 }  // namespace
@@ -187,26 +191,28 @@ struct isp_server {
     isp_server_config cfg{};
     std::mutex mu;
     std::condition_variable cv_dispatch;  // queued work or a free slot
-    std::condition_variable cv_complete;  // a batch in flight
+    std::condition_variable cv_work;      // a batch assigned to a slot, or the end
     std::condition_variable cv_space;     // budget freed
     std::condition_variable cv_done;      // a request completed
     std::deque<Piece> queue;
     std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
-    std::deque<Slot *> inflight;
     std::vector<std::unique_ptr<Slot>> slots;
     uint64_t next_ticket = 1;
     uint64_t bytes_in_use = 0;
-    uint64_t batches = 0;
+    uint64_t batches = 0;  // batches run (test mode counts failures by it)
+    uint64_t device_bytes = 0;  // the slots' device workspaces, reserved at creation
+    uint64_t pinned_bytes = 0;  // the slots' pinned staging buffers
     bool stop = false;
     bool dispatcher_done = false;
-    std::unique_ptr<CopyPool> stage_pool;  // used by the dispatcher only
-    std::thread dispatcher, completer;
+    std::mutex stage_mu;  // one batch staged at a time, with all the copy threads
+    std::unique_ptr<CopyPool> stage_pool;
+    std::thread dispatcher;
 };
 
 namespace {
 
 constexpr size_t BYTES_PER_ELEM = sizeof(uint64_t) + sizeof(uint8_t);
-constexpr int SERVER_COPY_THREADS = 3;  // staging helpers next to the dispatcher
+constexpr int SERVER_COPY_THREADS = 3;  // staging helpers next to the staging worker
 
 void free_slot_resources(isp_server *s, Slot &sl)
 {
@@ -214,18 +220,16 @@ void free_slot_resources(isp_server *s, Slot &sl)
         delete[] sl.h_n;
         delete[] sl.h_out;
     } else {
-        if (sl.d_n)
-            (void)hipFree(sl.d_n);
-        if (sl.d_out)
-            (void)hipFree(sl.d_out);
         if (sl.h_n)
             (void)hipHostFree(sl.h_n);
         if (sl.h_out)
             (void)hipHostFree(sl.h_out);
         if (sl.done)
             (void)hipEventDestroy(sl.done);
-        if (sl.stream)
+        if (sl.stream) {
+            isp::release_stream_ws(s->cfg.device, sl.stream);
             (void)hipStreamDestroy(sl.stream);
+        }
     }
     sl = Slot();
 }
@@ -250,8 +254,6 @@ void finish_batch(isp_server *s, Slot &sl)
 
 void dispatcher_main(isp_server *s)
 {
-    if (!s->cfg.test_mode)
-        (void)hipSetDevice(s->cfg.device);
     const size_t cap = s->cfg.max_batch_elems;
     for (;;) {
         Slot *sl = nullptr;
@@ -269,8 +271,7 @@ void dispatcher_main(isp_server *s)
             });
             if (s->queue.empty()) {  // stopping and drained
                 s->dispatcher_done = true;
-                s->cv_complete.notify_all();
-                return;
+                break;
             }
             for (auto &x : s->slots)
                 if (!x->busy) {
@@ -286,8 +287,26 @@ void dispatcher_main(isp_server *s)
             }
             sl->busy = true;
         }
-        // stage the inputs (outside the lock: the host arrays belong to the
-        // requests until they complete)
+        s->cv_work.notify_all();
+    }
+    s->cv_work.notify_all();
+}
+
+// One slot's worker: runs each batch the dispatcher assigns to the slot,
+// from staging to completion.
+void slot_main(isp_server *s, Slot *sl)
+{
+    if (!s->cfg.test_mode)
+        (void)hipSetDevice(s->cfg.device);
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> g(s->mu);
+            s->cv_work.wait(g, [&] { return sl->busy || s->dispatcher_done; });
+            if (!sl->busy)
+                return;  // the dispatcher finished and nothing is assigned
+        }
+        // stage the inputs (outside the server lock: the host arrays belong
+        // to the requests until they complete)
         {
             std::vector<CopyPool::Seg> segs;
             segs.reserve(sl->pieces.size());
@@ -296,65 +315,32 @@ void dispatcher_main(isp_server *s)
                 segs.push_back({sl->h_n + off, p.req->n + p.off, p.len * sizeof(uint64_t)});
                 off += p.len;
             }
+            std::lock_guard<std::mutex> sg(s->stage_mu);
             s->stage_pool->run(segs);
         }
-        int st = ISP_OK;
-        if (!s->cfg.test_mode) {
-            hipError_t e = hipMemcpyAsync(sl->d_n, sl->h_n, sl->elems * sizeof(uint64_t),
-                                          hipMemcpyHostToDevice, sl->stream);
-            if (e == hipSuccess) {
-                st = isprime_u64(sl->d_n, sl->d_out, sl->elems, sl->stream);
-                if (st == ISP_OK)
-                    e = hipMemcpyAsync(sl->h_out, sl->d_out, sl->elems, hipMemcpyDeviceToHost,
-                                       sl->stream);
-            }
-            if (e == hipSuccess && st == ISP_OK)
-                e = hipEventRecord(sl->done, sl->stream);
-            if (e != hipSuccess && st == ISP_OK)
-                st = ISP_EDEVICE;
-        }
+        uint64_t seq;
         {
             std::lock_guard<std::mutex> g(s->mu);
-            sl->status = st;
-            ++s->batches;
-            s->inflight.push_back(sl);
+            seq = ++s->batches;
         }
-        s->cv_complete.notify_one();
-    }
-}
-
-void completer_main(isp_server *s)
-{
-    if (!s->cfg.test_mode)
-        (void)hipSetDevice(s->cfg.device);
-    uint64_t seen = 0;
-    for (;;) {
-        Slot *sl = nullptr;
-        {
-            std::unique_lock<std::mutex> g(s->mu);
-            s->cv_complete.wait(g, [&] { return !s->inflight.empty() || s->dispatcher_done; });
-            if (s->inflight.empty())
-                return;  // dispatcher finished and nothing in flight
-            sl = s->inflight.front();
-            s->inflight.pop_front();
-        }
-        ++seen;
-        int st = sl->status;
+        int st = ISP_OK;
         if (s->cfg.test_mode) {
             if (s->cfg.test_delay_us > 0)
                 std::this_thread::sleep_for(std::chrono::microseconds(s->cfg.test_delay_us));
-            if (s->cfg.test_fail_every > 0 && seen % (uint64_t)s->cfg.test_fail_every == 0)
+            if (s->cfg.test_fail_every > 0 && seq % (uint64_t)s->cfg.test_fail_every == 0)
                 st = ISP_EDEVICE;
             else
                 for (size_t i = 0; i < sl->elems; ++i)
                     sl->h_out[i] = (uint8_t)(sl->h_n[i] & 1);
-        } else if (st == ISP_OK) {
-            hipError_t e = hipEventSynchronize(sl->done);
-            if (e != hipSuccess)
-                st = ISP_EDEVICE;
         } else {
-            // a failed enqueue may have left the copy of h_n in flight
-            (void)hipStreamSynchronize(sl->stream);
+            st = isprime_u64(sl->dev_n, sl->dev_out, sl->elems, sl->stream);
+            hipError_t e = st == ISP_OK ? hipEventRecord(sl->done, sl->stream) : hipSuccess;
+            if (st == ISP_OK && e == hipSuccess)
+                e = hipEventSynchronize(sl->done);
+            else
+                (void)hipStreamSynchronize(sl->stream);  // whatever was enqueued
+            if (e != hipSuccess && st == ISP_OK)
+                st = ISP_EDEVICE;
         }
         if (st == ISP_OK) {
             size_t off = 0;
@@ -417,15 +403,27 @@ int isp_server_create(const isp_server_config *cfg, isp_server **srv)
             hipError_t e = hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking);
             if (e == hipSuccess)
                 e = hipEventCreateWithFlags(&sl->done, hipEventDisableTiming);
+            const unsigned fl = hipHostMallocMapped | hipHostMallocCoherent;
             if (e == hipSuccess)
-                e = hipMalloc(&sl->d_n, cap * sizeof(uint64_t));
+                e = hipHostMalloc(&sl->h_n, cap * sizeof(uint64_t), fl);
             if (e == hipSuccess)
-                e = hipMalloc(&sl->d_out, cap);
+                e = hipHostMalloc(&sl->h_out, cap, fl);
+            void *dn = nullptr, *dout = nullptr;
             if (e == hipSuccess)
-                e = hipHostMalloc(&sl->h_n, cap * sizeof(uint64_t), hipHostMallocDefault);
+                e = hipHostGetDevicePointer(&dn, sl->h_n, 0);
             if (e == hipSuccess)
-                e = hipHostMalloc(&sl->h_out, cap, hipHostMallocDefault);
-            if (e != hipSuccess)
+                e = hipHostGetDevicePointer(&dout, sl->h_out, 0);
+            sl->dev_n = static_cast<const uint64_t *>(dn);
+            sl->dev_out = static_cast<uint8_t *>(dout);
+            // the workspace of the slot's stream, at its largest batch now,
+            // so that serving never allocates device memory
+            uint64_t wb = 0;
+            if (e == hipSuccess) {
+                st = isp::reserve_stream_ws(c.device, sl->stream, cap, &wb);
+                s->device_bytes += wb;
+                s->pinned_bytes += cap * BYTES_PER_ELEM;
+            }
+            if (e != hipSuccess && st == ISP_OK)
                 st = e == hipErrorOutOfMemory ? ISP_ENOMEM : ISP_EDEVICE;
         }
         s->slots.push_back(std::move(sl));
@@ -439,8 +437,9 @@ int isp_server_create(const isp_server_config *cfg, isp_server **srv)
     }
     isp_server *raw = s.release();
     raw->stage_pool.reset(new CopyPool(SERVER_COPY_THREADS));
+    for (auto &sl : raw->slots)
+        sl->worker = std::thread(slot_main, raw, sl.get());
     raw->dispatcher = std::thread(dispatcher_main, raw);
-    raw->completer = std::thread(completer_main, raw);
     *srv = raw;
     return ISP_OK;
 }
@@ -520,6 +519,15 @@ int isp_wait(isp_server *s, uint64_t ticket, int64_t timeout_us)
     return st;
 }
 
+int isp_server_footprint(const isp_server *s, uint64_t *device_bytes, uint64_t *pinned_bytes)
+{
+    if (!s || !device_bytes || !pinned_bytes)
+        return ISP_EINVAL;
+    *device_bytes = s->device_bytes;
+    *pinned_bytes = s->pinned_bytes;
+    return ISP_OK;
+}
+
 int isp_server_destroy(isp_server *s)
 {
     if (!s)
@@ -529,11 +537,11 @@ int isp_server_destroy(isp_server *s)
         s->stop = true;
     }
     s->cv_dispatch.notify_all();
-    s->cv_complete.notify_all();
     if (s->dispatcher.joinable())
-        s->dispatcher.join();
-    if (s->completer.joinable())
-        s->completer.join();
+        s->dispatcher.join();  // the queue is drained into the slots
+    for (auto &sl : s->slots)
+        if (sl->worker.joinable())
+            sl->worker.join();  // each finishes its batch, then sees the end
     if (!s->cfg.test_mode)
         (void)hipSetDevice(s->cfg.device);
     for (auto &sl : s->slots)

@@ -94,6 +94,10 @@ def test_served_at_the_benchmarked_configuration(isp):
     assert max(r.size for r in reqs) > (1 << 19)
     exp = [oracle.isprime_array(r, nthreads=NTHREADS, use_table=True)[0] for r in reqs]
     with isp.Server() as srv:
+        # the fixed footprint: 6 slots, each a workspace for 2^20 elements
+        # and 9 pinned bytes per element
+        dev_b, pin_b = srv.footprint()
+        assert dev_b == 6 * isp.workspace_bytes(1 << 20) and pin_b == 6 * 9 * (1 << 20)
         mixed = [np.full(r.size, 2, np.uint8) for r in reqs]
         tickets = [srv.submit(r, o) for r, o in zip(reqs, mixed)]
         for t in tickets:
