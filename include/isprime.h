@@ -122,6 +122,21 @@ size_t isp_noalloc_max_len(void);
 int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
                         const uint64_t *lens, size_t num_arrays, void *stream);
 
+/* Many arrays laid end to end in one buffer: array a is n[offsets[a] ..
+ * offsets[a + 1]) with its verdicts at the same places of out.
+ *   n, out     device pointers to the concatenated values and verdicts
+ *   offsets    num_arrays + 1 non-decreasing element offsets, in device or
+ *              host memory (device offsets are read after the stream's
+ *              earlier work: the call waits for the stream)
+ * Every element of [offsets[0], offsets[num_arrays]) is decided, and nothing
+ * else is written.  Decreasing offsets -> ISP_EINVAL; NULL n or out with a
+ * nonempty range -> ISP_EINVAL.  Since every element is decided alone, the
+ * arrays of one buffer run as a single isprime_u64 launch sequence over the
+ * covered range (for arrays in separate buffers, isprime_u64_batched).
+ * Results are identical to one isprime_u64 call per array. */
+int isprime_u64_batched_offsets(const uint64_t *n, uint8_t *out, const uint64_t *offsets,
+                                size_t num_arrays, void *stream);
+
 /* out[i] = primality of lo + i for 0 <= i < len: a contiguous interval,
  * with no input array.  lo + len - 1 must not exceed 2^64 - 1 (ISP_EINVAL).
  *   out  device pointer to len bytes, each written 0 or 1
@@ -143,6 +158,14 @@ int isprime_range_u64(uint64_t lo, uint8_t *out, size_t len, void *stream);
 
 /* Bytes of device workspace a call over `len` elements may use. */
 size_t isp_workspace_bytes(size_t len);
+
+/* Bytes of device workspace isprime_range_u64(lo, ..., len) holds: the
+ * survivor workspace of its largest piece that goes to Miller-Rabin and the
+ * bucket workspace of its largest bucket-mode piece (pieces decided by the
+ * sieve alone need neither); 0 for an empty or invalid interval.  The
+ * interval sieve's prime list (24.8 MB per device, built on the first
+ * interval call) is not counted. */
+size_t isp_range_workspace_bytes(uint64_t lo, size_t len);
 
 /* The hipError_t (as int) behind the most recent ISP_EDEVICE. */
 int isp_last_device_error(void);

@@ -89,8 +89,10 @@ SIGNATURES = {
     "isprime_u64_noalloc": (_I, [_P, _P, _SZ, _P]),
     "isp_noalloc_max_len": (_SZ, []),
     "isprime_u64_batched": (_I, [_P, _P, _P, _SZ, _P]),
+    "isprime_u64_batched_offsets": (_I, [_P, _P, _P, _SZ, _P]),
     "isprime_range_u64": (_I, [_U64, _P, _SZ, _P]),
     "isp_workspace_bytes": (_SZ, [_SZ]),
+    "isp_range_workspace_bytes": (_SZ, [_U64, _SZ]),
     "isp_last_device_error": (_I, []),
     "isp_strerror": (ctypes.c_char_p, [_I]),
     "isp_get_config": (_I, [ctypes.POINTER(Config)]),
@@ -161,6 +163,23 @@ def _stream_handle(stream) -> int:
     return stream.cuda_stream
 
 
+def _on_stream(stream, *tensors) -> None:
+    """Before a call on a stream other than the current one: that stream
+    waits for the current stream's work (copies and allocations made here,
+    e.g. a .contiguous() copy of the input or a new output), and each
+    tensor is recorded as used on it, so that the caching allocator does not
+    hand its memory out again while the call may still read or write it."""
+    if stream is None:
+        return
+    cur = torch.cuda.current_stream(stream.device)
+    if stream == cur:
+        return
+    stream.wait_stream(cur)
+    for t in tensors:
+        if t is not None and t.is_cuda:
+            t.record_stream(stream)
+
+
 def _as_u64(t: torch.Tensor) -> torch.Tensor:
     if t.dtype not in (torch.uint64, torch.int64):
         raise TypeError("expected a torch.uint64 (or int64-viewed) tensor, got %s" % t.dtype)
@@ -188,6 +207,7 @@ def isprime_into(n: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tenso
     if out.numel() != n.numel():
         raise ValueError("out has %d elements, n has %d" % (out.numel(), n.numel()))
     with torch.cuda.device(n.device):
+        _on_stream(stream, n, out)
         _check(lib().isprime_u64(n.data_ptr(), out.data_ptr(), n.numel(), _stream_handle(stream)),
                "isprime_u64")
     return out
@@ -205,6 +225,7 @@ def isprime_into_noalloc(n: torch.Tensor, out: torch.Tensor, stream=None) -> tor
     if out.numel() != n.numel():
         raise ValueError("out has %d elements, n has %d" % (out.numel(), n.numel()))
     with torch.cuda.device(n.device):
+        _on_stream(stream, n, out)
         _check(lib().isprime_u64_noalloc(n.data_ptr(), out.data_ptr(), n.numel(),
                                          _stream_handle(stream)), "isprime_u64_noalloc")
     return out
@@ -249,6 +270,7 @@ class Batch:
         if self.k == 0:
             return self.outs
         with torch.cuda.device(self._device):
+            _on_stream(stream, *self.arrays, *self.outs)
             _check(lib().isprime_u64_batched(ctypes.cast(self._nps, _P), ctypes.cast(self._ops, _P),
                                              ctypes.cast(self._lens, _P), self.k,
                                              _stream_handle(stream)),
@@ -261,6 +283,32 @@ def isprime_batched(arrays, outs=None, stream=None):
     return Batch(arrays, outs).run(stream)
 
 
+def isprime_batched_offsets(n: torch.Tensor, offsets: torch.Tensor, out: torch.Tensor | None = None,
+                            stream=None) -> torch.Tensor:
+    """Arrays laid end to end in one tensor: array a is n[offsets[a]:offsets[a+1]]
+    (offsets: int64/uint64, on the device or the host).  Returns the bool
+    verdicts over n's length (elements outside the arrays are left as
+    they were in `out`, which is created zeroed when not given)."""
+    n = _as_u64(n)
+    if offsets.dtype not in (torch.uint64, torch.int64) or not offsets.is_contiguous():
+        raise TypeError("offsets must be a contiguous uint64 / int64 tensor")
+    if out is None:
+        out = torch.zeros(n.shape, dtype=torch.bool, device=n.device)
+    if out.numel() != n.numel() or not out.is_contiguous() or out.dtype not in (torch.bool, torch.uint8):
+        raise ValueError("out must be a contiguous bool/uint8 tensor of n's size")
+    num = offsets.numel() - 1
+    if num < 0:
+        raise ValueError("offsets needs at least one entry")
+    if num > 0 and int(offsets[-1]) > n.numel():
+        raise ValueError("offsets run past the end of n")
+    with torch.cuda.device(n.device):
+        _on_stream(stream, n, out, offsets if offsets.is_cuda else None)
+        _check(lib().isprime_u64_batched_offsets(n.data_ptr(), out.data_ptr(), offsets.data_ptr(),
+                                                 num, _stream_handle(stream)),
+               "isprime_u64_batched_offsets")
+    return out
+
+
 def isprime_range(lo: int, length: int, out: torch.Tensor | None = None, stream=None,
                   device=None) -> torch.Tensor:
     """Boolean tensor: element i is True iff lo + i is prime (a contiguous
@@ -270,6 +318,7 @@ def isprime_range(lo: int, length: int, out: torch.Tensor | None = None, stream=
     if out.numel() != length or not out.is_contiguous() or out.dtype not in (torch.bool, torch.uint8):
         raise ValueError("out must be a contiguous bool/uint8 tensor of `length` elements")
     with torch.cuda.device(out.device):
+        _on_stream(stream, out)
         _check(lib().isprime_range_u64(lo, out.data_ptr() if length else None, length,
                                        _stream_handle(stream)), "isprime_range_u64")
     return out
@@ -279,6 +328,7 @@ def montmul(a: torch.Tensor, b: torch.Tensor, n: torch.Tensor, stream=None) -> t
     """Diagnostic: a*b mod n on the device through Montgomery form (odd n >= 3)."""
     a, b, n = _as_u64(a), _as_u64(b), _as_u64(n)
     out = torch.empty_like(n)
+    _on_stream(stream, a, b, n, out)
     _check(lib().isp_montmul_u64(a.data_ptr(), b.data_ptr(), n.data_ptr(), out.data_ptr(),
                                  n.numel(), _stream_handle(stream)), "isp_montmul_u64")
     return out

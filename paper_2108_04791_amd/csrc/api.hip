@@ -165,18 +165,6 @@ int ensure_range_ws(RangeWs &rw, uint64_t count_cap, uint64_t hit_cap, hipStream
     return ISP_OK;
 }
 
-// floor(sqrt(x)) for x < 2^64.
-uint64_t isqrt_host(uint64_t x)
-{
-    uint64_t r = (uint64_t)std::sqrt((double)x);
-    if (r > 0xffffffffull)
-        r = 0xffffffffull;
-    while (r * r > x)
-        --r;
-    while (r < 0xffffffffull && (r + 1) * (r + 1) <= x)
-        ++r;
-    return r;
-}
 
 // An upper bound on the bucket hits of one piece of `len` numbers: each odd
 // prime p in (BUCKET_SMALL, root] has at most floor(len / 2p) + 1 odd
@@ -523,6 +511,89 @@ int build_graph(BatchCtx &c, const DeviceState &ds, const Tuning &t)
 
 }  // namespace
 
+namespace {
+
+// How one piece of an interval call runs (isprime_range_u64), from its
+// first number and length.
+struct RangePlan {
+    uint64_t root;           // floor(sqrt(last number of the piece))
+    bool bucket;             // bucket mode: every segment complete, no Miller-Rabin
+    unsigned grid;           // sieve workgroups (segments)
+    unsigned groups;         // bucket mode: groups of the bucket passes
+    uint64_t count_words;    // bucket mode: bucket counts and scan sums
+    uint64_t hit_words;      // bucket mode: bound on the bucket hits
+    bool complete;           // the sieve decides every number (no Miller-Rabin)
+    int partial_log2;        // otherwise the primes below 2^this, then Miller-Rabin
+    int complete_log2;       // segments whose root is below 2^this are complete
+};
+
+RangePlan plan_range_piece(uint64_t first, uint64_t piece)
+{
+    RangePlan p{};
+    p.root = isqrt_u64(first + (piece - 1));
+    // Bucket mode (every segment complete, no Miller-Rabin) once the
+    // per-segment loop over the primes up to the root costs more than the
+    // bucket passes (measured: roots above 2^23), and while the passes'
+    // cost is below Miller-Rabin's on the piece's survivors.  Measured on
+    // 2^28-number pieces: the bucket mode takes about 2.5 ps per number
+    // plus 11 ps per prime up to the root, Miller-Rabin about 12 ps per
+    // number, so buckets win while pi(root) < 0.85 len (pi(root) is taken
+    // as root / ln root, a few percent low; a choice of mode only, which
+    // changes no output bit).
+    const double pi_root = (double)p.root / std::log((double)p.root + 2.0);
+    p.bucket = p.root > ((uint64_t)1 << BUCKET_FROM_LOG2) && pi_root < 0.8 * (double)piece;
+    const unsigned full = (unsigned)((piece + RANGE_SEG - 1) / RANGE_SEG);
+    if (p.bucket) {
+        p.grid = full;
+        const uint64_t words = (p.root >> 6) + 1 - ((BUCKET_SMALL + 1) >> 6);
+        // groups of 1024 threads, two per CU (their LDS allows it): one per
+        // 1024 table words, at most MAX_BUCKET_GROUPS, and half of that for
+        // roots below 2^26 (fewer words per group do not pay for the longer
+        // count array and scans) and for pieces of more than 512 segments
+        // (whose count array grows with groups x segments); measured on 2^28
+        // and 2^30 numbers at 2^48 .. 2^64
+        const uint64_t gmax = p.grid > 512 || words < ((uint64_t)1 << 20) ? MAX_BUCKET_GROUPS / 2
+                                                                          : MAX_BUCKET_GROUPS;
+        p.groups = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(gmax, words / 1024));
+        // counts (+ total) and the scan's tile sums (+ total)
+        const uint64_t n = (uint64_t)p.grid * p.groups;
+        p.count_words = n + 1 + n / 8192 + 2;
+        p.hit_words = bucket_hit_bound(piece, p.root);
+        p.complete = true;
+        return p;
+    }
+    // every segment of a piece whose square root is below 2^25 is decided
+    // by the sieve alone (no survivors, no Miller-Rabin), unless the piece
+    // is short and the primes up to its root many: then its few segments
+    // would each wait on a pass over all of them, and the primes below 2^18
+    // with Miller-Rabin on the 4.5% that survive cost less.  Measured: a
+    // segment pass costs about 0.45 ns per prime, Miller-Rabin on the
+    // survivors about 0.011 ns per number of the piece, over 0.03 ms more
+    // of fixed cost.
+    const bool short_piece = full < PARTIAL_FULL_GRID;
+    const bool force_partial = short_piece && p.root >= ((uint64_t)1 << PARTIAL_SHORT_LOG2) &&
+                               pi_root > (double)piece / 40.0 + 65536.0;
+    p.complete_log2 = force_partial ? PARTIAL_SHORT_LOG2 : RANGE_PRIME_LOG2;
+    p.complete = p.root < ((uint64_t)1 << p.complete_log2);
+    // a short piece in Miller-Rabin mode is cut into up to PARTIAL_FULL_GRID
+    // shorter segments (at least RANGE_MIN_CHUNK numbers each): its
+    // workgroups then share the crossings, while each still visits the few
+    // primes below the short-piece bound (in complete mode each segment
+    // visits every prime up to the root, so more segments would only repeat
+    // that work)
+    p.grid = p.complete || !short_piece
+                 ? full
+                 : (unsigned)std::max<uint64_t>(
+                       full, std::min<uint64_t>(PARTIAL_FULL_GRID, piece / RANGE_MIN_CHUNK));
+    // a short piece has few segments, each visiting all the primes below
+    // the bound one after another: a lower bound there costs more
+    // Miller-Rabin on the extra survivors but far less sieve latency
+    p.partial_log2 = short_piece ? PARTIAL_SHORT_LOG2 : RANGE_PARTIAL_LOG2;
+    return p;
+}
+
+}  // namespace
+
 namespace isp {
 
 // The workspace of `stream` on `dev`, grown now to serve plain calls of up
@@ -818,84 +889,40 @@ int isprime_range_u64(uint64_t lo, uint8_t *out, size_t len, void *stream)
         return ISP_OK;
     StreamWs *sw = stream_ws(dev, stream);
     std::lock_guard<std::mutex> g(sw->mu);
-    st = ensure_ws(sw->ws, std::min<uint64_t>(len - below, RANGE_PIECE), s);
+    // pieces decided by the sieve alone need no survivor workspace: it is
+    // allocated (or grown) only for a piece that goes to Miller-Rabin
+    const Workspace none;
     for (uint64_t off = below; off < len && st == ISP_OK; off += RANGE_PIECE) {
         const uint64_t piece = std::min<uint64_t>(RANGE_PIECE, len - off);
-        const uint64_t root = isqrt_host(lo + off + (piece - 1));
-        // Bucket mode (every segment complete, no Miller-Rabin) once the
-        // per-segment loop over the primes up to the root costs more than the
-        // bucket passes (measured: roots above 2^23), and while the passes'
-        // cost is below Miller-Rabin's on the piece's survivors.  Measured on
-        // 2^28-number pieces: the bucket mode takes about 2.5 ps per number
-        // plus 11 ps per prime up to the root, Miller-Rabin about 12 ps per
-        // number, so buckets win while pi(root) < 0.85 len (pi(root) is taken
-        // as root / ln root, a few percent low).
-        const double pi_root = (double)root / std::log((double)root + 2.0);
-        const bool bucket = root > ((uint64_t)1 << BUCKET_FROM_LOG2) && pi_root < 0.8 * (double)piece;
+        const RangePlan pl = plan_range_piece(lo + off, piece);
         hipError_t e = hipSuccess;
-        if (bucket) {
-            const unsigned grid = (unsigned)((piece + RANGE_SEG - 1) / RANGE_SEG);
-            const uint64_t words = (root >> 6) + 1 - ((BUCKET_SMALL + 1) >> 6);
-            // groups of 1024 threads, two per CU (their LDS allows it): one
-            // per 1024 table words, at most MAX_BUCKET_GROUPS, and half of
-            // that for roots below 2^26 (fewer words per group do not pay
-            // for the longer count array and scans) and for pieces of more
-            // than 512 segments (whose count array grows with groups x
-            // segments); measured on 2^28 and 2^30 numbers at 2^48 .. 2^64
-            const uint64_t gmax = grid > 512 || words < ((uint64_t)1 << 20) ? MAX_BUCKET_GROUPS / 2
-                                                                            : MAX_BUCKET_GROUPS;
-            const unsigned groups =
-                (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(gmax, words / 1024));
-            // counts (+ total) and the scan's tile sums (+ total)
-            const uint64_t n = (uint64_t)grid * groups;
-            st = ensure_range_ws(sw->rws, n + 1 + n / 8192 + 2, bucket_hit_bound(piece, root), s);
+        if (pl.bucket) {
+            st = ensure_range_ws(sw->rws, pl.count_words, pl.hit_words, s);
             if (st != ISP_OK)
                 break;
-            e = launch_range_buckets(lo + off, piece, root, groups, ds, sw->rws, s);
+            e = launch_range_buckets(lo + off, piece, pl.root, pl.groups, ds, sw->rws, s);
             if (e == hipSuccess)
-                e = launch_range_sieve(lo + off, out + off, piece, grid, RANGE_SEG, groups, ds,
-                                       sw->ws, sw->rws, s);
+                e = launch_range_sieve(lo + off, out + off, piece, pl.grid, RANGE_SEG, pl.groups,
+                                       ds, none, sw->rws, s);
         } else {
-            const unsigned full = (unsigned)((piece + RANGE_SEG - 1) / RANGE_SEG);
-            // every segment of a piece whose square root is below 2^25 is
-            // decided by the sieve alone (no survivors, no Miller-Rabin),
-            // unless the piece is short and the primes up to its root many:
-            // then its few segments would each wait on a pass over all of
-            // them, and the primes below 2^18 with Miller-Rabin on the 4.5%
-            // that survive cost less.  Measured: a segment pass costs about
-            // 0.45 ns per prime, Miller-Rabin on the survivors about 0.011 ns
-            // per number of the piece, over 0.03 ms more of fixed cost.
-            const bool short_piece = full < PARTIAL_FULL_GRID;
-            const bool force_partial = short_piece && root >= ((uint64_t)1 << PARTIAL_SHORT_LOG2) &&
-                                       pi_root > (double)piece / 40.0 + 65536.0;
-            const int complete_log2 = force_partial ? PARTIAL_SHORT_LOG2 : RANGE_PRIME_LOG2;
-            const bool complete = root < ((uint64_t)1 << complete_log2);
-            // a short piece in Miller-Rabin mode is cut into up to
-            // PARTIAL_FULL_GRID shorter segments (at least RANGE_MIN_CHUNK
-            // numbers each): its workgroups then share the crossings, while
-            // each still visits the few primes below the short-piece bound
-            // (in complete mode each segment visits every prime up to the
-            // root, so more segments would only repeat that work)
-            const unsigned grid =
-                complete || !short_piece
-                    ? full
-                    : (unsigned)std::max<uint64_t>(
-                          full, std::min<uint64_t>(PARTIAL_FULL_GRID, piece / RANGE_MIN_CHUNK));
+            if (!pl.complete) {
+                st = ensure_ws(sw->ws, piece, s);
+                if (st != ISP_OK)
+                    break;
+            }
+            const Workspace &ws = pl.complete ? none : sw->ws;
             ClassifyArgs ca;
             MrArgs ma;
             unsigned grid_c, grid1;
-            make_args(ds, sw->ws, t, piece, ca, ma, grid_c, grid1);
+            make_args(ds, ws, t, piece, ca, ma, grid_c, grid1);
             ma.total = piece;
-            ma.grid_c = grid;
-            // a short piece has few segments, each visiting all the primes below
-            // the bound one after another: a lower bound there costs more
-            // Miller-Rabin on the extra survivors but far less sieve latency
-            const int partial = short_piece ? PARTIAL_SHORT_LOG2 : RANGE_PARTIAL_LOG2;
-            e = launch_range_sieve(lo + off, out + off, piece, grid, classify_chunk(piece, grid),
-                                   0, ds, sw->ws, sw->rws, s, partial, complete_log2);
-            if (e == hipSuccess && !complete)
+            ma.grid_c = pl.grid;
+            e = launch_range_sieve(lo + off, out + off, piece, pl.grid,
+                                   classify_chunk(piece, pl.grid), 0, ds, ws, sw->rws, s,
+                                   pl.partial_log2, pl.complete_log2);
+            if (e == hipSuccess && !pl.complete)
                 e = launch_mr1(ma, t.mr_block, s);
-            if (e == hipSuccess && !complete)
+            if (e == hipSuccess && !pl.complete)
                 e = t.rest_test ? launch_lucas(ma, ds.cus, t.mr_blocks_per_cu, grid1, t.mr_block, s)
                                 : launch_mr2(ma, ds.cus, t.mr_blocks_per_cu, grid1, t.mr_block,
                                              t.mr_window, s);
@@ -1039,6 +1066,47 @@ int isprime_u64_batched(const uint64_t *const *n_ptrs, uint8_t *const *out_ptrs,
     return ISP_OK;
 }
 
+int isprime_u64_batched_offsets(const uint64_t *n, uint8_t *out, const uint64_t *offsets,
+                                size_t num_arrays, void *stream)
+{
+    if (num_arrays == 0)
+        return ISP_OK;
+    if (!offsets || num_arrays > 0x7fffffffu)
+        return ISP_EINVAL;
+    int dev = 0;
+    int st = current_device(&dev);
+    if (st != ISP_OK)
+        return st;
+    // the offsets, wherever they live: device memory is read after the
+    // stream's earlier work (which may have written them)
+    std::vector<uint64_t> off(num_arrays + 1);
+    hipPointerAttribute_t attr;
+    const bool on_device = hipPointerGetAttributes(&attr, offsets) == hipSuccess &&
+                           attr.type == hipMemoryTypeDevice;
+    (void)hipGetLastError();  // a plain host pointer is not an error
+    if (on_device) {
+        hipError_t e = hipMemcpyAsync(off.data(), offsets, off.size() * sizeof(uint64_t),
+                                      hipMemcpyDeviceToHost, (hipStream_t)stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess)
+            return fail(e);
+    } else {
+        std::memcpy(off.data(), offsets, off.size() * sizeof(uint64_t));
+    }
+    for (size_t a = 0; a < num_arrays; ++a)
+        if (off[a + 1] < off[a])
+            return ISP_EINVAL;  // arrays must follow one another
+    const uint64_t len = off[num_arrays] - off[0];
+    if (len == 0)
+        return ISP_OK;
+    if (!n || !out)
+        return ISP_EINVAL;
+    // the arrays tile [off[0], off[num]) of the buffers and every element is
+    // decided alone, so one launch sequence over that range decides them all
+    return isprime_u64(n + off[0], out + off[0], len, stream);
+}
+
 size_t isp_workspace_bytes(size_t len)
 {
     size_t cap = 1 << 16;
@@ -1046,6 +1114,23 @@ size_t isp_workspace_bytes(size_t len)
         cap <<= 1;
     return (2 * cap + 65 * (size_t)MAX_GRID) * sizeof(Survivor) +
            (cap + (size_t)MAX_GRID) * sizeof(MontPrep) + 2 * MAX_GRID * sizeof(uint32_t);
+}
+
+size_t isp_range_workspace_bytes(uint64_t lo, size_t len)
+{
+    if (len == 0 || lo + (uint64_t)(len - 1) < lo)
+        return 0;
+    const uint64_t below = lo < TABLE_BOUND ? std::min<uint64_t>(len, TABLE_BOUND - lo) : 0;
+    size_t mr = 0, buckets = 0;
+    for (uint64_t off = below; off < len; off += RANGE_PIECE) {
+        const uint64_t piece = std::min<uint64_t>(RANGE_PIECE, len - off);
+        const RangePlan p = plan_range_piece(lo + off, piece);
+        if (p.bucket)
+            buckets = std::max<size_t>(buckets, (p.count_words + p.hit_words) * sizeof(uint32_t));
+        else if (!p.complete)
+            mr = std::max(mr, isp_workspace_bytes(piece));
+    }
+    return mr + buckets;
 }
 
 int isp_last_device_error(void) { return g_last_err.load(); }

@@ -44,6 +44,25 @@ static_assert(WHEEL.res[0] == 1 && WHEEL.res[1] == 11 && WHEEL.res[WHEEL_RES - 1
                   WHEEL.pos[209] == WHEEL_RES - 1 && WHEEL.pos[3] == 0xff,
               "48 residues coprime to 210");
 
+// floor(sqrt(x)) for every x < 2^64 by the digit-by-digit method (one
+// result bit per step, 32 steps at most): integer arithmetic only.
+__host__ __device__ inline uint64_t isqrt_u64(uint64_t x)
+{
+    uint64_t r = 0, bit = (uint64_t)1 << 62;
+    while (bit > x)
+        bit >>= 2;
+    while (bit != 0) {
+        if (x >= r + bit) {
+            x -= r + bit;
+            r = (r >> 1) + bit;
+        } else {
+            r >>= 1;
+        }
+        bit >>= 2;
+    }
+    return r;
+}
+
 // floor(n / 210) for odd n < 2^32: floor((n >> 1) / 105), by the
 // multiplier ceil(2^38 / 105) = 2617884829, exact for every value below
 // 2^31 (its excess 2617884829 * 105 - 2^38 = 101 is below 2^7).

@@ -313,13 +313,7 @@ __device__ __forceinline__ int strong_lucas(uint64_t n)
     if (n == ~(uint64_t)0)
         return 0;  // 3 divides 2^64 - 1 (and n + 1 would wrap)
     // a perfect square has no D with (D/n) = -1
-    uint64_t r = (uint64_t)sqrt((double)n);
-    if (r > 0xffffffffull)
-        r = 0xffffffffull;
-    while (r * r > n)
-        --r;
-    while (r < 0xffffffffull && (r + 1) * (r + 1) <= n)
-        ++r;
+    const uint64_t r = isqrt_u64(n);
     if (r * r == n)
         return 0;
     int32_t D = 5;

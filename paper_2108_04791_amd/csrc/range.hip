@@ -225,18 +225,6 @@ struct RangeArgs {
     uint32_t complete_log2;     // segments whose root is below 2^this are complete
 };
 
-// Integer square root of x < 2^64 (floor), from a double estimate.
-__device__ __forceinline__ uint64_t isqrt64(uint64_t x)
-{
-    uint64_t r = (uint64_t)sqrt((double)x);
-    if (r > 0xffffffffull)
-        r = 0xffffffffull;
-    while (r * r > x)
-        --r;
-    while (r < 0xffffffffull && (r + 1) * (r + 1) <= x)
-        ++r;
-    return r;
-}
 
 __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
 {
@@ -252,7 +240,7 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
     const uint64_t r0 = (uint64_t)blockIdx.x * chunk;
     const uint64_t r1 = r0 + chunk < a.len ? r0 + chunk : a.len;
     if (r0 >= r1) {
-        if (tid == 0)
+        if (tid == 0 && a.counts)
             a.counts[blockIdx.x] = 0;
         return;
     }
@@ -292,7 +280,7 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
             bits[nwords] = 0;
     }
     __syncthreads();
-    const uint64_t root = isqrt64(s_last);
+    const uint64_t root = isqrt_u64(s_last);
     // Crossing off every prime up to the root costs about one reduction per
     // prime and segment; below a root of 2^25 (2 million primes) that is
     // cheaper than Miller-Rabin on the survivors, and the sieve alone decides
@@ -460,7 +448,7 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
         filled += all;
         __syncthreads();  // wsum is rewritten next pass
     }
-    if (tid == 0)
+    if (tid == 0 && a.counts)
         a.counts[blockIdx.x] = filled;
 }
 

@@ -73,16 +73,6 @@ __device__ __forceinline__ uint64_t inv64_of(uint32_t d)
     return y;
 }
 
-// floor(sqrt(n)) for n < 2^40 (the double estimate is within one).
-__device__ __forceinline__ uint32_t isqrt40(uint64_t n)
-{
-    uint32_t r = (uint32_t)sqrt((double)n);
-    if ((uint64_t)r * r > n)
-        --r;
-    else if ((uint64_t)(r + 1) * (r + 1) <= n)
-        ++r;
-    return r;
-}
 
 __device__ __forceinline__ void wave_sync_lds()
 {
@@ -129,7 +119,7 @@ __global__ void __launch_bounds__(WHEEL_BLOCK) wheel_kernel(Survivor *__restrict
             mine = e.n < bound;
         }
         const uint32_t nl = (uint32_t)e.n, nh = (uint32_t)(e.n >> 32);
-        const uint32_t root = mine ? isqrt40(e.n) : 0u;
+        const uint32_t root = mine ? (uint32_t)isqrt_u64(e.n) : 0u;
         uint32_t hmin = ~0u;  // smallest high word of n * d^-1 so far
         // chunks of 64 divisors (lane j: divisor k0 + j of 3, 5, 7, 11, ...)
         // while some undecided lane's root lies beyond the last one tested

@@ -126,3 +126,34 @@ def test_batched_invalid(isp):
     assert L.isprime_u64_batched(ctypes.cast(z, ctypes.c_void_p), ctypes.cast(z, ctypes.c_void_p),
                                  ctypes.cast(five, ctypes.c_void_p), 1, None) == isp.ISP_EINVAL
     assert L.isprime_u64_batched(None, None, None, 0, None) == isp.ISP_OK
+
+
+def test_offsets_form_against_oracle(isp):
+    """The arrays of C4 laid end to end in one buffer with an offsets table
+    (on the device, then on the host): equal to the oracle; bytes outside
+    [offsets[0], offsets[-1]) untouched; decreasing offsets refused."""
+    arrs = [a for a, _ in W.c4_batched(num_arrays=512)]
+    flat = np.concatenate(arrs)
+    exp, _ = oracle.isprime_array(flat, nthreads=NTHREADS, use_table=False)
+    offs = np.concatenate([[0], np.cumsum([a.size for a in arrs])]).astype(np.int64)
+    dev = to_dev(np.concatenate([flat, np.array([2, 3], dtype=np.uint64)]))  # 2 extra at the end
+    for where in ("cuda", "cpu"):
+        out = torch.full((dev.numel(),), 7, dtype=torch.uint8, device="cuda")
+        isp.isprime_batched_offsets(dev, torch.from_numpy(offs).to(where), out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        assert np.array_equal(got[:flat.size], exp), where
+        assert got[flat.size:].tolist() == [7, 7]  # outside the arrays: not written
+    # a sub-range: arrays 10 .. 20 only
+    out = torch.full((dev.numel(),), 7, dtype=torch.uint8, device="cuda")
+    sub = torch.from_numpy(offs[10:21].copy()).cuda()
+    isp.isprime_batched_offsets(dev, sub, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    lo, hi = offs[10], offs[20]
+    assert np.array_equal(got[lo:hi], exp[lo:hi])
+    assert (got[:lo] == 7).all() and (got[hi:] == 7).all()
+    bad = torch.tensor([0, 5, 3], dtype=torch.int64, device="cuda")
+    with pytest.raises(isp.IsprimeError) as e:
+        isp.isprime_batched_offsets(dev, bad, out)
+    assert e.value.status == isp.ISP_EINVAL
