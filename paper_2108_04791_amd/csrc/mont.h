@@ -23,16 +23,19 @@
 
 namespace isp {
 
-// n^-1 mod 2^64 for odd n by Newton-Hensel lifting x <- x (2 - n x); the seed
-// (3n) xor 2 is correct to 5 bits, and each step doubles the correct bits.
+// n^-1 mod 2^64 for odd n by Newton-Hensel lifting x <- x (2 - n x): the
+// seed (3n) xor 2 is correct to 5 bits and each step doubles the correct
+// bits.  The first three steps (to 10, 20, 40 bits) need only n mod 2^32 and
+// run on 32-bit words; one 64-bit step finishes.
 __device__ __forceinline__ uint64_t inv64(uint64_t n)
 {
-    uint64_t x = (3 * n) ^ 2;  // 5 bits
-    x *= 2 - n * x;            // 10
-    x *= 2 - n * x;            // 20
-    x *= 2 - n * x;            // 40
-    x *= 2 - n * x;            // 80
-    return x;
+    const uint32_t n0 = (uint32_t)n;
+    uint32_t y = (3u * n0) ^ 2u;  // 5 bits
+    y *= 2u - n0 * y;             // 10
+    y *= 2u - n0 * y;             // 20
+    y *= 2u - n0 * y;             // 40 >= 32
+    const uint64_t x = y;
+    return x * (2 - n * x);       // 64
 }
 
 __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b)
@@ -155,12 +158,23 @@ __device__ __forceinline__ uint64_t montsqr63(uint64_t a, uint64_t n, uint64_t n
     return hi < h ? t + n : t;
 }
 
-// The square for n < 2^62 and a < 2n, in (0, 2n) like montmul_lazy.
+// The square in (0, 2n) like montmul_lazy, for a < 2^63 with a*a < n 2^64
+// (so that hi < n): a < 2n with n < 2^62, or a < 4n with n < 2^60.
 __device__ __forceinline__ uint64_t montsqr63_lazy(uint64_t a, uint64_t n, uint64_t ninv)
 {
     uint64_t hi, h;
     redc_sqr_parts(a, n, ninv, hi, h);
     return (hi + n) - h;
+}
+
+// (x << b) + a modulo 2^64 for a per-lane shift b in {0, 1}, as the single
+// gfx950 instruction v_lshl_add_u64 (its shift operand takes 0 to 4).  Pure
+// VALU arithmetic, no memory access.
+__device__ __forceinline__ uint64_t shl_add(uint64_t x, uint32_t b, uint64_t a)
+{
+    uint64_t r;
+    asm("v_lshl_add_u64 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(b), "v"(a));
+    return r;
 }
 
 // 2x mod n for x < n (ModAdd of x and x: the carry out of x + x is kept).
@@ -186,6 +200,22 @@ __device__ __forceinline__ uint64_t r_mod_n(uint64_t n, int L)
     for (int k = L - 1; k < 64; ++k)
         x = dbl_mod(x, n);
     return x;
+}
+
+// 2^64 mod n for odd n >= 2^32 with bit length L, in a loop whose count is
+// the same on every lane: Lmin (wavefront-uniform, <= L) is the smallest bit
+// length in the wavefront.  A lane with n < 2^63 starts from 2^(Lmin - 1)
+// <= 2^(L - 1) < n and doubles 65 - Lmin times; for x < n < 2^63, 2x has no
+// carry and 2x >= n exactly when x >= (n + 1) / 2, so each doubling is one
+// compare, a select and one shift-and-add.  For n >= 2^63, 2^64 mod n is
+// 2^64 - n.
+__device__ __forceinline__ uint64_t r_mod_n_uniform(uint64_t n, int L, int Lmin)
+{
+    const uint64_t half = (n >> 1) + 1, neg_n = 0 - n;
+    uint64_t x = (uint64_t)1 << (Lmin - 1);
+    for (int k = Lmin - 1; k < 64; ++k)
+        x = shl_add(x, 1, x >= half ? neg_n : 0);
+    return L == 64 ? neg_n : x;
 }
 
 __device__ __forceinline__ MontCtx make_ctx(uint64_t n, int L)

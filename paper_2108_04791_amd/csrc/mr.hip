@@ -49,25 +49,23 @@ namespace isp {
 
 namespace {
 
-// (x << b) + a modulo 2^64 for a per-lane shift b in {0, 1}, as the single
-// gfx950 instruction v_lshl_add_u64 (its shift operand takes 0 to 4).  Pure
-// VALU arithmetic, no memory access.
-__device__ __forceinline__ uint64_t shl_add(uint64_t x, uint32_t b, uint64_t a)
-{
-    uint64_t r;
-    asm("v_lshl_add_u64 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(b), "v"(a));
-    return r;
-}
-
-// Largest value of v over the wavefront, as a wavefront-uniform (scalar)
-// value; every lane must be active.
+// Largest value of v over the wavefront for 0 <= v < 2^BITS, as a
+// wavefront-uniform (scalar) value, built from the top bit down with one
+// ballot per bit; every lane must be active.
+template <int BITS>
 __device__ __forceinline__ int wave_max(int v)
 {
+    int acc = 0;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v = max(v, __shfl_xor(v, o, 64));
-    return __builtin_amdgcn_readfirstlane(v);
+    for (int b = 1 << (BITS - 1); b > 0; b >>= 1)
+        if (__ballot(v >= acc + b) != 0)
+            acc += b;
+    return acc;
 }
+
+// Extremes of the bit lengths L in [33, 64] of a wavefront's values.
+__device__ __forceinline__ int wave_max_len(int L) { return 33 + wave_max<5>(L - 33); }
+__device__ __forceinline__ int wave_min_len(int L) { return 64 - wave_max<5>(64 - L); }
 
 // Strong probable-prime test to base 2 for odd n >= 2^32, n - 1 = 2^s d.
 // Called with all 64 lanes of the wavefront active.
@@ -82,16 +80,21 @@ __device__ __forceinline__ int wave_max(int v)
 // x = 1 and squares it through its leading zero bits, so its first set bit
 // makes x = 2 exactly where its own exponent starts.  The loop count is the
 // same on all lanes (a scalar loop), and only the last smax steps (smax: the
-// largest s in the wavefront) compare.
+// largest s in the wavefront) compare.  The bit of each step is read from
+// the 32-bit half of n - 1 that holds it, one bit-field extract.
 //
-// SQ (wavefront-uniform): 0 when every n is below 2^62, 1 below 2^63, 2
-// otherwise.  Below 2^63 the squares take the carry-free form (montsqr63).
+// SQ (wavefront-uniform) by the largest n of the wavefront: 0 below 2^60,
+// 1 below 2^62, 2 below 2^63, 3 otherwise.  Below 2^63 the squares take the
+// carry-free form (montsqr63).  Below 2^60 the steps before the comparisons
+// keep x in (0, 4n) (lazy squares, whose input may be below 4n there, and a
+// plain shift for the doubling); below 2^62 they keep it in [0, 2n)
+// (reduced squares of inputs below 2n, and the shift).
 template <int SQ>
 __device__ __forceinline__ bool sprp_base2_run(uint64_t n, const MontCtx &c, uint64_t e, int s,
                                                int L, int Lmax, int smax)
 {
     auto sqr = [&](uint64_t y) {
-        return SQ == 2 ? montsqr(y, n, c.ninv) : montsqr63(y, n, c.ninv);
+        return SQ == 3 ? montsqr(y, n, c.ninv) : montsqr63(y, n, c.ninv);
     };
     // bit Lmax - 1: the leading one of the longest lanes (x = 2), a leading
     // zero of the others (x = 1)
@@ -106,32 +109,25 @@ __device__ __forceinline__ bool sprp_base2_run(uint64_t n, const MontCtx &c, uin
         const uint64_t sub = (bit != 0 && x >= half) ? neg_n : 0;
         x = shl_add(x, bit, sub);
     };
-    // bits Lmax - 2 .. smax + 1 from the top of `rest` (bit t of n - 1 at
-    // t + 65 - Lmax)
-    uint64_t rest = e << (65 - Lmax);
-    if constexpr (SQ == 0) {
-        // n < 2^62: x may stay in [0, 2n) between squarings (a product of
-        // two such values is below 4 n^2 < n 2^64, which the Montgomery
-        // product accepts, and its result is reduced), so the doubling is a
-        // plain shift
-        for (int t = Lmax - 2; t > smax; --t) {
-            const uint32_t bit = hi32(rest) >> 31;
-            rest <<= 1;
-            x = sqr(x) << bit;
+    // steps for bits hi_t down to lo_t of n - 1, held in `word` at t - base
+    auto steps = [&](uint32_t word, int base, int hi_t, int lo_t) {
+        for (int t = hi_t; t >= lo_t; --t) {
+            const uint32_t bit = __builtin_amdgcn_ubfe(word, (uint32_t)(t - base), 1u);
+            if constexpr (SQ == 0)
+                x = montsqr63_lazy(x, n, c.ninv) << bit;
+            else if constexpr (SQ == 1)
+                x = montsqr63(x, n, c.ninv) << bit;
+            else
+                step(bit);
         }
-    } else {
-        for (int t = Lmax - 2; t > smax; --t) {
-            // the top bit as an opaque value, so the select below tests it
-            // rather than the old `rest` (which would keep a copy of it alive)
-            uint32_t bit;
-            asm("v_lshrrev_b32 %0, 31, %1" : "=v"(bit) : "v"(hi32(rest)));
-            rest <<= 1;
-            step(bit);
-        }
-    }
-    // bits min(smax, Lmax - 2) .. 1, comparing
+    };
+    // bits Lmax - 2 .. smax + 1, those above 31 first
+    const int top = Lmax - 2, low = smax + 1;
+    steps(hi32(e), 32, top, low > 32 ? low : 32);
+    steps(lo32(e), 0, top < 31 ? top : 31, low);
+    // bits min(smax, Lmax - 2) .. 1, comparing (the first square reduces x)
     bool pass = false;
-    for (int t = smax < Lmax - 2 ? smax : Lmax - 2; t >= 1; --t) {
+    for (int t = smax < top ? smax : top; t >= 1; --t) {
         step((uint32_t)(e >> t) & 1u);
         pass |= (t <= s && x == c.mone) || (t == s && x == c.one);
     }
@@ -142,15 +138,20 @@ __device__ __forceinline__ bool sprp_base2_run(uint64_t n, const MontCtx &c, uin
 __device__ __forceinline__ bool sprp_base2(uint64_t n, MontCtx &c)
 {
     const int L = 64 - __clzll(n);
-    c = make_ctx(n, L);
     const uint64_t e = n - 1;
-    const int s = __ffsll((long long)e) - 1;
-    const int Lmax = wave_max(L), smax = wave_max(s);
-    if (Lmax <= 62)
+    const int s = __ffsll((long long)e) - 1;  // 1 .. 63
+    const int Lmax = wave_max_len(L), smax = wave_max<6>(s);
+    c.n = n;
+    c.ninv = inv64(n);
+    c.one = r_mod_n_uniform(n, L, wave_min_len(L));
+    c.mone = n - c.one;
+    if (Lmax <= 60)
         return sprp_base2_run<0>(n, c, e, s, L, Lmax, smax);
-    if (Lmax == 63)
+    if (Lmax <= 62)
         return sprp_base2_run<1>(n, c, e, s, L, Lmax, smax);
-    return sprp_base2_run<2>(n, c, e, s, L, Lmax, smax);
+    if (Lmax == 63)
+        return sprp_base2_run<2>(n, c, e, s, L, Lmax, smax);
+    return sprp_base2_run<3>(n, c, e, s, L, Lmax, smax);
 }
 
 // Strong test for one base (am: its Montgomery form) with n - 1 = 2^s d.
@@ -185,7 +186,7 @@ __device__ __forceinline__ bool sprp_window(uint64_t am, uint64_t d, int s, cons
     // reads window value 0 (table entry 1) until its own top window, so every
     // lane runs the same scalar loop (all lanes must be active)
     const int Ld = 64 - __clzll(d);
-    const int nwin = wave_max((Ld + W - 1) / W);
+    const int nwin = wave_max<6>((Ld + W - 1) / W);  // <= 63
     int pos = (nwin - 1) * W;  // at most 63 - W: d < 2^63
     uint64_t x = tbl[((unsigned)(d >> pos) & (TS - 1)) * stride + col];
     for (pos -= W; pos >= 0; pos -= W) {
@@ -220,7 +221,7 @@ __device__ __forceinline__ bool sprp_one_base(uint64_t n, const MontPrep &pr, ui
     const uint64_t e = n - 1;
     const int s = __ffsll((long long)e) - 1;
     const uint64_t am = to_mont(a, pr.r2, c);
-    const int Lmax = wave_max(64 - __clzll(n));
+    const int Lmax = wave_max_len(64 - __clzll(n));
     if (Lmax <= 62)
         return sprp_window<W, 0>(am, e >> s, s, c, tbl);
     if (Lmax == 63)
