@@ -11,8 +11,10 @@
 // Every output byte is written here with coalesced stores (survivors get 0);
 // the Miller-Rabin kernels later store a 1 for each prime survivor.
 //
-// Divisibility without division (Granlund and Montgomery, PLDI 1994):
-// p | n iff n * p^-1 mod 2^64 <= floor((2^64 - 1) / p), for odd p.
+// Divisibility without division: a residue of n modulo a product of a few
+// consecutive filter primes from two dot-product instructions, then per
+// prime p: p | s iff s * p^-1 mod 2^32 <= floor((2^32 - 1) / p) (Granlund
+// and Montgomery, PLDI 1994); see divisible_range.
 //
 // Work split without global atomics: the grid is a fixed number of
 // workgroups; workgroup g owns the contiguous element range
@@ -38,8 +40,8 @@ namespace {
 
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(8)));
 
-// Compile-time table of the first odd primes with their inverses modulo 2^64
-// and the bound floor((2^64 - 1) / p), so the unrolled filter below uses
+// Compile-time table of the first odd primes with their inverses modulo 2^32
+// and the bound floor((2^32 - 1) / p), so the unrolled filter below uses
 // immediate constants and issues no memory load.
 constexpr int DENSE_TO = 64;  // the second stage ends at the 64th odd prime (313)
 constexpr int FILTER2_BLOCK = 256;
@@ -61,23 +63,80 @@ constexpr uint64_t ce_inv64(uint64_t p)
 }
 
 struct FilterTable {
-    uint64_t inv[MAX_FILTER_PRIMES];
-    uint64_t lim[MAX_FILTER_PRIMES];
-    constexpr FilterTable() : inv(), lim()
+    uint64_t prime[MAX_FILTER_PRIMES];
+    uint32_t inv[MAX_FILTER_PRIMES];  // p^-1 mod 2^32
+    uint32_t lim[MAX_FILTER_PRIMES];  // floor((2^32 - 1) / p)
+    constexpr FilterTable() : prime(), inv(), lim()
     {
         int k = 0;
         for (uint64_t p = 3; k < MAX_FILTER_PRIMES; p += 2) {
             if (ce_is_prime(p)) {
-                inv[k] = ce_inv64(p);
-                lim[k] = ~(uint64_t)0 / p;
+                prime[k] = p;
+                inv[k] = (uint32_t)ce_inv64(p);
+                lim[k] = 0xffffffffu / (uint32_t)p;
                 ++k;
             }
         }
     }
+    // The residue groups: consecutive primes k .. end - 1 (end <= k1) whose
+    // product M stays at most RES_M_MAX.
+    constexpr int group_end(int k, int k1) const
+    {
+        uint64_t m = prime[k];
+        int e = k + 1;
+        while (e < k1 && m * prime[e] <= RES_M_MAX)
+            m *= prime[e++];
+        return e;
+    }
+    constexpr uint32_t product(int k, int e) const
+    {
+        uint64_t m = 1;
+        for (int i = k; i < e; ++i)
+            m *= prime[i];
+        return (uint32_t)m;
+    }
+    static constexpr uint64_t RES_M_MAX = 16383;
 };
 constexpr FilterTable FILTER{};
-static_assert(FILTER.inv[0] * 3 == 1 && FILTER.lim[0] == 6148914691236517205ull, "p = 3");
-static_assert(FILTER.inv[MAX_FILTER_PRIMES - 1] * 727 == 1, "the 128th odd prime is 727");
+static_assert(FILTER.inv[0] * 3u == 1u && FILTER.lim[0] == 1431655765u, "p = 3");
+static_assert(FILTER.prime[MAX_FILTER_PRIMES - 1] == 727, "the 128th odd prime is 727");
+static_assert(FILTER.group_end(0, 64) == 5 && FILTER.product(0, 5) == 15015, "3 5 7 11 13");
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// Whether one of the odd primes K .. K1 - 1 divides n = h 2^32 + l, one
+// residue group at a time.  With n's 16-bit chunks c_0 .. c_3 and a group's
+// product M <= 16383, s = sum c_i (2^(16 i) mod M) is congruent to n modulo
+// M, hence modulo each prime of the group, and s <= 4 (2^16 - 1) 16382 <
+// 2^32: two v_dot2_u32_u16 form it.  Each prime p of the group then divides
+// n iff it divides s, i.e. iff s p^-1 mod 2^32 <= floor((2^32 - 1) / p)
+// (Granlund and Montgomery, PLDI 1994): one multiply and one compare.
+template <int K, int K1>
+__device__ __forceinline__ bool divisible_range(uint32_t l, uint32_t h)
+{
+    if constexpr (K >= K1) {
+        return false;
+    } else {
+        constexpr int E = FILTER.group_end(K, K1);
+        constexpr uint32_t M = FILTER.product(K, E);
+        constexpr uint32_t W1 = (uint32_t)((1ull << 16) % M), W2 = (uint32_t)((1ull << 32) % M),
+                           W3 = (uint32_t)((1ull << 48) % M);
+        const uint32_t s0 = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, l),
+                                                   u16x2{(unsigned short)1, (unsigned short)W1}, 0u,
+                                                   false);
+        const uint32_t s = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, h),
+                                                  u16x2{(unsigned short)W2, (unsigned short)W3}, s0,
+                                                  false);
+        bool d = false;
+#pragma unroll
+        for (int k = K; k < E; ++k)
+            d |= s * FILTER.inv[k] <= FILTER.lim[k];
+        return d | divisible_range<E, K1>(l, h);
+    }
+}
+
+__device__ __forceinline__ uint32_t lo_word(uint64_t v) { return (uint32_t)v; }
+__device__ __forceinline__ uint32_t hi_word(uint64_t v) { return (uint32_t)(v >> 32); }
 
 // 0 or 1: decided; 2: survivor of the filter (NF odd primes).
 template <int NF>
@@ -89,11 +148,7 @@ __device__ __forceinline__ int classify_one(uint64_t v, const uint32_t *__restri
         return 0;
     if (v < TABLE_BOUND)
         return (int)((table[v >> 6] >> ((v >> 1) & 31)) & 1u);
-    bool divisible = false;
-#pragma unroll
-    for (int k = 0; k < NF; ++k)
-        divisible |= v * FILTER.inv[k] <= FILTER.lim[k];
-    return divisible ? 0 : 2;
+    return divisible_range<0, NF>(lo_word(v), hi_word(v)) ? 0 : 2;
 }
 
 // The same decision split in two, so that a thread issues the table reads
@@ -126,11 +181,7 @@ __device__ __forceinline__ int classify_with(uint64_t v, uint32_t word, int bit)
         return 0;
     if (v < TABLE_BOUND)
         return bit >= 0 ? (int)((word >> bit) & 1u) : (v <= 7 ? 1 : 0);
-    bool divisible = false;
-#pragma unroll
-    for (int k = 0; k < NF; ++k)
-        divisible |= v * FILTER.inv[k] <= FILTER.lim[k];
-    return divisible ? 0 : 2;
+    return divisible_range<0, NF>(lo_word(v), hi_word(v)) ? 0 : 2;
 }
 
 struct ClassifyShared {
@@ -412,11 +463,7 @@ constexpr uint32_t F2_WINDOW = FILTER2_BLOCK * F2_PER_THREAD;
 template <int NF>
 __device__ __forceinline__ bool filter2_keep(uint64_t n)
 {
-    bool divisible = false;
-#pragma unroll
-    for (int k = NF; k < DENSE_TO; ++k)
-        divisible |= n * FILTER.inv[k] <= FILTER.lim[k];
-    return !divisible;
+    return !divisible_range<NF, DENSE_TO>(lo_word(n), hi_word(n));
 }
 
 template <int NF, bool SORT>
