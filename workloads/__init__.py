@@ -134,8 +134,9 @@ def odd_band(n: int, bits: int, seed: int = SEED_BAND, start: int = 0) -> np.nda
 
 
 def lookup32(n: int = 1 << 26, seed: int = SEED_LOOKUP, start: int = 0) -> np.ndarray:
-    """n values uniform in [0, 2^32): every odd one is answered by the table
-    (the lookup path alone, over the whole 256 MiB table)."""
+    """n values uniform in [0, 2^32): the lookup path alone (every odd value
+    is decided below the table bound; those coprime to 210 by one random
+    read of the wheel table, spread over the whole of it)."""
     idx = np.arange(start, start + n, dtype=np.uint64)
     return element_draws(seed, idx, 0) >> np.uint64(32)
 
