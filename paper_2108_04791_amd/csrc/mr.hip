@@ -13,9 +13,10 @@
 // bits of n - 1 from the top in a loop whose count is the same on every lane
 // of a wavefront (L - 2 steps for the longest n in it); the multiply by 2 is
 // a modular doubling (the ModAdd of section 2.2) selected without a branch.
-// About 4 in 5 survivors of random inputs fail here.  Passers go to the
-// workgroup's own region with out = 1, and the workgroup then computes each
-// passer's Montgomery constants once for phase 2.
+// About 4 in 5 survivors of random inputs fail here (their output byte keeps
+// the 0 that classify wrote).  Passers go to the workgroup's own region, and
+// the workgroup then computes each passer's Montgomery constants once for
+// phase 2.
 //
 // Phase 2 (base-2 passers): in two rounds per workgroup over its slice of
 // the candidates.  Round 1 tests base 325, one candidate per lane, and
@@ -23,8 +24,11 @@
 // independent tasks per candidate, laid out densely over the lanes.  A
 // composite that passes base 2 (a strong pseudoprime, e.g. a Carmichael
 // number) almost always fails 325, so it costs one base instead of six.  A
-// lane whose base fails stores out = 0, so the verdict is the AND of the
-// bases without any cross-lane step (several lanes may store the same 0).
+// candidate that passes 325 stores out = 1 in round 1, and a lane whose base
+// fails in round 2 stores out = 0 after the workgroup barrier between the
+// rounds, so the verdict is the AND of the bases without any cross-lane step
+// (several lanes may store the same 0).  Only about as many bytes as there
+// are primes are written, scattered, by this phase, and none by phase 1.
 // a^d uses a fixed window of W bits with the lane's table of
 // a^0..a^(2^W - 1) in LDS, so all lanes multiply at the same steps; then up
 // to s - 1 squarings look for -1.
@@ -509,7 +513,6 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase1_kernel(MrArgs a)
                     prep[pos].ninv = c.ninv;
                     prep[pos].one = c.one;
                 }
-                *sv.out = 1;  // provisional: a failing later base clears it
             }
         }
     }
@@ -637,8 +640,8 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase2_kernel(MrArgs a)
         const Survivor sv = a.cand[slot];
         const MontPrep pr = a.prep[slot];
         const bool ok = sprp_one_base<W>(sv.n, pr, BASES[0], tbl);
-        if (!ok && real)
-            *sv.out = 0;  // composite; the base-2 round had written 1
+        if (ok && real)
+            *sv.out = 1;  // provisional: a failing base of round 2 clears it
         const uint64_t m = __ballot(ok && real);
         if (m != 0) {
             uint32_t at = 0;
@@ -673,7 +676,7 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) mr_phase2_kernel(MrArgs a)
 }
 
 // Remaining test of every base-2 passer by the strong Lucas test (one task
-// per candidate; see strong_lucas).  A composite stores out = 0.
+// per candidate; see strong_lucas).  A prime stores out = 1.
 template <int W>
 __global__ void __launch_bounds__(MR_MAX_BLOCK) lucas_kernel(MrArgs a)
 {
@@ -721,8 +724,8 @@ __global__ void __launch_bounds__(MR_MAX_BLOCK) lucas_kernel(MrArgs a)
             if (need)
                 v = w ? 1 : 0;
         }
-        if (!v && real)
-            *sv.out = 0;
+        if (v && real)
+            *sv.out = 1;
     }
 }
 
