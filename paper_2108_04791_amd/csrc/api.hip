@@ -136,6 +136,8 @@ void free_range_ws(RangeWs &rw)
         (void)hipFree(rw.counts);
     if (rw.hits)
         (void)hipFree(rw.hits);
+    if (rw.stream)
+        (void)hipFree(rw.stream);
     rw = RangeWs();
 }
 
@@ -156,6 +158,8 @@ int ensure_range_ws(RangeWs &rw, uint64_t count_cap, uint64_t hit_cap, hipStream
     hipError_t e = hipMalloc(&rw.counts, count_cap * sizeof(uint32_t));
     if (e == hipSuccess)
         e = hipMalloc(&rw.hits, hit_cap * sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMalloc(&rw.stream, hit_cap * sizeof(uint32_t));
     if (e != hipSuccess) {
         free_range_ws(rw);
         return fail(e);
@@ -555,10 +559,8 @@ RangePlan plan_range_piece(uint64_t first, uint64_t piece)
         const uint64_t gmax = p.grid > 512 || words < ((uint64_t)1 << 20) ? MAX_BUCKET_GROUPS / 2
                                                                           : MAX_BUCKET_GROUPS;
         p.groups = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(gmax, words / 1024));
-        // counts (+ total) and the scan's tile sums (+ total)
-        const uint64_t n = (uint64_t)p.grid * p.groups;
-        p.count_words = n + 1 + n / 8192 + 2;
         p.hit_words = bucket_hit_bound(piece, p.root);
+        p.count_words = bucket_layout(p.grid, p.groups, p.hit_words).count_words;
         p.complete = true;
         return p;
     }
@@ -900,7 +902,8 @@ int isprime_range_u64(uint64_t lo, uint8_t *out, size_t len, void *stream)
             st = ensure_range_ws(sw->rws, pl.count_words, pl.hit_words, s);
             if (st != ISP_OK)
                 break;
-            e = launch_range_buckets(lo + off, piece, pl.root, pl.groups, ds, sw->rws, s);
+            e = launch_range_buckets(lo + off, piece, pl.root, pl.groups, pl.hit_words, ds,
+                                     sw->rws, s);
             if (e == hipSuccess)
                 e = launch_range_sieve(lo + off, out + off, piece, pl.grid, RANGE_SEG, pl.groups,
                                        ds, none, sw->rws, s);
@@ -1126,7 +1129,7 @@ size_t isp_range_workspace_bytes(uint64_t lo, size_t len)
         const uint64_t piece = std::min<uint64_t>(RANGE_PIECE, len - off);
         const RangePlan p = plan_range_piece(lo + off, piece);
         if (p.bucket)
-            buckets = std::max<size_t>(buckets, (p.count_words + p.hit_words) * sizeof(uint32_t));
+            buckets = std::max<size_t>(buckets, (p.count_words + 2 * p.hit_words) * sizeof(uint32_t));
         else if (!p.complete)
             mr = std::max(mr, isp_workspace_bytes(piece));
     }

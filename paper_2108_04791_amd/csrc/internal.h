@@ -208,6 +208,7 @@ struct DeviceState {
 struct RangeWs {
     uint32_t *counts = nullptr;  // count_cap words
     uint32_t *hits = nullptr;    // hit_cap words
+    uint32_t *stream = nullptr;  // hit_cap words: the fill pass's output, sorted into hits
     uint64_t count_cap = 0, hit_cap = 0;
 };
 
@@ -245,8 +246,20 @@ hipError_t launch_lucas(const MrArgs &a, int cus, int per_cu, unsigned max_grid,
 hipError_t launch_range_primes(DeviceState &ds, hipStream_t s);
 hipError_t launch_range_table(uint64_t lo, uint8_t *out, uint64_t len, const DeviceState &ds,
                               hipStream_t s);
+// Bucket mode's sort tile, per-tile launch size and count words for nseg
+// segments, `groups` workgroups and room for hit_cap hits (ok false: no
+// tile fits the scan).
+struct BucketLayout {
+    uint32_t tile = 0, max_tiles = 0;
+    uint64_t count_words = 0;
+    bool ok = false;
+};
+BucketLayout bucket_layout(uint32_t nseg, unsigned groups, uint64_t hit_cap);
+// hit_bound: an upper bound on the piece's hits (at most rw.hit_cap), from
+// which the layout is sized.
 hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsigned groups,
-                                const DeviceState &ds, const RangeWs &rw, hipStream_t s);
+                                uint64_t hit_bound, const DeviceState &ds, const RangeWs &rw,
+                                hipStream_t s);
 // Without buckets, a segment whose square root is below 2^complete_log2
 // (partial_log2 .. RANGE_PRIME_LOG2) is decided by the sieve alone; the others
 // are sieved by the primes below 2^partial_log2 (17 .. RANGE_PARTIAL_LOG2)

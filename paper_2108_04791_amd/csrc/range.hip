@@ -460,12 +460,33 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
 // bucket sieve of segmented sieving): the odd primes in (BUCKET_SMALL,
 // sqrt(end)] are read from the device table, each prime's odd multiples at
 // or above max(lo, p^2) are enumerated once over the whole piece, and each
-// becomes a hit (its bit index) in the bucket of its segment.  Two passes
-// over the same primes by `groups` workgroups: count the hits per (segment,
-// group) in LDS, then after an exclusive scan write them at their places,
-// so no global atomic is needed.  The segment kernel then applies its
-// bucket.  With every prime up to the square root crossed off, the
-// segments are complete at any magnitude below 2^64.
+// becomes a hit (its bit index) in the bucket of its segment.  `groups`
+// workgroups share the primes; no global atomic is needed:
+//   0. split (one workgroup): each group's table words;
+//   1. bound: an upper bound on each group's hits, floor((len - 1) / 2p) + 1
+//      per prime p (at most that many odd multiples of p lie in len
+//      consecutive numbers): a popcount of the table words, plus the
+//      quotient for the primes below len / 2;
+//   2. plan (one workgroup): each group's stretch of the stream (its bound)
+//      and its number of sort tiles;
+//   3. fill: each group enumerates its hits and appends them, in the order
+//      found, to its stretch of the stream (one contiguous store per
+//      wavefront step), and records how many it found;
+//   4. histogram: per tile of a group's stretch, its hits per segment;
+//   5. an exclusive scan of those counts, laid out (group, segment, tile),
+//      which is exactly the order of the buckets and of the tiles within a
+//      bucket: each count's scanned value is where that tile's hits of that
+//      segment go;
+//   6. starts: the first hit of each (group, segment);
+//   7. scatter: each tile's hits, put in segment order in LDS, written to
+//      their places, consecutive threads at consecutive places.
+// Writing each hit straight to its bucket from the enumeration would keep
+// groups x segments partly written 128-byte lines open at once (32 MB for
+// 512 groups and 512 segments, the whole L2): measured, each line reached
+// HBM about 2.5 times over and the pass took twice the enumeration.  The
+// segment kernel then applies bucket (group, segment) for every group.
+// With every prime up to the square root crossed off, the segments are
+// complete at any magnitude below 2^64.
 
 struct BucketArgs {
     uint64_t lo, len;        // the piece
@@ -473,10 +494,29 @@ struct BucketArgs {
     uint64_t root;
     const uint32_t *table;
     uint32_t nseg;           // segments of RANGE_SEG numbers
-    uint32_t *counts;        // [groups * nseg + 1], group-major: (group, g)
-    uint32_t *hits;
+    uint32_t groups;         // workgroups of the count and fill passes
+    uint32_t tile;           // hits per sort tile (a multiple of BUCKET_SORT_SUB)
+    uint32_t max_tiles;      // workgroups of the per-tile kernels (at least the tiles)
+    uint32_t bound_per;      // table words per thread of the bound pass
+    uint32_t *wsplit;        // [groups + 1]: each group's first table word
+    uint32_t *totals;        // [groups]: bound on the hits of each group
+    uint32_t *filled;        // [groups]: hits each group found
+    uint32_t *sbase;         // [groups + 1]: each group's first place in the stream
+    uint32_t *tprefix;       // [groups + 1]: each group's first tile
+    uint32_t *tcounts;       // [nseg * max_tiles + 1]: hits per (group, segment, tile),
+                             // scanned in place
+    uint32_t *hs;            // [groups * nseg + 1]: the first hit of (group, segment)
+    uint32_t *hits;          // hit_cap entries: bit indices within their segment
+    uint32_t *stream;        // hit_cap entries: segment << HIT_BITS | bit index
     uint64_t hit_cap;
 };
+
+// A hit in the stream: the segment (at most MAX_BUCKET_SEGS = 2^11) above
+// the bit index (below 2^18).
+constexpr int HIT_BITS = RANGE_SEG_LOG2 - 1;
+static_assert(MAX_BUCKET_SEGS <= (1 << (32 - HIT_BITS)), "segment fits above the bit index");
+// Hits per LDS round of the scatter kernel (1024 threads x 4).
+constexpr uint32_t BUCKET_SORT_SUB = 4096;
 
 // lo mod p for p < 2^32 from a double-precision quotient estimate (error
 // below one unit: lo < 2^64 is rounded to 53 bits and the quotient is below
@@ -521,10 +561,11 @@ __device__ __forceinline__ double bucket_cost(double x, double len)
     return 24.0 * x / lx + 4.0 * 0.5 * len * log(lx);
 }
 
-// The prime bound where the cumulative cost reaches `target` (bisection).
+// The prime bound where the cumulative cost reaches `target` (bisection,
+// down to below one number over any interval up to 2^32).
 __device__ double bucket_split(double target, double lo, double hi, double len)
 {
-    for (int it = 0; it < 80; ++it) {
+    for (int it = 0; it < 32; ++it) {
         const double mid = 0.5 * (lo + hi);
         if (bucket_cost(mid, len) < target)
             lo = mid;
@@ -541,15 +582,12 @@ constexpr int BUCKET_THREADS = 1024;
 // y = 4096; a chunk that still had more would take the per-lane path.
 constexpr uint32_t BUCKET_PBUF = 1024;
 
-// Every odd multiple of p in the piece, each counted in (FILL: written to)
-// the bucket of its segment.  The lanes of a wavefront hold consecutive
-// primes, whose multiples march through the segments together; each lane
-// starts at its own share (lane / 64) of its K multiples and wraps around,
-// so at each step the lanes touch different segments instead of queueing on
-// the same LDS counter.
-template <bool FILL>
+// Each odd multiple of p in the piece appended to the group's stream: the
+// lanes with a hit at a step take consecutive places in the stream (one LDS
+// atomic by the first of them), so each step is one contiguous store of the
+// wavefront.
 __device__ __forceinline__ void bucket_hits(const BucketArgs &a, uint32_t p, uint32_t lane,
-                                            uint32_t *cnt)
+                                            uint32_t *fill, uint64_t gbase, uint64_t gend)
 {
     const uint64_t first = bucket_first(a, p);
     if (first >= a.len)
@@ -561,59 +599,162 @@ __device__ __forceinline__ void bucket_hits(const BucketArgs &a, uint32_t p, uin
     uint32_t K = 1;
     if (step <= span)
         K = (uint32_t)span / (uint32_t)step + 1u;
-    uint64_t off = first + (uint64_t)((lane * K) >> 6) * step;
+    uint64_t off = first;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     for (uint32_t j = 0; j < K; ++j) {
-        const uint32_t g = (uint32_t)(off >> RANGE_SEG_LOG2);
-        if (FILL) {
-            const uint32_t at = atomicAdd(&cnt[g], 1u);
-            if (at < a.hit_cap)
-                a.hits[at] = (uint32_t)((off & (RANGE_SEG - 1)) >> 1);
-        } else {
-            atomicAdd(&cnt[g], 1u);
-        }
+        const uint64_t m = __ballot(1);  // the lanes still in the loop
+        const int leader = __ffsll((long long)m) - 1;
+        uint32_t base = 0;
+        if ((int)lane == leader)
+            base = atomicAdd(fill, (uint32_t)__popcll(m));
+        base = __builtin_amdgcn_readlane(base, leader);
+        const uint64_t at = gbase + base + (uint32_t)__popcll(m & lt);
+        if (at < gend)
+            a.stream[at] = (uint32_t)(off >> RANGE_SEG_LOG2) << HIT_BITS |
+                           (uint32_t)((off & (RANGE_SEG - 1)) >> 1);
         off += step;
-        if (off >= a.len)
-            off = first;
     }
 }
 
-// Count pass (FILL false): cnt[g] counts this group's hits in segment g and
-// goes to counts[group * nseg + g] (group-major, so that each group's hits
-// land in one contiguous stretch of `hits`).  Fill pass: cnt[g] starts at the
-// scanned offset of (group, g), so each atomic increment yields the hit's
-// place in `hits` directly.  The wavefront-scope fences below order LDS
-// accesses between the lanes of one wavefront (whose LDS operations complete
-// in order) without waiting for its global stores.
-template <bool FILL>
-__global__ void __launch_bounds__(BUCKET_THREADS) range_bucket_kernel(BucketArgs a)
+// The groups' table words: wsplit[g] = the first word of group g, so that
+// the groups take equal shares of the cost between BUCKET_SMALL and root
+// (a choice of work split only, which changes no output bit).  One thread
+// per boundary; launched with one workgroup of at least groups + 1 threads.
+__global__ void __launch_bounds__(1024) bucket_split_kernel(BucketArgs a)
 {
-    __shared__ uint32_t cnt[MAX_BUCKET_SEGS];
-    __shared__ uint32_t pbuf[BUCKET_THREADS / 64][BUCKET_PBUF];
-    __shared__ uint64_t wrange[2];
-    const uint32_t groups = gridDim.x;
-    for (uint32_t g = threadIdx.x; g < a.nseg; g += blockDim.x)
-        cnt[g] = FILL ? a.counts[(uint64_t)blockIdx.x * a.nseg + g] : 0u;
-    if (threadIdx.x == 0) {
-        // this group's words: equal shares of the cost between BUCKET_SMALL and root
+    const uint32_t g = threadIdx.x;
+    if (g > a.groups)
+        return;
+    if (g < a.groups)
+        a.totals[g] = 0;  // summed by the bound pass
+    uint64_t w = g == 0 ? a.w_begin : a.w_end;
+    if (g > 0 && g < a.groups) {
         const double len = (double)a.len, x0 = (double)BUCKET_SMALL, x1 = (double)a.root + 1.0;
         const double c0 = bucket_cost(x0, len), c1 = bucket_cost(x1, len);
-        uint64_t wb = a.w_begin, we = a.w_end;
-        if (blockIdx.x > 0)
-            wb = (uint64_t)bucket_split(c0 + (c1 - c0) * blockIdx.x / groups, x0, x1, len) >> 6;
-        if (blockIdx.x + 1 < groups)
-            we = (uint64_t)bucket_split(c0 + (c1 - c0) * (blockIdx.x + 1) / groups, x0, x1, len) >> 6;
-        wrange[0] = wb < a.w_begin ? a.w_begin : (wb > a.w_end ? a.w_end : wb);
-        wrange[1] = we < a.w_begin ? a.w_begin : (we > a.w_end ? a.w_end : we);
+        w = (uint64_t)bucket_split(c0 + (c1 - c0) * g / a.groups, x0, x1, len) >> 6;
+        w = w < a.w_begin ? a.w_begin : (w > a.w_end ? a.w_end : w);
     }
+    a.wsplit[g] = (uint32_t)w;
+}
+
+// Sum of v over a workgroup of up to 1024 threads (wsum: one word per
+// wavefront; ends with the workgroup's threads past a barrier).
+__device__ __forceinline__ uint32_t block_sum_1024(uint32_t v, uint32_t *wsum)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    if (lane == 0)
+        wsum[wave] = v;
     __syncthreads();
-    const uint64_t wb = wrange[0], we = wrange[1];
+    uint32_t t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+        t += wsum[w];
+    return t;
+}
+
+// Bound pass: totals[group] >= the group's hits (zeroed by the split
+// kernel).  Each prime p in (BUCKET_SMALL, root] adds floor((len - 1) / 2p)
+// + 1; a word whose 32 numbers all lie in (max(BUCKET_SMALL, (len - 1) / 2),
+// root] adds its popcount (each of its primes adds 1), any other word its
+// primes one by one.  The words are split evenly over the workgroups
+// (1024 x bound_per each, whatever the groups), and each workgroup adds
+// its sum over each group's words to that group's total.
+constexpr uint32_t BUCKET_BOUND_PER = 8;  // the most words per thread
+
+__device__ __forceinline__ uint32_t bucket_bound_word(const BucketArgs &a, uint32_t word,
+                                                      uint64_t w, uint64_t lo_p)
+{
+    const uint64_t v0 = 64 * w + 1, v1 = 64 * w + 63;  // the word's first and last number
+    if (v0 > lo_p && v1 <= a.root)
+        return (uint32_t)__popc(word);
+    uint32_t c = 0;
+    while (word) {
+        const int b = __ffs(word) - 1;
+        word &= word - 1;
+        const uint64_t p = v0 + 2 * (uint64_t)b;
+        if (p > BUCKET_SMALL && p <= a.root)  // len - 1 < 2^30: 32-bit quotients
+            c += (2 * p > a.len - 1 ? 0u : (uint32_t)(a.len - 1) / (uint32_t)(2 * p)) + 1u;
+    }
+    return c;
+}
+
+__global__ void __launch_bounds__(1024) bucket_bound_kernel(BucketArgs a)
+{
+    __shared__ uint32_t wsum[16];
+    const uint32_t per = a.bound_per;  // 1 .. BUCKET_BOUND_PER
+    const uint64_t w0 = a.w_begin + (uint64_t)blockIdx.x * 1024 * per;
+    if (w0 >= a.w_end)
+        return;  // (uniform)
+    const uint64_t w1 = min(w0 + 1024 * per, a.w_end);
+    const uint64_t pcut = (a.len - 1) / 2;  // primes above it have at most one hit
+    const uint64_t lo_p = pcut > BUCKET_SMALL ? pcut : BUCKET_SMALL;
+    // every word read before any is used
+    uint32_t words[BUCKET_BOUND_PER];
+#pragma unroll
+    for (uint32_t k = 0; k < BUCKET_BOUND_PER; ++k) {
+        const uint64_t w = w0 + k * 1024 + threadIdx.x;
+        words[k] = k < per && w < w1 ? a.table[w] : 0u;
+    }
+    uint32_t c[BUCKET_BOUND_PER];
+#pragma unroll
+    for (uint32_t k = 0; k < BUCKET_BOUND_PER; ++k)
+        c[k] = k < per ? bucket_bound_word(a, words[k], w0 + k * 1024 + threadIdx.x, lo_p) : 0u;
+    // the groups holding words w0 .. w1 - 1: q with wsplit[q] <= w < wsplit[q + 1]
+    auto group_of = [&](uint64_t w) {
+        uint32_t lo = 0, hi = a.groups;  // wsplit[lo] <= w < wsplit[hi] (w < w_end)
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a.wsplit[mid] <= w)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        return lo;
+    };
+    const uint32_t q0 = group_of(w0), q1 = group_of(w1 - 1);
+    for (uint32_t q = q0; q <= q1; ++q) {
+        const uint64_t lo = max(w0, (uint64_t)a.wsplit[q]);
+        const uint64_t hi = min(w1, (uint64_t)a.wsplit[q + 1]);
+        uint32_t sum = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < BUCKET_BOUND_PER; ++k) {
+            const uint64_t w = w0 + k * 1024 + threadIdx.x;
+            sum += k < per && w >= lo && w < hi ? c[k] : 0u;
+        }
+        sum = block_sum_1024(sum, wsum);
+        if (threadIdx.x == 0 && sum)
+            atomicAdd(&a.totals[q], sum);
+        __syncthreads();  // wsum is reused for the next group
+    }
+}
+
+// Fill pass: the group's hits appended to its stretch [sbase[group],
+// sbase[group + 1]) of the stream, their number to filled[group].  The
+// wavefront-scope fences below order LDS accesses between the lanes of one
+// wavefront (whose LDS operations complete in order) without waiting for
+// its global stores.
+__global__ void __launch_bounds__(BUCKET_THREADS) range_fill_kernel(BucketArgs a)
+{
+    __shared__ uint32_t pbuf[BUCKET_THREADS / 64][BUCKET_PBUF];
+    __shared__ uint32_t fill;
+    // (the clamps only keep writes inside the stream: the bounds sum to at
+    // most hit_cap)
+    const uint64_t gbase = min((uint64_t)a.sbase[blockIdx.x], a.hit_cap);
+    const uint64_t gend = min((uint64_t)a.sbase[blockIdx.x + 1], a.hit_cap);
+    if (threadIdx.x == 0)
+        fill = 0;
+    __syncthreads();
+    const uint64_t wb = a.wsplit[blockIdx.x];
+    const uint64_t we = max((uint64_t)a.wsplit[blockIdx.x + 1], wb);
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t nwaves = blockDim.x >> 6;
     uint32_t *buf = pbuf[wave];
     auto take = [&](uint32_t p) {
         if (p > BUCKET_SMALL && p <= a.root)
-            bucket_hits<FILL>(a, p, lane, cnt);
+            bucket_hits(a, p, lane, &fill, gbase, gend);
     };
     // the primes of a chunk of 64 words (w0 .. w0 + 63; lane l holds word
     // w0 + l) are listed densely in LDS (a wavefront prefix sum of the
@@ -659,10 +800,240 @@ __global__ void __launch_bounds__(BUCKET_THREADS) range_bucket_kernel(BucketArgs
         const uint64_t w = wb + 64 * ch + lane;
         chunk(wb + 64 * ch, w < we ? a.table[w] : 0u);
     }
-    if (!FILL) {
-        __syncthreads();
-        for (uint32_t g = threadIdx.x; g < a.nseg; g += blockDim.x)
-            a.counts[(uint64_t)blockIdx.x * a.nseg + g] = cnt[g];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        a.filled[blockIdx.x] = fill < gend - gbase ? fill : (uint32_t)(gend - gbase);
+}
+
+// One workgroup of 1024 threads: sbase = the exclusive scan of the groups'
+// totals (their stretches of the stream), tprefix = that of their tile
+// counts ceil(total / tile); both with the sum at [groups].
+__global__ void __launch_bounds__(1024) bucket_plan_kernel(BucketArgs a)
+{
+    __shared__ uint32_t wsum[2][16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t q = threadIdx.x;
+    const uint32_t h = q < a.groups ? a.totals[q] : 0u;
+    const uint32_t t = (h + a.tile - 1) / a.tile;
+    uint32_t ih = h, it = t;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t yh = __shfl_up(ih, o, 64), yt = __shfl_up(it, o, 64);
+        if (lane >= o) {
+            ih += yh;
+            it += yt;
+        }
+    }
+    if (lane == 63) {
+        wsum[0][wave] = ih;
+        wsum[1][wave] = it;
+    }
+    __syncthreads();
+    uint32_t bh = 0, bt = 0;
+    for (int w = 0; w < wave; ++w) {
+        bh += wsum[0][w];
+        bt += wsum[1][w];
+    }
+    if (q < a.groups) {
+        a.sbase[q] = bh + ih - h;
+        a.tprefix[q] = bt + it - t;
+    }
+    if (q == a.groups - 1) {
+        a.sbase[a.groups] = bh + ih;
+        a.tprefix[a.groups] = bt + it;
+    }
+}
+
+// The (group, tile) of per-tile workgroup b, or false past the last tile:
+// the group q with tprefix[q] <= b < tprefix[q + 1] (binary search).
+__device__ __forceinline__ bool bucket_tile_of(const BucketArgs &a, uint32_t b, uint32_t &q,
+                                               uint32_t &t, uint32_t &nt)
+{
+    if (b >= a.tprefix[a.groups])
+        return false;
+    uint32_t lo = 0, hi = a.groups;  // tprefix[lo] <= b < tprefix[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a.tprefix[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    q = lo;
+    t = b - a.tprefix[q];
+    nt = a.tprefix[q + 1] - a.tprefix[q];
+    return true;
+}
+
+// Index of count (group q, segment g, tile t of the group's nt) in tcounts:
+// the groups' blocks in order, segment-major within a group.
+__device__ __forceinline__ uint64_t bucket_count_at(const BucketArgs &a, uint32_t q, uint32_t g,
+                                                    uint32_t t, uint32_t nt)
+{
+    return (uint64_t)a.nseg * a.tprefix[q] + (uint64_t)g * nt + t;
+}
+
+// Histogram pass: per tile, its hits per segment, stored at their
+// (group, segment, tile) place; workgroups past the last tile store zeros
+// over the rest of the array (nseg entries each), so that the scan reads a
+// fully written array.
+__global__ void __launch_bounds__(1024) bucket_hist_kernel(BucketArgs a)
+{
+    __shared__ uint32_t hist[MAX_BUCKET_SEGS];
+    const uint32_t nseg = a.nseg;
+    for (uint32_t g = threadIdx.x; g < nseg; g += blockDim.x)
+        hist[g] = 0;
+    __syncthreads();
+    uint32_t q, t, nt;
+    if (!bucket_tile_of(a, blockIdx.x, q, t, nt)) {
+        for (uint32_t g = threadIdx.x; g < nseg; g += blockDim.x)
+            a.tcounts[(uint64_t)nseg * blockIdx.x + g] = 0;
+        return;
+    }
+    const uint64_t t0 = (uint64_t)a.sbase[q] + (uint64_t)t * a.tile;
+    const uint64_t t1 = min((uint64_t)a.sbase[q] + a.filled[q], t0 + a.tile);
+    // eight entries per thread and round, all read before any is counted
+    constexpr int UNROLL = 8;
+    for (uint64_t i0 = t0 + threadIdx.x; i0 < t1; i0 += (uint64_t)UNROLL * blockDim.x) {
+        uint32_t v[UNROLL];
+#pragma unroll
+        for (int k = 0; k < UNROLL; ++k) {
+            const uint64_t i = i0 + (uint64_t)k * blockDim.x;
+            v[k] = i < t1 ? a.stream[i] : ~0u;
+        }
+#pragma unroll
+        for (int k = 0; k < UNROLL; ++k)
+            if (v[k] != ~0u)
+                atomicAdd(&hist[min(v[k] >> HIT_BITS, nseg - 1)], 1u);
+    }
+    __syncthreads();
+    const uint64_t n2 = (uint64_t)nseg * a.max_tiles;
+    for (uint32_t g = threadIdx.x; g < nseg; g += blockDim.x) {
+        const uint64_t at = bucket_count_at(a, q, g, t, nt);
+        if (at < n2)  // (always, while the hits stay within hit_cap)
+            a.tcounts[at] = hist[g];
+    }
+}
+
+// Starts: hs[q * nseg + g] = the scanned count of (q, g, tile 0), i.e. the
+// first place of bucket (q, g) (for a group without hits, the place where
+// its buckets would begin), and hs[groups * nseg] = the total.
+__global__ void __launch_bounds__(256) bucket_starts_kernel(BucketArgs a)
+{
+    const uint32_t q = blockIdx.x;
+    const uint32_t nt = a.tprefix[q + 1] - a.tprefix[q];
+    const uint64_t n2 = (uint64_t)a.nseg * a.max_tiles;  // the scanned total is at [n2]
+    for (uint32_t g = threadIdx.x; g < a.nseg; g += blockDim.x) {
+        const uint64_t at = nt ? bucket_count_at(a, q, g, 0, nt) : (uint64_t)a.nseg * a.tprefix[q];
+        a.hs[(uint64_t)q * a.nseg + g] = a.tcounts[min(at, n2)];
+    }
+    if (q + 1 == a.groups && threadIdx.x == 0)
+        a.hs[(uint64_t)a.groups * a.nseg] =
+            a.tcounts[min((uint64_t)a.nseg * a.tprefix[a.groups], n2)];
+}
+
+// Scatter pass: per tile, in rounds of BUCKET_SORT_SUB hits: counted by
+// segment (LDS atomics), scanned, put in segment order in LDS and written
+// out so that consecutive threads write consecutive places of one bucket;
+// each segment's cursor starts at the tile's scanned count and moves past
+// each round's hits.  The order of hits within a bucket is free (the sieve
+// clears each hit's bit).  Launched with 1024 threads (nseg <= 2 x 1024).
+__global__ void __launch_bounds__(1024, 8) bucket_scatter_kernel(BucketArgs a)
+{
+    __shared__ uint32_t cursor[MAX_BUCKET_SEGS];
+    __shared__ uint32_t toff[MAX_BUCKET_SEGS + 1];
+    __shared__ uint32_t sorted[BUCKET_SORT_SUB];
+    __shared__ uint32_t wsum[16];
+    constexpr int PER = BUCKET_SORT_SUB / 1024;
+    uint32_t q, t, nt;
+    if (!bucket_tile_of(a, blockIdx.x, q, t, nt))
+        return;
+    const uint32_t nseg = a.nseg;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t n2 = (uint64_t)nseg * a.max_tiles;
+    for (uint32_t g = threadIdx.x; g < nseg; g += blockDim.x) {
+        cursor[g] = a.tcounts[min(bucket_count_at(a, q, g, t, nt), n2)];
+        toff[g] = 0;
+    }
+    const uint64_t b0 = (uint64_t)a.sbase[q] + (uint64_t)t * a.tile;
+    const uint64_t b1 = min((uint64_t)a.sbase[q] + a.filled[q], b0 + a.tile);
+    __syncthreads();
+    for (uint64_t r0 = b0; r0 < b1; r0 += BUCKET_SORT_SUB) {
+        const uint32_t n = (uint32_t)min((uint64_t)BUCKET_SORT_SUB, b1 - r0);
+        uint32_t v[PER], rank[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const uint32_t i = threadIdx.x + k * blockDim.x;
+            v[k] = 0;
+            rank[k] = 0;
+            if (i < n) {
+                v[k] = a.stream[r0 + i];
+                // (the clamp only keeps LDS indices inside the array: every
+                // entry was written by the fill pass with its segment)
+                v[k] = min(v[k] >> HIT_BITS, nseg - 1) << HIT_BITS | (v[k] & ((1u << HIT_BITS) - 1u));
+                rank[k] = atomicAdd(&toff[v[k] >> HIT_BITS], 1u);
+            }
+        }
+        __syncthreads();  // the round's counts are in toff
+        // exclusive scan of toff[0 .. nseg) in place, two consecutive
+        // entries per thread
+        {
+            const uint32_t g0 = 2 * threadIdx.x;
+            const uint32_t c0 = g0 < nseg ? toff[g0] : 0u, c1 = g0 + 1 < nseg ? toff[g0 + 1] : 0u;
+            const uint32_t local = c0 + c1;
+            uint32_t incl = local;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(incl, o, 64);
+                if (lane >= o)
+                    incl += y;
+            }
+            if (lane == 63)
+                wsum[wave] = incl;
+            __syncthreads();
+            uint32_t run = incl - local;
+            for (int w = 0; w < wave; ++w)
+                run += wsum[w];
+            if (g0 < nseg)
+                toff[g0] = run;
+            if (g0 + 1 < nseg)
+                toff[g0 + 1] = run + c0;
+            if (threadIdx.x == 0)
+                toff[nseg] = n;
+        }
+        __syncthreads();  // toff: the round's offset of each segment
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const uint32_t i = threadIdx.x + k * blockDim.x;
+            if (i < n)
+                sorted[toff[v[k] >> HIT_BITS] + rank[k]] = v[k];
+        }
+        __syncthreads();  // the round is in segment order
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const uint32_t i = threadIdx.x + k * blockDim.x;
+            if (i < n) {
+                const uint32_t w = sorted[i];
+                const uint32_t g = w >> HIT_BITS;
+                const uint64_t at = (uint64_t)cursor[g] + (i - toff[g]);
+                if (at < a.hit_cap)
+                    a.hits[at] = w & ((1u << HIT_BITS) - 1u);
+            }
+        }
+        // the round's count per segment, read before any thread clears toff
+        const uint32_t ga = threadIdx.x, gb = threadIdx.x + blockDim.x;
+        const uint32_t na = ga < nseg ? toff[ga + 1] - toff[ga] : 0u;
+        const uint32_t nb = gb < nseg ? toff[gb + 1] - toff[gb] : 0u;
+        __syncthreads();  // every place and count is taken from cursor and toff
+        if (ga < nseg) {
+            cursor[ga] += na;
+            toff[ga] = 0;
+        }
+        if (gb < nseg) {
+            cursor[gb] += nb;
+            toff[gb] = 0;
+        }
+        __syncthreads();  // ready for the next round
     }
 }
 
@@ -671,20 +1042,6 @@ __global__ void __launch_bounds__(BUCKET_THREADS) range_bucket_kernel(BucketArgs
 // workgroup), then each tile scanned and offset.
 constexpr int SCAN_TILE = 8192;  // 1024 threads x 8
 
-__device__ __forceinline__ uint32_t block_sum_1024(uint32_t v, uint32_t *wsum)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v += __shfl_xor(v, o, 64);
-    if (lane == 0)
-        wsum[wave] = v;
-    __syncthreads();
-    uint32_t t = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
-        t += wsum[w];
-    return t;
-}
 
 __global__ void __launch_bounds__(1024) scan_tile_sums(const uint32_t *counts, uint32_t n,
                                                       uint32_t *sums)
@@ -789,8 +1146,36 @@ hipError_t launch_range_table(uint64_t lo, uint8_t *out, uint64_t len, const Dev
     return hipGetLastError();
 }
 
+BucketLayout bucket_layout(uint32_t nseg, unsigned groups, uint64_t hit_cap)
+{
+    BucketLayout L{};
+    // the smallest tile of at least 16 rounds (a power-of-two multiple of
+    // BUCKET_SORT_SUB) whose count array fits the three-pass scan (at most
+    // 1024 scan tiles); longer tiles leave fewer counts and let one
+    // workgroup's consecutive rounds complete more of each bucket's lines
+    // (measured at 2^63: 2^14-hit tiles 1.46 ms and 866 MiB written per
+    // 2^28 numbers, 2^16-hit tiles 1.37 ms and 732 MiB)
+    for (uint64_t tile = 16 * BUCKET_SORT_SUB; tile <= ((uint64_t)1 << 24); tile *= 2) {
+        const uint64_t max_tiles = (hit_cap + tile - 1) / tile + groups;
+        const uint64_t n2 = (uint64_t)nseg * max_tiles;
+        if (n2 <= (uint64_t)SCAN_TILE * 1024) {
+            L.tile = (uint32_t)tile;
+            L.max_tiles = (uint32_t)max_tiles;
+            const uint64_t ntiles = (n2 + SCAN_TILE - 1) / SCAN_TILE;
+            // starts, wsplit, totals, filled, sbase, tprefix, counts + total,
+            // scan sums + total
+            L.count_words = (uint64_t)groups * nseg + 1 + 2 * (uint64_t)groups +
+                            3 * ((uint64_t)groups + 1) + n2 + 1 + ntiles + 1;
+            L.ok = true;
+            return L;
+        }
+    }
+    return L;
+}
+
 hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsigned groups,
-                                const DeviceState &ds, const RangeWs &rw, hipStream_t s)
+                                uint64_t hit_bound, const DeviceState &ds, const RangeWs &rw,
+                                hipStream_t s)
 {
     BucketArgs a;
     a.lo = lo;
@@ -800,35 +1185,60 @@ hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsign
     a.w_begin = (BUCKET_SMALL + 1) >> 6;
     a.w_end = (root >> 6) + 1;
     a.nseg = (uint32_t)((len + RANGE_SEG - 1) / RANGE_SEG);
-    a.counts = rw.counts;
+    a.groups = groups;
     a.hits = rw.hits;
-    a.hit_cap = rw.hit_cap;
+    a.stream = rw.stream;
+    a.hit_cap = hit_bound;  // the layout's room; the buffers may hold more
     if (a.nseg > (uint32_t)MAX_BUCKET_SEGS || a.w_end > (uint64_t)TABLE_WORDS ||
-        a.w_end <= a.w_begin)
+        a.w_end <= a.w_begin || groups == 0 || groups > (unsigned)MAX_BUCKET_GROUPS ||
+        hit_bound > rw.hit_cap || hit_bound >= ((uint64_t)1 << 32))
         return hipErrorInvalidValue;
-    const uint32_t n = a.nseg * groups;
-    const uint32_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
-    if (ntiles > 1024 || rw.count_cap < (uint64_t)n + 1 + ntiles + 1)
+    const BucketLayout L = bucket_layout(a.nseg, groups, hit_bound);
+    if (!L.ok || rw.count_cap < L.count_words)
         return hipErrorInvalidValue;
-    uint32_t *sums = rw.counts + n + 1;  // ntiles + 1 words after the counts
-    range_bucket_kernel<false><<<groups, BUCKET_THREADS, 0, s>>>(a);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) {
-        scan_tile_sums<<<ntiles, 1024, 0, s>>>(rw.counts, n, sums);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) {
-        scan_small<<<1, 1024, 0, s>>>(sums, ntiles);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) {
-        scan_tiles<<<ntiles, 1024, 0, s>>>(rw.counts, n, sums);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) {
-        range_bucket_kernel<true><<<groups, BUCKET_THREADS, 0, s>>>(a);
-        e = hipGetLastError();
-    }
+    a.tile = L.tile;
+    a.max_tiles = L.max_tiles;
+    const uint64_t n2 = (uint64_t)a.nseg * L.max_tiles;
+    const uint32_t ntiles = (uint32_t)((n2 + SCAN_TILE - 1) / SCAN_TILE);
+    uint32_t *w = rw.counts;
+    a.hs = w;  // first: the segment kernel reads the starts at the workspace's base
+    w += (uint64_t)groups * a.nseg + 1;
+    a.wsplit = w;
+    w += groups + 1;
+    a.totals = w;
+    w += groups;
+    a.filled = w;
+    w += groups;
+    a.sbase = w;
+    w += groups + 1;
+    a.tprefix = w;
+    w += groups + 1;
+    a.tcounts = w;
+    w += n2 + 1;
+    uint32_t *sums = w;  // ntiles + 1
+    hipError_t e = hipSuccess;
+    auto step = [&](auto launch) {
+        if (e == hipSuccess) {
+            launch();
+            e = hipGetLastError();
+        }
+    };
+    step([&] { bucket_split_kernel<<<1, 1024, 0, s>>>(a); });
+    // the bound pass: at most BUCKET_BOUND_PER words per thread, and at
+    // least 1024 workgroups while the words allow
+    const uint64_t words = a.w_end - a.w_begin;
+    a.bound_per = (uint32_t)std::min<uint64_t>(
+        BUCKET_BOUND_PER, std::max<uint64_t>(1, (words + 1024 * 1024 - 1) / (1024 * 1024)));
+    const unsigned bound_grid = (unsigned)((words + 1024 * a.bound_per - 1) / (1024 * a.bound_per));
+    step([&] { bucket_bound_kernel<<<bound_grid, 1024, 0, s>>>(a); });
+    step([&] { bucket_plan_kernel<<<1, 1024, 0, s>>>(a); });
+    step([&] { range_fill_kernel<<<groups, BUCKET_THREADS, 0, s>>>(a); });
+    step([&] { bucket_hist_kernel<<<L.max_tiles, 1024, 0, s>>>(a); });
+    step([&] { scan_tile_sums<<<ntiles, 1024, 0, s>>>(a.tcounts, (uint32_t)n2, sums); });
+    step([&] { scan_small<<<1, 1024, 0, s>>>(sums, ntiles); });
+    step([&] { scan_tiles<<<ntiles, 1024, 0, s>>>(a.tcounts, (uint32_t)n2, sums); });
+    step([&] { bucket_starts_kernel<<<groups, 256, 0, s>>>(a); });
+    step([&] { bucket_scatter_kernel<<<L.max_tiles, 1024, 0, s>>>(a); });
     return e;
 }
 
