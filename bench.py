@@ -266,7 +266,13 @@ def bench_paper_suite(isp, W, torch, reps: int = 7) -> dict:
     return res
 
 
-def bench_intervals(isp, torch, reps: int = 5, array_call: bool = True) -> dict:
+INTERVAL_CASES = (("2^34+[0,2^28)", 1 << 34, 1 << 28), ("2^44+[0,2^28)", 1 << 44, 1 << 28),
+                  ("2^50+[0,2^28)", 1 << 50, 1 << 28), ("2^63+[0,2^28)", 1 << 63, 1 << 28),
+                  ("2^64-2^28+[0,2^28)", (1 << 64) - (1 << 28), 1 << 28),
+                  ("2^63+[0,2^24)", 1 << 63, 1 << 24))
+
+
+def bench_intervals(isp, torch, reps: int = 5, array_call: bool = True, only=None) -> dict:
     """The interval call above 2^32, where each workgroup sieves a segment of
     2^19 numbers in LDS, in each of its modes: segments decided by the primes
     up to their square root (2^34, 2^44), the bucket sieve of the primes
@@ -276,10 +282,9 @@ def bench_intervals(isp, torch, reps: int = 5, array_call: bool = True) -> dict:
     against the array call on the same values."""
     stream = torch.cuda.current_stream()
     res = {}
-    for name, lo, length in (("2^34+[0,2^28)", 1 << 34, 1 << 28), ("2^44+[0,2^28)", 1 << 44, 1 << 28),
-                             ("2^50+[0,2^28)", 1 << 50, 1 << 28), ("2^63+[0,2^28)", 1 << 63, 1 << 28),
-                             ("2^64-2^28+[0,2^28)", (1 << 64) - (1 << 28), 1 << 28),
-                             ("2^63+[0,2^24)", 1 << 63, 1 << 24)):
+    for name, lo, length in INTERVAL_CASES:
+        if only is not None and name != only:
+            continue
         rout = torch.empty(length, dtype=torch.bool, device="cuda")
         rms = _time_ms(torch, stream, lambda: isp.isprime_range(lo, length, rout, stream), reps)
         if not array_call:
@@ -724,6 +729,8 @@ def main() -> int:
                          "and --steps with per-kernel events; for profiling)")
     ap.add_argument("--intervals-only", action="store_true",
                     help="only time the interval call on its cases (for profiling its kernels)")
+    ap.add_argument("--interval-case", choices=[c[0] for c in INTERVAL_CASES], default=None,
+                    help="with --intervals-only: only this case")
     ap.add_argument("--wheel-only", action="store_true",
                     help="only time the wheel stage against Miller-Rabin per octave")
     ap.add_argument("--sieve-only", action="store_true",
@@ -757,7 +764,7 @@ def main() -> int:
         return 0
     if args.intervals_only:
         print(json.dumps({"intervals": bench_intervals(isp, torch, reps=args.steps,
-                                                       array_call=False)}))
+                                                       array_call=False, only=args.interval_case)}))
         return 0
     if args.wheel_only:
         print(json.dumps({"wheel_vs_miller_rabin": bench_wheel(isp, W, torch, reps=args.steps)}))
