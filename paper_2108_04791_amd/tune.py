@@ -29,7 +29,7 @@ SPACE = {
     "classify_ept": [2, 4, 8],
     "classify_block": [256, 512, 1024],
     "classify_blocks_per_cu": [1, 2, 4, 8, 16],
-    "filter_primes": [8, 16, 24, 32, 48],
+    "filter_primes": [8, 16, 24, 32, 48, 64],
     "sort_survivors": [1, -1],
     "mr_block": [256, 512, 1024],
     "mr_blocks_per_cu": [1, 2, 4, 8],
