@@ -215,9 +215,8 @@ struct RangeArgs {
     Survivor *surv;      // grid regions of `chunk` entries
     uint32_t *counts;    // [grid]
     // bucket mode: the primes above BUCKET_SMALL come as precomputed hits
-    const uint32_t *hit_start;  // [groups * grid + 1]: the hits of segment g found
-                                // by group q are hits[hit_start[q * grid + g] ..
-                                // hit_start[q * grid + g + 1])
+    const uint32_t *hit_start;  // [grid + 1]: the hits of segment g are
+                                // hits[hit_start[g] .. hit_start[g + 1])
     const uint32_t *hits;       // bit indices within their segment
     uint64_t hit_cap;           // entries allocated in hits
     uint32_t groups;            // 0: no buckets
@@ -373,18 +372,24 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
             inv = invn;
         }
     }
-    // bucket mode: the hits of the primes above BUCKET_SMALL in this segment
+    // bucket mode: the hits of the primes above BUCKET_SMALL in this segment,
+    // one contiguous run (the clamp only keeps reads inside the allocation),
+    // eight per thread and round, all read before any is applied
     if (buckets) {
-        // one run per group, read by one wavefront (the hits fit by
-        // construction; the clamp only keeps reads inside the allocation)
-        for (uint32_t q = wave; q < a.groups; q += nwaves) {
-            const uint64_t at = (uint64_t)q * gridDim.x + blockIdx.x;
-            const uint32_t h0 = a.hit_start[at];
-            const uint32_t h1 = (uint32_t)min((uint64_t)a.hit_start[at + 1], a.hit_cap);
-            for (uint32_t h = h0 + lane; h < h1; h += 64) {
-                const uint32_t j = a.hits[h];
-                atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
+        const uint32_t h0 = a.hit_start[blockIdx.x];
+        const uint32_t h1 = (uint32_t)min((uint64_t)a.hit_start[blockIdx.x + 1], a.hit_cap);
+        constexpr int UNROLL = 8;
+        for (uint32_t h = h0 + tid; h < h1; h += UNROLL * blockDim.x) {
+            uint32_t j[UNROLL];
+#pragma unroll
+            for (int k = 0; k < UNROLL; ++k) {
+                const uint32_t i = h + k * blockDim.x;
+                j[k] = i < h1 ? a.hits[i] : ~0u;
             }
+#pragma unroll
+            for (int k = 0; k < UNROLL; ++k)
+                if (j[k] < nbits)
+                    atomicAnd(&bits[j[k] >> 5], ~(1u << (j[k] & 31)));
         }
     }
     __syncthreads();
@@ -473,18 +478,18 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
 //      found, to its stretch of the stream (one contiguous store per
 //      wavefront step), and records how many it found;
 //   4. histogram: per tile of a group's stretch, its hits per segment;
-//   5. an exclusive scan of those counts, laid out (group, segment, tile),
-//      which is exactly the order of the buckets and of the tiles within a
-//      bucket: each count's scanned value is where that tile's hits of that
-//      segment go;
-//   6. starts: the first hit of each (group, segment);
+//   5. an exclusive scan of those counts, laid out (segment, tile), which is
+//      exactly the order of the hits: each segment's together, by tile
+//      within it, so each count's scanned value is where that tile's hits of
+//      that segment go;
+//   6. starts: the first hit of each segment;
 //   7. scatter: each tile's hits, put in segment order in LDS, written to
 //      their places, consecutive threads at consecutive places.
 // Writing each hit straight to its bucket from the enumeration would keep
 // groups x segments partly written 128-byte lines open at once (32 MB for
 // 512 groups and 512 segments, the whole L2): measured, each line reached
 // HBM about 2.5 times over and the pass took twice the enumeration.  The
-// segment kernel then applies bucket (group, segment) for every group.
+// segment kernel then applies its segment's one run of hits.
 // With every prime up to the square root crossed off, the segments are
 // complete at any magnitude below 2^64.
 
@@ -505,7 +510,7 @@ struct BucketArgs {
     uint32_t *tprefix;       // [groups + 1]: each group's first tile
     uint32_t *tcounts;       // [nseg * max_tiles + 1]: hits per (group, segment, tile),
                              // scanned in place
-    uint32_t *hs;            // [groups * nseg + 1]: the first hit of (group, segment)
+    uint32_t *hs;            // [nseg + 1]: the first hit of each segment
     uint32_t *hits;          // hit_cap entries: bit indices within their segment
     uint32_t *stream;        // hit_cap entries: segment << HIT_BITS | bit index
     uint64_t hit_cap;
@@ -865,18 +870,18 @@ __device__ __forceinline__ bool bucket_tile_of(const BucketArgs &a, uint32_t b, 
     return true;
 }
 
-// Index of count (group q, segment g, tile t of the group's nt) in tcounts:
-// the groups' blocks in order, segment-major within a group.
-__device__ __forceinline__ uint64_t bucket_count_at(const BucketArgs &a, uint32_t q, uint32_t g,
-                                                    uint32_t t, uint32_t nt)
+// Index of the count of segment g in tile b (b: the tile's index over all
+// groups, tprefix[q] + t) in tcounts: segment-major, so that the flat scan
+// puts every segment's hits together, in the order of the tiles (and so of
+// the groups) within it.
+__device__ __forceinline__ uint64_t bucket_count_at(const BucketArgs &a, uint32_t g, uint32_t b)
 {
-    return (uint64_t)a.nseg * a.tprefix[q] + (uint64_t)g * nt + t;
+    return (uint64_t)g * a.max_tiles + b;
 }
 
 // Histogram pass: per tile, its hits per segment, stored at their
-// (group, segment, tile) place; workgroups past the last tile store zeros
-// over the rest of the array (nseg entries each), so that the scan reads a
-// fully written array.
+// (segment, tile) place; workgroups past the last tile store zeros in their
+// column, so that the scan reads a fully written array.
 __global__ void __launch_bounds__(1024) bucket_hist_kernel(BucketArgs a)
 {
     __shared__ uint32_t hist[MAX_BUCKET_SEGS];
@@ -887,7 +892,7 @@ __global__ void __launch_bounds__(1024) bucket_hist_kernel(BucketArgs a)
     uint32_t q, t, nt;
     if (!bucket_tile_of(a, blockIdx.x, q, t, nt)) {
         for (uint32_t g = threadIdx.x; g < nseg; g += blockDim.x)
-            a.tcounts[(uint64_t)nseg * blockIdx.x + g] = 0;
+            a.tcounts[bucket_count_at(a, g, blockIdx.x)] = 0;
         return;
     }
     const uint64_t t0 = (uint64_t)a.sbase[q] + (uint64_t)t * a.tile;
@@ -907,29 +912,17 @@ __global__ void __launch_bounds__(1024) bucket_hist_kernel(BucketArgs a)
                 atomicAdd(&hist[min(v[k] >> HIT_BITS, nseg - 1)], 1u);
     }
     __syncthreads();
-    const uint64_t n2 = (uint64_t)nseg * a.max_tiles;
-    for (uint32_t g = threadIdx.x; g < nseg; g += blockDim.x) {
-        const uint64_t at = bucket_count_at(a, q, g, t, nt);
-        if (at < n2)  // (always, while the hits stay within hit_cap)
-            a.tcounts[at] = hist[g];
-    }
+    for (uint32_t g = threadIdx.x; g < nseg; g += blockDim.x)
+        a.tcounts[bucket_count_at(a, g, blockIdx.x)] = hist[g];
 }
 
-// Starts: hs[q * nseg + g] = the scanned count of (q, g, tile 0), i.e. the
-// first place of bucket (q, g) (for a group without hits, the place where
-// its buckets would begin), and hs[groups * nseg] = the total.
+// Starts: hs[g] = the scanned count of (segment g, tile 0), the first place
+// of segment g's hits, and hs[nseg] = the total.
 __global__ void __launch_bounds__(256) bucket_starts_kernel(BucketArgs a)
 {
-    const uint32_t q = blockIdx.x;
-    const uint32_t nt = a.tprefix[q + 1] - a.tprefix[q];
-    const uint64_t n2 = (uint64_t)a.nseg * a.max_tiles;  // the scanned total is at [n2]
-    for (uint32_t g = threadIdx.x; g < a.nseg; g += blockDim.x) {
-        const uint64_t at = nt ? bucket_count_at(a, q, g, 0, nt) : (uint64_t)a.nseg * a.tprefix[q];
-        a.hs[(uint64_t)q * a.nseg + g] = a.tcounts[min(at, n2)];
-    }
-    if (q + 1 == a.groups && threadIdx.x == 0)
-        a.hs[(uint64_t)a.groups * a.nseg] =
-            a.tcounts[min((uint64_t)a.nseg * a.tprefix[a.groups], n2)];
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g <= a.nseg)
+        a.hs[g] = a.tcounts[(uint64_t)g * a.max_tiles];  // [nseg * max_tiles]: the total
 }
 
 // Scatter pass: per tile, in rounds of BUCKET_SORT_SUB hits: counted by
@@ -950,9 +943,8 @@ __global__ void __launch_bounds__(1024, 8) bucket_scatter_kernel(BucketArgs a)
         return;
     const uint32_t nseg = a.nseg;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t n2 = (uint64_t)nseg * a.max_tiles;
     for (uint32_t g = threadIdx.x; g < nseg; g += blockDim.x) {
-        cursor[g] = a.tcounts[min(bucket_count_at(a, q, g, t, nt), n2)];
+        cursor[g] = a.tcounts[bucket_count_at(a, g, blockIdx.x)];
         toff[g] = 0;
     }
     const uint64_t b0 = (uint64_t)a.sbase[q] + (uint64_t)t * a.tile;
@@ -1164,7 +1156,7 @@ BucketLayout bucket_layout(uint32_t nseg, unsigned groups, uint64_t hit_cap)
             const uint64_t ntiles = (n2 + SCAN_TILE - 1) / SCAN_TILE;
             // starts, wsplit, totals, filled, sbase, tprefix, counts + total,
             // scan sums + total
-            L.count_words = (uint64_t)groups * nseg + 1 + 2 * (uint64_t)groups +
+            L.count_words = (uint64_t)nseg + 1 + 2 * (uint64_t)groups +
                             3 * ((uint64_t)groups + 1) + n2 + 1 + ntiles + 1;
             L.ok = true;
             return L;
@@ -1202,7 +1194,7 @@ hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsign
     const uint32_t ntiles = (uint32_t)((n2 + SCAN_TILE - 1) / SCAN_TILE);
     uint32_t *w = rw.counts;
     a.hs = w;  // first: the segment kernel reads the starts at the workspace's base
-    w += (uint64_t)groups * a.nseg + 1;
+    w += (uint64_t)a.nseg + 1;
     a.wsplit = w;
     w += groups + 1;
     a.totals = w;
@@ -1237,7 +1229,7 @@ hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsign
     step([&] { scan_tile_sums<<<ntiles, 1024, 0, s>>>(a.tcounts, (uint32_t)n2, sums); });
     step([&] { scan_small<<<1, 1024, 0, s>>>(sums, ntiles); });
     step([&] { scan_tiles<<<ntiles, 1024, 0, s>>>(a.tcounts, (uint32_t)n2, sums); });
-    step([&] { bucket_starts_kernel<<<groups, 256, 0, s>>>(a); });
+    step([&] { bucket_starts_kernel<<<(a.nseg + 1 + 255) / 256, 256, 0, s>>>(a); });
     step([&] { bucket_scatter_kernel<<<L.max_tiles, 1024, 0, s>>>(a); });
     return e;
 }
