@@ -44,7 +44,7 @@ typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(8)));
 // and the bound floor((2^32 - 1) / p), so the unrolled filter below uses
 // immediate constants and issues no memory load.
 constexpr int DENSE_TO = 64;  // the second stage ends at the 64th odd prime (313)
-constexpr int FILTER2_BLOCK = 256;
+constexpr int FILTER2_BLOCK = 512;
 
 constexpr bool ce_is_prime(uint64_t p)
 {
@@ -457,7 +457,7 @@ __global__ void __launch_bounds__(SMALL_BLOCK) small_kernel(const uint64_t *__re
 // window is read into registers before the first barrier, and it is written
 // back at most at its own position, so the sort is in place.  Without SORT
 // the survivors keep their order.
-constexpr int F2_PER_THREAD = 8;
+constexpr int F2_PER_THREAD = 4;
 constexpr uint32_t F2_WINDOW = FILTER2_BLOCK * F2_PER_THREAD;
 
 template <int NF>
