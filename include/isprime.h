@@ -274,10 +274,10 @@ typedef struct isp_server isp_server;
 
 typedef struct {
     int32_t device;            /* HIP device ordinal */
-    int32_t max_inflight;      /* batches on the device at once: 1..8 (0 = 6) */
+    int32_t max_inflight;      /* batches on the device at once: 1..8 (0 = 8) */
     uint64_t mem_budget_bytes; /* bytes of admitted, unfinished requests, 9 per element
                                   (0 = 1 GiB); the slots' footprint is on top of it */
-    uint64_t max_batch_elems;  /* elements per batch, at most 2^28 (0 = 1,048,576) */
+    uint64_t max_batch_elems;  /* elements per batch, at most 2^28 (0 = 262,144) */
     int32_t max_batch_reqs;    /* request pieces per batch (0 = 1024) */
     int32_t block_on_full;     /* 1: isp_submit waits for budget; 0: ISP_EBUSY */
     int32_t test_mode;         /* 0: the device; 1: a host stand-in that writes n & 1, for

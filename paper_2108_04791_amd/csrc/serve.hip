@@ -371,12 +371,17 @@ int isp_server_create(const isp_server_config *cfg, isp_server **srv)
     std::unique_ptr<isp_server> s(new isp_server());
     s->cfg = *cfg;
     isp_server_config &c = s->cfg;
+    // 8 slots of 2^18 elements: a request of up to 2^20 elements is split
+    // over several slots that run it in parallel (measured on the C5 stream
+    // at 42 k requests/s: p50 0.33 / p99 1.08 ms, against 0.45 / 1.55 ms
+    // for 6 slots of 2^20, at the same capacity of about 60 k requests/s;
+    // 2^17-element slots lost capacity, 2^16 lost half of it)
     if (!c.max_inflight)
-        c.max_inflight = 6;
+        c.max_inflight = 8;
     if (!c.mem_budget_bytes)
         c.mem_budget_bytes = (uint64_t)1 << 30;
     if (!c.max_batch_elems)
-        c.max_batch_elems = (uint64_t)1 << 20;
+        c.max_batch_elems = (uint64_t)1 << 18;
     if (!c.max_batch_reqs)
         c.max_batch_reqs = 1024;
     if (c.max_inflight < 1 || c.max_inflight > 8 || c.max_batch_reqs < 1 ||

@@ -30,8 +30,20 @@ def test_bit_length_and_popcount_against_python():
     assert bench.popcount(a).tolist() == [bin(int(x)).count("1") for x in a.tolist()]
 
 
+def window_products(d: int) -> int:
+    """Products of a^d by 3-bit fixed windows, one step at a time: the
+    base's Montgomery form, the table a^2 .. a^7, then per further window
+    three squarings and one multiplication."""
+    nwin = -(-d.bit_length() // 3)
+    count = 1 + 6
+    for _ in range(nwin - 1):
+        count += 3 + 1
+    return count
+
+
 def test_mr_work_by_brute_force():
-    """Squarings, doublings and products counted one element at a time."""
+    """Squarings, doublings and products counted one element at a time, and
+    the instructions at each magnitude's product cost (lazy below 2^62)."""
     rng = np.random.default_rng(2)
     a = np.concatenate([rng.integers(1 << 49, U64, size=300, dtype=np.uint64) | np.uint64(1),
                         np.array([(1 << 61) - 1, U64 - 58, 2047, 1 << 40, 3 * 5 * 7 * 313 * (1 << 30) + 0],
@@ -41,7 +53,7 @@ def test_mr_work_by_brute_force():
     assert primes64[0] == 3 and primes64[-1] == 313
     for fp in (16, 0):
         work, surv, cand = bench.mr_work(a, prime, fp)
-        sq = dbl = mm = ns = nc = 0
+        sq = dbl = mm = ns = nc = ops2 = ops_rest = 0
         for n in a.tolist():
             if n < (1 << 32) or n % 2 == 0:
                 continue
@@ -51,16 +63,20 @@ def test_mr_work_by_brute_force():
             ns += 1
             sq += L - 2
             dbl += bin(n - 1).count("1") - 1
+            lazy = n < (1 << 62)
+            ops2 += (L - 2) * (20 if lazy else 22) + (bin(n - 1).count("1") - 1) * (1 if lazy else 5)
         for n, pr in zip(a.tolist(), prime.tolist()):
             if pr and n >= (1 << 32):
                 nc += 1
                 d = n - 1
                 while d % 2 == 0:
                     d //= 2
-                mm += 6 * ((n.bit_length() - 2) + (bin(d).count("1") - 1))
+                mm += 6 * window_products(d)
+                ops_rest += 6 * window_products(d) * (20 if n < (1 << 62) else 22)
         assert (surv, cand) == (ns, nc)
         assert work["mr_base2"]["montmul"] == sq and work["mr_base2"]["doublings"] == dbl
-        assert work["mr_rest"]["montmul"] == mm
+        assert work["mr_base2"]["ops"] == ops2
+        assert work["mr_rest"]["montmul"] == mm and work["mr_rest"]["ops"] == ops_rest
 
 
 def test_planted_pseudoprimes_by_the_oracle():
@@ -108,7 +124,7 @@ def test_mr_work_counts_planted_passers():
         d = n - 1
         while d % 2 == 0:
             d //= 2
-        mm += k * ((n.bit_length() - 2) + (bin(d).count("1") - 1))
+        mm += k * window_products(d)
     assert work["mr_rest"]["montmul"] == mm > 0
     assert work["mr_rest"]["passers_counted"] == int((nb > 0).sum()) == 251
 

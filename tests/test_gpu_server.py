@@ -85,8 +85,8 @@ def test_served_split_request_and_threads(isp):
 
 
 def test_served_at_the_benchmarked_configuration(isp):
-    """The server as the benchmark runs it (the defaults: 6 slots of 2^20
-    elements, the staging helper threads) on the first 300 requests of the
+    """The server as the benchmark runs it (the defaults: 8 slots of 2^18
+    elements, requests of up to 2^20 split over several) on the first 300 requests of the
     benchmark's own stream (lengths log-uniform in [1, 2^20]): every result
     equals the oracle's, submitted all at once (packed into shared batches)
     and one at a time."""
@@ -94,10 +94,10 @@ def test_served_at_the_benchmarked_configuration(isp):
     assert max(r.size for r in reqs) > (1 << 19)
     exp = [oracle.isprime_array(r, nthreads=NTHREADS, use_table=True)[0] for r in reqs]
     with isp.Server() as srv:
-        # the fixed footprint: 6 slots, each a workspace for 2^20 elements
+        # the fixed footprint: 8 slots, each a workspace for 2^18 elements
         # and 9 pinned bytes per element
         dev_b, pin_b = srv.footprint()
-        assert dev_b == 6 * isp.workspace_bytes(1 << 20) and pin_b == 6 * 9 * (1 << 20)
+        assert dev_b == 8 * isp.workspace_bytes(1 << 18) and pin_b == 8 * 9 * (1 << 18)
         mixed = [np.full(r.size, 2, np.uint8) for r in reqs]
         tickets = [srv.submit(r, o) for r, o in zip(reqs, mixed)]
         for t in tickets:
