@@ -523,19 +523,26 @@ static_assert(MAX_BUCKET_SEGS <= (1 << (32 - HIT_BITS)), "segment fits above the
 // Hits per LDS round of the scatter kernel (1024 threads x 4).
 constexpr uint32_t BUCKET_SORT_SUB = 4096;
 
-// lo mod p for p < 2^32 from a double-precision quotient estimate (error
-// below one unit: lo < 2^64 is rounded to 53 bits and the quotient is below
-// 2^45, so the estimate is within 2^-7 of lo / p) and one correction each way.
+// x mod p for 2^19 <= p < 2^32, in double precision with exact remainder
+// arithmetic.  The reciprocal is the hardware estimate refined by two Newton
+// steps (relative error a few units of 2^-53); x rounded to 53 bits times it
+// is within 2^-7 of x / p < 2^45, so q = floor(x * (1/p) - 1/2) is
+// floor(x / p) or one less, and r = x - q p lies in [0, 2p).  r is formed
+// from the exact halves xh = x - (x mod 2^32) and xl = x mod 2^32 as
+// fma(-q, p, xh) + xl: the fused product-sum is exact because its result,
+// r - xl, is an integer of magnitude below 2^33, and so is the sum.  One
+// conditional subtraction of p ends it.
 __device__ __forceinline__ uint64_t mod_u32(uint64_t x, uint32_t p)
 {
-    const double q = (double)x * (1.0 / (double)p);
-    uint64_t qi = q < 1.0 ? 0 : (uint64_t)q;
-    int64_t r = (int64_t)(x - qi * (uint64_t)p);
-    if (r < 0)
-        r += p;
-    if (r >= (int64_t)p)
-        r -= p;
-    return (uint64_t)r;
+    const double xh = (double)(x & ~(uint64_t)0xffffffffu), xl = (double)(uint32_t)x;
+    const double pd = (double)p;
+    double inv = __builtin_amdgcn_rcp(pd);
+    inv = fma(inv, fma(-pd, inv, 1.0), inv);
+    inv = fma(inv, fma(-pd, inv, 1.0), inv);
+    const double q = floor(fma((double)x, inv, -0.5));
+    double r = fma(-q, pd, xh) + xl;
+    r = r >= pd ? r - pd : r;
+    return (uint64_t)(uint32_t)r;
 }
 
 // Offset from lo of p's first odd multiple at or above max(lo, p^2), or an
@@ -588,11 +595,10 @@ constexpr int BUCKET_THREADS = 1024;
 constexpr uint32_t BUCKET_PBUF = 1024;
 
 // Each odd multiple of p in the piece appended to the group's stream: the
-// lanes with a hit at a step take consecutive places in the stream (one LDS
-// atomic by the first of them), so each step is one contiguous store of the
-// wavefront.
-__device__ __forceinline__ void bucket_hits(const BucketArgs &a, uint32_t p, uint32_t lane,
-                                            uint32_t *fill, uint64_t gbase, uint64_t gend)
+// lanes with a hit at a step take consecutive places in the stream, so each
+// step is one contiguous store of the wavefront.
+__device__ __forceinline__ void bucket_hits(const BucketArgs &a, uint32_t p, uint32_t *fill,
+                                            uint64_t gbase, uint64_t gend)
 {
     const uint64_t first = bucket_first(a, p);
     if (first >= a.len)
@@ -605,15 +611,11 @@ __device__ __forceinline__ void bucket_hits(const BucketArgs &a, uint32_t p, uin
     if (step <= span)
         K = (uint32_t)span / (uint32_t)step + 1u;
     uint64_t off = first;
-    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     for (uint32_t j = 0; j < K; ++j) {
-        const uint64_t m = __ballot(1);  // the lanes still in the loop
-        const int leader = __ffsll((long long)m) - 1;
-        uint32_t base = 0;
-        if ((int)lane == leader)
-            base = atomicAdd(fill, (uint32_t)__popcll(m));
-        base = __builtin_amdgcn_readlane(base, leader);
-        const uint64_t at = gbase + base + (uint32_t)__popcll(m & lt);
+        // one place per lane still in the loop (the compiler combines the
+        // wavefront's increments into one LDS atomic and numbers the lanes
+        // in order, so the places are consecutive)
+        const uint64_t at = gbase + atomicAdd(fill, 1u);
         if (at < gend)
             a.stream[at] = (uint32_t)(off >> RANGE_SEG_LOG2) << HIT_BITS |
                            (uint32_t)((off & (RANGE_SEG - 1)) >> 1);
@@ -759,7 +761,7 @@ __global__ void __launch_bounds__(BUCKET_THREADS) range_fill_kernel(BucketArgs a
     uint32_t *buf = pbuf[wave];
     auto take = [&](uint32_t p) {
         if (p > BUCKET_SMALL && p <= a.root)
-            bucket_hits(a, p, lane, &fill, gbase, gend);
+            bucket_hits(a, p, &fill, gbase, gend);
     };
     // the primes of a chunk of 64 words (w0 .. w0 + 63; lane l holds word
     // w0 + l) are listed densely in LDS (a wavefront prefix sum of the
