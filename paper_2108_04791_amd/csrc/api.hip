@@ -752,6 +752,8 @@ void isp_shutdown(void)
             (void)hipFree(ds.range_inv);
         if (ds.range_count)
             (void)hipFree(ds.range_count);
+        if (ds.chunk_primes)
+            (void)hipFree(ds.chunk_primes);
         ds = DeviceState();
     }
 }
@@ -838,26 +840,36 @@ static int ensure_range_primes(int dev)
     if (e == hipSuccess)
         e = hipMalloc(&ds.range_count, (RANGE_LIST_GROUPS + 1) * sizeof(uint32_t));
     if (e == hipSuccess)
+        e = hipMalloc(&ds.chunk_primes, chunk_primes_words() * sizeof(uint32_t));
+    if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (e == hipSuccess)
         e = launch_range_primes(ds, s);
-    uint32_t count = 0;
+    if (e == hipSuccess)
+        e = launch_chunk_primes(ds, s);
+    uint32_t count = 0, chunk_total = 0;
     if (e == hipSuccess)
         e = hipMemcpyAsync(&count, ds.range_count + RANGE_LIST_GROUPS, sizeof(count),
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&chunk_total, ds.chunk_primes + TABLE_CHUNKS, sizeof(chunk_total),
                            hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
     if (s)
         (void)hipStreamDestroy(s);
-    if (e == hipSuccess && count != RANGE_MAX_PRIMES - 1)
-        e = hipErrorUnknown;  // 2063688 odd primes below 2^25
+    // 2063688 odd primes below 2^25, 203280220 below 2^32
+    if (e == hipSuccess && (count != RANGE_MAX_PRIMES - 1 || chunk_total != TABLE_ODD_PRIMES))
+        e = hipErrorUnknown;
     if (e != hipSuccess) {
         (void)hipFree(ds.range_primes);
         (void)hipFree(ds.range_inv);
         (void)hipFree(ds.range_count);
+        (void)hipFree(ds.chunk_primes);
         ds.range_primes = nullptr;
         ds.range_inv = nullptr;
         ds.range_count = nullptr;
+        ds.chunk_primes = nullptr;
         return fail(e);
     }
     ds.num_range_primes = (int)count;

@@ -13,6 +13,10 @@ namespace isp {
 constexpr uint64_t TABLE_BOUND = (uint64_t)1 << 32;
 constexpr uint64_t TABLE_WORDS = (uint64_t)1 << 26;  // 2^31 odd numbers / 32
 constexpr int MAX_BASE_PRIMES = 6542;                // odd primes below 2^16: 6541
+// Prime counts of the table by chunks of 64 words (4096 numbers): entry c is
+// the number of odd primes below 4096 c, c = 0 .. TABLE_CHUNKS.
+constexpr uint64_t TABLE_CHUNKS = TABLE_WORDS / 64;
+constexpr uint32_t TABLE_ODD_PRIMES = 203280220;  // odd primes below 2^32
 // The lookup table for n < 2^32 on the 2*3*5*7 wheel: block q of 48 bits
 // for the numbers 210 q + r with r coprime to 210 (48 residues in [1, 209]),
 // bit 48 q + (index of r); the multiples of 3, 5 and 7 need no bit.
@@ -198,6 +202,9 @@ struct DeviceState {
     uint64_t *range_inv = nullptr;
     uint32_t *range_count = nullptr;  // RANGE_LIST_GROUPS + 1 words
     int num_range_primes = 0;
+    // bucket mode: the table's prime counts by chunks (TABLE_CHUNKS + 1
+    // words, then the build's scan sums), built with the list
+    uint32_t *chunk_primes = nullptr;
     // device address of this device's copy of the allocation-free entry
     // point's static scratch array (hipGetSymbolAddress at isp_init)
     unsigned char *scratch = nullptr;
@@ -244,6 +251,9 @@ hipError_t launch_lucas(const MrArgs &a, int cus, int per_cu, unsigned max_grid,
                         hipStream_t s);
 
 hipError_t launch_range_primes(DeviceState &ds, hipStream_t s);
+// Builds ds.chunk_primes (chunk_primes_words() words) from the table.
+size_t chunk_primes_words();
+hipError_t launch_chunk_primes(DeviceState &ds, hipStream_t s);
 hipError_t launch_range_table(uint64_t lo, uint8_t *out, uint64_t len, const DeviceState &ds,
                               hipStream_t s);
 // Bucket mode's sort tile, per-tile launch size and count words for nseg

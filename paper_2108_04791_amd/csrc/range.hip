@@ -496,8 +496,10 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
 struct BucketArgs {
     uint64_t lo, len;        // the piece
     uint64_t w_begin, w_end; // table words holding the odd primes in (BUCKET_SMALL, root]
+    uint64_t w_mid;          // the bound pass takes words w_begin .. w_mid - 1 prime by prime
     uint64_t root;
     const uint32_t *table;
+    const uint32_t *chunk_primes;  // [TABLE_CHUNKS + 1]: odd primes below 4096 c
     uint32_t nseg;           // segments of RANGE_SEG numbers
     uint32_t groups;         // workgroups of the count and fill passes
     uint32_t tile;           // hits per sort tile (a multiple of BUCKET_SORT_SUB)
@@ -523,43 +525,43 @@ static_assert(MAX_BUCKET_SEGS <= (1 << (32 - HIT_BITS)), "segment fits above the
 // Hits per LDS round of the scatter kernel (1024 threads x 4).
 constexpr uint32_t BUCKET_SORT_SUB = 4096;
 
-// x mod p for 2^19 <= p < 2^32, in double precision with exact remainder
-// arithmetic.  The reciprocal is the hardware estimate refined by two Newton
-// steps (relative error a few units of 2^-53); x rounded to 53 bits times it
-// is within 2^-7 of x / p < 2^45, so q = floor(x * (1/p) - 1/2) is
-// floor(x / p) or one less, and r = x - q p lies in [0, 2p).  r is formed
+// x mod d for integers 2^19 <= d < 2^34, in double precision with exact
+// remainder arithmetic.  The reciprocal is the hardware estimate refined by
+// two Newton steps (relative error a few units of 2^-53); x rounded to 53
+// bits times it is within 2^-7 of x / d < 2^45, so q = floor(x * (1/d) - 1/2)
+// is floor(x / d) or one less, and r = x - q d lies in [0, 2d).  r is formed
 // from the exact halves xh = x - (x mod 2^32) and xl = x mod 2^32 as
-// fma(-q, p, xh) + xl: the fused product-sum is exact because its result,
-// r - xl, is an integer of magnitude below 2^33, and so is the sum.  One
-// conditional subtraction of p ends it.
-__device__ __forceinline__ uint64_t mod_u32(uint64_t x, uint32_t p)
+// fma(-q, d, xh) + xl: the fused product-sum is exact because its result,
+// r - xl, is an integer of magnitude below 2^35, and so is the sum.  One
+// conditional subtraction of d ends it.
+__device__ __forceinline__ double mod_small(uint64_t x, double d)
 {
     const double xh = (double)(x & ~(uint64_t)0xffffffffu), xl = (double)(uint32_t)x;
-    const double pd = (double)p;
-    double inv = __builtin_amdgcn_rcp(pd);
-    inv = fma(inv, fma(-pd, inv, 1.0), inv);
-    inv = fma(inv, fma(-pd, inv, 1.0), inv);
+    double inv = __builtin_amdgcn_rcp(d);
+    inv = fma(inv, fma(-d, inv, 1.0), inv);
+    inv = fma(inv, fma(-d, inv, 1.0), inv);
     const double q = floor(fma((double)x, inv, -0.5));
-    double r = fma(-q, pd, xh) + xl;
-    r = r >= pd ? r - pd : r;
-    return (uint64_t)(uint32_t)r;
+    const double r = fma(-q, d, xh) + xl;
+    return r >= d ? r - d : r;
 }
 
-// Offset from lo of p's first odd multiple at or above max(lo, p^2), or an
-// offset >= len when there is none.
-__device__ __forceinline__ uint64_t bucket_first(const BucketArgs &a, uint32_t p)
+// Offset from lo of p's first odd multiple at or above max(lo, p^2) when it
+// is below len, else len (a piece holds at most 2^30 numbers, so the offset
+// fits 32 bits).
+__device__ __forceinline__ uint32_t bucket_first(const BucketArgs &a, uint32_t p)
 {
     const uint64_t pp = (uint64_t)p * p;
-    uint64_t off;
     if (pp >= a.lo) {
-        off = pp - a.lo;  // odd square: odd when lo is even, and lo + off is odd
-    } else {
-        const uint64_t r = mod_u32(a.lo, p);
-        off = r ? p - r : 0;
-        if (((a.lo + off) & 1) == 0)
-            off += p;  // the next multiple is odd
+        const uint64_t off = pp - a.lo;  // p^2 is odd
+        return off < a.len ? (uint32_t)off : (uint32_t)a.len;
     }
-    return off;
+    // the odd multiples of p are the numbers congruent to p mod 2p: with
+    // m = lo mod 2p, the first at or above lo is lo + p - m (m <= p) or
+    // lo + 3p - m (all exact in double precision: below 2^35)
+    const double pd = (double)p;
+    const double m = mod_small(a.lo, 2.0 * pd);
+    const double off = (m <= pd ? pd : 3.0 * pd) - m;
+    return off < (double)a.len ? (uint32_t)off : (uint32_t)a.len;
 }
 
 // Cost of the primes below x, up to constants: one first-hit computation per
@@ -600,26 +602,27 @@ constexpr uint32_t BUCKET_PBUF = 1024;
 __device__ __forceinline__ void bucket_hits(const BucketArgs &a, uint32_t p, uint32_t *fill,
                                             uint64_t gbase, uint64_t gend)
 {
-    const uint64_t first = bucket_first(a, p);
-    if (first >= a.len)
+    const uint32_t len = (uint32_t)a.len;  // at most 2^30
+    const uint32_t first = bucket_first(a, p);
+    if (first >= len)
         return;
-    const uint64_t step = 2ull * p;
-    const uint64_t span = a.len - 1 - first;  // < 2^30
-    // K = floor(span / step) + 1; step > span means a single multiple, and
-    // otherwise step < 2^30 fits 32 bits
+    const uint32_t span = len - 1 - first;
+    // K = floor(span / 2p) + 1: a single multiple when 2p > span, and
+    // otherwise 2p <= span < 2^30
     uint32_t K = 1;
-    if (step <= span)
-        K = (uint32_t)span / (uint32_t)step + 1u;
-    uint64_t off = first;
+    if (p <= span / 2)
+        K = span / (2u * p) + 1u;
+    uint32_t off = first;
     for (uint32_t j = 0; j < K; ++j) {
         // one place per lane still in the loop (the compiler combines the
         // wavefront's increments into one LDS atomic and numbers the lanes
         // in order, so the places are consecutive)
         const uint64_t at = gbase + atomicAdd(fill, 1u);
+        // segment off >> RANGE_SEG_LOG2 above bit index (off mod RANGE_SEG) / 2,
+        // which with HIT_BITS = RANGE_SEG_LOG2 - 1 is off / 2
         if (at < gend)
-            a.stream[at] = (uint32_t)(off >> RANGE_SEG_LOG2) << HIT_BITS |
-                           (uint32_t)((off & (RANGE_SEG - 1)) >> 1);
-        off += step;
+            a.stream[at] = off >> 1;
+        off += 2u * p;  // (only read again while j < K, when 2p < 2^30)
     }
 }
 
@@ -663,11 +666,16 @@ __device__ __forceinline__ uint32_t block_sum_1024(uint32_t v, uint32_t *wsum)
 
 // Bound pass: totals[group] >= the group's hits (zeroed by the split
 // kernel).  Each prime p in (BUCKET_SMALL, root] adds floor((len - 1) / 2p)
-// + 1; a word whose 32 numbers all lie in (max(BUCKET_SMALL, (len - 1) / 2),
-// root] adds its popcount (each of its primes adds 1), any other word its
-// primes one by one.  The words are split evenly over the workgroups
-// (1024 x bound_per each, whatever the groups), and each workgroup adds
-// its sum over each group's words to that group's total.
+// + 1, which is 1 for p > (len - 1) / 2.  Words w_begin .. w_mid - 1 (whose
+// numbers do not all exceed max(BUCKET_SMALL, (len - 1) / 2)) are taken
+// prime by prime: split evenly over the first workgroups (1024 x bound_per
+// words each, whatever the groups), each adding its sum over each group's
+// words to that group's total.  The words from w_mid on add their prime
+// counts: for each group boundary w, C(w) = the primes in the words below
+// w, from the chunk counts and the popcounts of at most 63 words (one
+// wavefront per boundary, in the last workgroups), added to the total of
+// the group it ends and subtracted from that of the group it starts (modulo
+// 2^32: every partial sum cancels); the last word is counted up to root.
 constexpr uint32_t BUCKET_BOUND_PER = 8;  // the most words per thread
 
 __device__ __forceinline__ uint32_t bucket_bound_word(const BucketArgs &a, uint32_t word,
@@ -687,14 +695,51 @@ __device__ __forceinline__ uint32_t bucket_bound_word(const BucketArgs &a, uint3
     return c;
 }
 
-__global__ void __launch_bounds__(1024) bucket_bound_kernel(BucketArgs a)
+// The chunk-count part of the bound pass: one wavefront per group boundary
+// g = 16 b + wavefront, g <= groups.
+__device__ __forceinline__ void bucket_bound_counts(const BucketArgs &a, uint32_t b)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t g = b * 16 + (threadIdx.x >> 6);
+    if (g > a.groups)
+        return;  // (uniform per wavefront)
+    // the boundary clamped to the counted words [w_mid, w_top): the last
+    // word, which may hold numbers above root, is counted on its own
+    const uint64_t w_top = max(a.w_mid, a.w_end - 1);
+    const uint64_t w = min(max((uint64_t)a.wsplit[g], a.w_mid), w_top);
+    const uint64_t c = w >> 6;
+    uint32_t v = lane < (uint32_t)(w & 63) ? (uint32_t)__popc(a.table[(c << 6) + lane]) : 0u;
+    if (g == a.groups && a.w_mid < a.w_end && lane == 0) {
+        // word w_end - 1 holds 64 (w_end - 1) + 2i + 1 for i < 32; those up
+        // to root are the first (r + 1) / 2, r = root mod 64
+        const uint32_t nb = (uint32_t)((a.root & 63) + 1) >> 1;
+        const uint32_t mask = nb >= 32 ? ~0u : (1u << nb) - 1u;
+        atomicAdd(&a.totals[a.groups - 1], (uint32_t)__popc(a.table[a.w_end - 1] & mask));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    const uint32_t count = a.chunk_primes[c] + v;  // C(w)
+    if (lane == 0) {
+        if (g > 0)
+            atomicAdd(&a.totals[g - 1], count);
+        if (g < a.groups)
+            atomicSub(&a.totals[g], count);
+    }
+}
+
+__global__ void __launch_bounds__(1024) bucket_bound_kernel(BucketArgs a, uint32_t enum_blocks)
 {
     __shared__ uint32_t wsum[16];
+    if (blockIdx.x >= enum_blocks) {
+        bucket_bound_counts(a, blockIdx.x - enum_blocks);
+        return;  // (uniform)
+    }
     const uint32_t per = a.bound_per;  // 1 .. BUCKET_BOUND_PER
     const uint64_t w0 = a.w_begin + (uint64_t)blockIdx.x * 1024 * per;
-    if (w0 >= a.w_end)
+    if (w0 >= a.w_mid)
         return;  // (uniform)
-    const uint64_t w1 = min(w0 + 1024 * per, a.w_end);
+    const uint64_t w1 = min(w0 + 1024 * per, a.w_mid);
     const uint64_t pcut = (a.len - 1) / 2;  // primes above it have at most one hit
     const uint64_t lo_p = pcut > BUCKET_SMALL ? pcut : BUCKET_SMALL;
     // every word read before any is used
@@ -1118,6 +1163,42 @@ __global__ void __launch_bounds__(1024) scan_tiles(uint32_t *counts, uint32_t n,
 
 }  // namespace
 
+namespace {
+
+// Chunk c's odd primes (the popcount of table words 64c .. 64c + 63): one
+// wavefront per chunk.
+__global__ void __launch_bounds__(256) chunk_popc_kernel(const uint32_t *table, uint32_t *cnt)
+{
+    const uint64_t c = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t lane = threadIdx.x & 63;
+    if (c >= TABLE_CHUNKS)
+        return;  // (uniform per wavefront)
+    uint32_t v = (uint32_t)__popc(table[(c << 6) + lane]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    if (lane == 0)
+        cnt[c] = v;
+}
+
+constexpr uint32_t CHUNK_SCAN_TILES = (uint32_t)((TABLE_CHUNKS + SCAN_TILE - 1) / SCAN_TILE);
+static_assert(CHUNK_SCAN_TILES <= 1024, "one workgroup scans the tile sums");
+
+}  // namespace
+
+size_t chunk_primes_words() { return TABLE_CHUNKS + 1 + CHUNK_SCAN_TILES + 1; }
+
+hipError_t launch_chunk_primes(DeviceState &ds, hipStream_t s)
+{
+    uint32_t *cnt = ds.chunk_primes, *sums = cnt + TABLE_CHUNKS + 1;
+    const uint32_t n = (uint32_t)TABLE_CHUNKS;
+    chunk_popc_kernel<<<(unsigned)(TABLE_CHUNKS * 64 / 256), 256, 0, s>>>(ds.table, cnt);
+    scan_tile_sums<<<CHUNK_SCAN_TILES, 1024, 0, s>>>(cnt, n, sums);
+    scan_small<<<1, 1024, 0, s>>>(sums, CHUNK_SCAN_TILES);
+    scan_tiles<<<CHUNK_SCAN_TILES, 1024, 0, s>>>(cnt, n, sums);
+    return hipGetLastError();
+}
+
 hipError_t launch_range_primes(DeviceState &ds, hipStream_t s)
 {
     range_count_kernel<<<RANGE_LIST_GROUPS, 256, 0, s>>>(ds.table, ds.range_count);
@@ -1178,6 +1259,10 @@ hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsign
     a.table = ds.table;
     a.w_begin = (BUCKET_SMALL + 1) >> 6;
     a.w_end = (root >> 6) + 1;
+    // the first word whose numbers all exceed max(BUCKET_SMALL, (len - 1) / 2)
+    const uint64_t lo_p = std::max<uint64_t>((len - 1) / 2, BUCKET_SMALL);
+    a.w_mid = std::min(a.w_end, std::max(a.w_begin, (lo_p >> 6) + 1));
+    a.chunk_primes = ds.chunk_primes;
     a.nseg = (uint32_t)((len + RANGE_SEG - 1) / RANGE_SEG);
     a.groups = groups;
     a.hits = rw.hits;
@@ -1185,7 +1270,7 @@ hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsign
     a.hit_cap = hit_bound;  // the layout's room; the buffers may hold more
     if (a.nseg > (uint32_t)MAX_BUCKET_SEGS || a.w_end > (uint64_t)TABLE_WORDS ||
         a.w_end <= a.w_begin || groups == 0 || groups > (unsigned)MAX_BUCKET_GROUPS ||
-        hit_bound > rw.hit_cap || hit_bound >= ((uint64_t)1 << 32))
+        hit_bound > rw.hit_cap || hit_bound >= ((uint64_t)1 << 32) || !ds.chunk_primes)
         return hipErrorInvalidValue;
     const BucketLayout L = bucket_layout(a.nseg, groups, hit_bound);
     if (!L.ok || rw.count_cap < L.count_words)
@@ -1218,13 +1303,15 @@ hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsign
         }
     };
     step([&] { bucket_split_kernel<<<1, 1024, 0, s>>>(a); });
-    // the bound pass: at most BUCKET_BOUND_PER words per thread, and at
-    // least 1024 workgroups while the words allow
-    const uint64_t words = a.w_end - a.w_begin;
+    // the bound pass: the words taken prime by prime at most
+    // BUCKET_BOUND_PER per thread, and over at least 1024 workgroups while
+    // they allow; then one wavefront per group boundary
+    const uint64_t words = a.w_mid - a.w_begin;
     a.bound_per = (uint32_t)std::min<uint64_t>(
         BUCKET_BOUND_PER, std::max<uint64_t>(1, (words + 1024 * 1024 - 1) / (1024 * 1024)));
-    const unsigned bound_grid = (unsigned)((words + 1024 * a.bound_per - 1) / (1024 * a.bound_per));
-    step([&] { bucket_bound_kernel<<<bound_grid, 1024, 0, s>>>(a); });
+    const unsigned enum_blocks = (unsigned)((words + 1024 * a.bound_per - 1) / (1024 * a.bound_per));
+    const unsigned count_blocks = (groups + 1 + 15) / 16;
+    step([&] { bucket_bound_kernel<<<enum_blocks + count_blocks, 1024, 0, s>>>(a, enum_blocks); });
     step([&] { bucket_plan_kernel<<<1, 1024, 0, s>>>(a); });
     step([&] { range_fill_kernel<<<groups, BUCKET_THREADS, 0, s>>>(a); });
     step([&] { bucket_hist_kernel<<<L.max_tiles, 1024, 0, s>>>(a); });
