@@ -568,19 +568,21 @@ __device__ __forceinline__ uint32_t bucket_first(const BucketArgs &a, uint32_t p
 // prime (x / ln x primes) and one bucket entry per hit (len/2 * sum 1/p, which
 // grows like ln ln x).  Group g takes the primes whose cumulative cost falls
 // in its equal share, so the low primes with hundreds of hits each and the
-// high primes with at most one are spread evenly.
-__device__ __forceinline__ double bucket_cost(double x, double len)
+// high primes with at most one are spread evenly.  (Single precision with
+// the fast logarithm and quotient: the split only balances the work, and
+// every split gives the same bits.)
+__device__ __forceinline__ float bucket_cost(float x, float len)
 {
-    const double lx = log(x);
-    return 24.0 * x / lx + 4.0 * 0.5 * len * log(lx);
+    const float lx = __logf(x);
+    return __fdividef(24.0f * x, lx) + 2.0f * len * __logf(lx);
 }
 
-// The prime bound where the cumulative cost reaches `target` (bisection,
-// down to below one number over any interval up to 2^32).
-__device__ double bucket_split(double target, double lo, double hi, double len)
+// The prime bound where the cumulative cost reaches `target` (bisection
+// down to the resolution of single precision).
+__device__ float bucket_split(float target, float lo, float hi, float len)
 {
-    for (int it = 0; it < 32; ++it) {
-        const double mid = 0.5 * (lo + hi);
+    for (int it = 0; it < 26; ++it) {
+        const float mid = 0.5f * (lo + hi);
         if (bucket_cost(mid, len) < target)
             lo = mid;
         else
@@ -632,19 +634,35 @@ __device__ __forceinline__ void bucket_hits(const BucketArgs &a, uint32_t p, uin
 // per boundary; launched with one workgroup of at least groups + 1 threads.
 __global__ void __launch_bounds__(1024) bucket_split_kernel(BucketArgs a)
 {
+    __shared__ uint32_t wmax[16];
     const uint32_t g = threadIdx.x;
-    if (g > a.groups)
-        return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (g < a.groups)
         a.totals[g] = 0;  // summed by the bound pass
-    uint64_t w = g == 0 ? a.w_begin : a.w_end;
+    uint32_t w = g == 0 ? (uint32_t)a.w_begin : (uint32_t)a.w_end;
     if (g > 0 && g < a.groups) {
-        const double len = (double)a.len, x0 = (double)BUCKET_SMALL, x1 = (double)a.root + 1.0;
-        const double c0 = bucket_cost(x0, len), c1 = bucket_cost(x1, len);
-        w = (uint64_t)bucket_split(c0 + (c1 - c0) * g / a.groups, x0, x1, len) >> 6;
-        w = w < a.w_begin ? a.w_begin : (w > a.w_end ? a.w_end : w);
+        const float len = (float)a.len, x0 = (float)BUCKET_SMALL, x1 = (float)a.root + 1.0f;
+        const float c0 = bucket_cost(x0, len), c1 = bucket_cost(x1, len);
+        const float x = bucket_split(c0 + (c1 - c0) * ((float)g / (float)a.groups), x0, x1, len);
+        const uint64_t wx = (uint64_t)x >> 6;
+        w = (uint32_t)(wx < a.w_begin ? a.w_begin : (wx > a.w_end ? a.w_end : wx));
     }
-    a.wsplit[g] = (uint32_t)w;
+    // the boundaries made nondecreasing whatever the rounding (an inclusive
+    // maximum scan over the threads; thread groups holds w_end, the largest)
+    uint32_t m = g <= a.groups ? w : 0u;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(m, o, 64);
+        if (lane >= o)
+            m = max(m, y);
+    }
+    if (lane == 63)
+        wmax[wave] = m;
+    __syncthreads();
+    for (int k = 0; k < wave; ++k)
+        m = max(m, wmax[k]);
+    if (g <= a.groups)
+        a.wsplit[g] = m;
 }
 
 // Sum of v over a workgroup of up to 1024 threads (wsum: one word per
@@ -847,10 +865,17 @@ __global__ void __launch_bounds__(BUCKET_THREADS) range_fill_kernel(BucketArgs a
             }
         }
     };
+    // each chunk's words are loaded while the chunk before is processed
     const uint64_t nch = we > wb ? (we - wb + 63) / 64 : 0;
-    for (uint64_t ch = wave; ch < nch; ch += nwaves) {
+    auto load = [&](uint64_t ch) {
         const uint64_t w = wb + 64 * ch + lane;
-        chunk(wb + 64 * ch, w < we ? a.table[w] : 0u);
+        return ch < nch && w < we ? a.table[w] : 0u;
+    };
+    uint32_t next = load(wave);
+    for (uint64_t ch = wave; ch < nch; ch += nwaves) {
+        const uint32_t word = next;
+        next = load(ch + nwaves);
+        chunk(wb + 64 * ch, word);
     }
     __syncthreads();
     if (threadIdx.x == 0)
