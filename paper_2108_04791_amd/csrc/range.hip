@@ -231,8 +231,7 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
     __shared__ uint32_t bits[MAX_WORDS + 1];          // + one zero word past the end
     __shared__ uint32_t wsum[RANGE_THREADS / 64];
     const int tid = threadIdx.x, lane = tid & 63;
-    // the wavefront index as a scalar, so per-prime work of the wavefront
-    // loop below (the prime, its first multiple) runs on the scalar unit
+    // the wavefront index as a scalar (the wavefront loop below is uniform)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nwaves = blockDim.x >> 6;
     const uint64_t chunk = a.chunk;
@@ -334,15 +333,29 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
         }
         k_split = lo_i;
     }
-    for (uint32_t k = PRESIEVED + wave; k < k_split; k += nwaves) {
-        const uint32_t p = a.primes[k];
-        const uint64_t j0 = first_bit(p, a.inv[k]);
-        if (j0 >= nbits)
-            continue;
-        // bit indices below 2^18: 32-bit arithmetic
-        const uint32_t stride = 64u * p;
-        for (uint32_t j = (uint32_t)j0 + (uint32_t)lane * p; j < nbits; j += stride)
-            atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
+    // (the wavefront's primes are k = PRESIEVED + wave + m nwaves; their
+    // first bits are computed 64 at a time, one per lane, and each crossing
+    // loop takes its prime and start from a lane: the reductions run on the
+    // vector units instead of the compute unit's one scalar unit)
+    for (uint32_t kb = PRESIEVED + wave; kb < k_split; kb += 64u * nwaves) {
+        const uint32_t k = kb + (uint32_t)lane * nwaves;
+        uint32_t pl = 0, jl = ~0u;
+        if (k < k_split) {
+            pl = a.primes[k];
+            const uint64_t j0 = first_bit(pl, a.inv[k]);
+            jl = j0 < nbits ? (uint32_t)j0 : ~0u;
+        }
+        const uint32_t cnt = min(64u, (k_split - kb + nwaves - 1) / nwaves);
+        for (uint32_t i = 0; i < cnt; ++i) {
+            const uint32_t p = __builtin_amdgcn_readlane(pl, i);
+            const uint32_t j0 = __builtin_amdgcn_readlane(jl, i);
+            if (j0 == ~0u)
+                continue;
+            // bit indices below 2^18: 32-bit arithmetic
+            const uint32_t stride = 64u * p;
+            for (uint32_t j = j0 + (uint32_t)lane * p; j < nbits; j += stride)
+                atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
+        }
     }
     // larger primes: one thread per prime; the thread's next prime and its
     // constant are loaded while the current one is crossed off (the loads'
@@ -534,7 +547,7 @@ constexpr uint32_t BUCKET_SORT_SUB = 4096;
 // fma(-q, d, xh) + xl: the fused product-sum is exact because its result,
 // r - xl, is an integer of magnitude below 2^35, and so is the sum.  One
 // conditional subtraction of d ends it.
-__device__ __forceinline__ double mod_small(uint64_t x, double d)
+__device__ __forceinline__ double mod_double(uint64_t x, double d)
 {
     const double xh = (double)(x & ~(uint64_t)0xffffffffu), xl = (double)(uint32_t)x;
     double inv = __builtin_amdgcn_rcp(d);
@@ -559,7 +572,7 @@ __device__ __forceinline__ uint32_t bucket_first(const BucketArgs &a, uint32_t p
     // m = lo mod 2p, the first at or above lo is lo + p - m (m <= p) or
     // lo + 3p - m (all exact in double precision: below 2^35)
     const double pd = (double)p;
-    const double m = mod_small(a.lo, 2.0 * pd);
+    const double m = mod_double(a.lo, 2.0 * pd);
     const double off = (m <= pd ? pd : 3.0 * pd) - m;
     return off < (double)a.len ? (uint32_t)off : (uint32_t)a.len;
 }
