@@ -141,14 +141,14 @@ int isprime_u64_batched_offsets(const uint64_t *n, uint8_t *out, const uint64_t 
  * with no input array.  lo + len - 1 must not exceed 2^64 - 1 (ISP_EINVAL).
  *   out  device pointer to len bytes, each written 0 or 1
  * The part below 2^32 is read from the sieve table.  Above it, each
- * workgroup sieves a segment of 2^19 numbers in LDS, in pieces of at most
- * 2^30 numbers.  A piece ending below 2^50 is sieved by every odd prime up
+ * workgroup sieves a segment of 2^20 or 2^19 numbers in LDS, in pieces of
+ * at most 2^30 numbers.  A piece ending below 2^50 is sieved by every odd prime up
  * to the square root of its end, which decides it.  Above, a piece long
  * enough for the primes up to its square root (pi(sqrt) below 0.8 times its
  * length) also gets every such prime: those above 2^20 are sorted once into
  * per-segment buckets (bucket sieve), and the segments are again complete.
  * Otherwise it is sieved by the odd primes below 2^22 (below 2^18 for a
- * piece of fewer than 256 segments, which is then cut into up to 256
+ * piece of fewer than 256 segments of 2^19, which is then cut into up to 256
  * shorter segments) and the survivors go through the same Miller-Rabin
  * kernels as isprime_u64.  The workspace kept
  * for the stream grows to the largest call seen.  Asynchronous on `stream`.

@@ -31,7 +31,7 @@ constexpr int MAX_DEVICES = 64;
 // A plain call is split into pieces of at most this many elements, so the
 // 32-bit device counters never overflow and a workspace stays below 8 GiB.
 constexpr size_t PLAIN_PIECE = (size_t)1 << 28;
-// Interval pieces of fewer full segments (RANGE_SEG numbers) than this, where
+// Interval pieces of fewer full segments (RANGE_SEG_SMALL numbers) than this, where
 // the sieve cannot be complete, sieve by the primes below
 // 2^PARTIAL_SHORT_LOG2, in up to this many segments of at least
 // RANGE_MIN_CHUNK numbers.
@@ -572,25 +572,35 @@ RangePlan plan_range_piece(uint64_t first, uint64_t piece)
     // segment pass costs about 0.45 ns per prime, Miller-Rabin on the
     // survivors about 0.011 ns per number of the piece, over 0.03 ms more
     // of fixed cost.
-    const bool short_piece = full < PARTIAL_FULL_GRID;
+    const unsigned full_small = (unsigned)((piece + RANGE_SEG_SMALL - 1) / RANGE_SEG_SMALL);
+    const bool short_piece = full_small < PARTIAL_FULL_GRID;
     const bool force_partial = short_piece && p.root >= ((uint64_t)1 << PARTIAL_SHORT_LOG2) &&
                                pi_root > (double)piece / 40.0 + 65536.0;
     p.complete_log2 = force_partial ? PARTIAL_SHORT_LOG2 : RANGE_PRIME_LOG2;
     p.complete = p.root < ((uint64_t)1 << p.complete_log2);
-    // a short piece in Miller-Rabin mode is cut into up to PARTIAL_FULL_GRID
-    // shorter segments (at least RANGE_MIN_CHUNK numbers each): its
-    // workgroups then share the crossings, while each still visits the few
-    // primes below the short-piece bound (in complete mode each segment
-    // visits every prime up to the root, so more segments would only repeat
-    // that work)
-    p.grid = p.complete || !short_piece
-                 ? full
-                 : (unsigned)std::max<uint64_t>(
-                       full, std::min<uint64_t>(PARTIAL_FULL_GRID, piece / RANGE_MIN_CHUNK));
     // a short piece has few segments, each visiting all the primes below
     // the bound one after another: a lower bound there costs more
     // Miller-Rabin on the extra survivors but far less sieve latency
     p.partial_log2 = short_piece ? PARTIAL_SHORT_LOG2 : RANGE_PARTIAL_LOG2;
+    // segments of RANGE_SEG numbers where every segment visits primes past
+    // 2^20 and the piece fills at least PARTIAL_FULL_GRID of them (each
+    // prime's first multiple is then found once per 2^20 numbers; measured
+    // on 2^28 numbers at 2^44, complete up to 2^22: 0.360 -> 0.273 ms), else
+    // of RANGE_SEG_SMALL (twice the workgroups: at 2^34, primes up to 2^17,
+    // 0.099 ms against 0.118 ms).  A short piece in Miller-Rabin mode is cut
+    // into up to PARTIAL_FULL_GRID shorter segments (at least RANGE_MIN_CHUNK
+    // numbers each): its workgroups then share the crossings, while each
+    // still visits the few primes below the short-piece bound (in complete
+    // mode each segment visits every prime up to the root, so more segments
+    // would only repeat that work)
+    const uint64_t sieve_bound = p.complete ? p.root : ((uint64_t)1 << p.partial_log2);
+    if (sieve_bound > ((uint64_t)1 << 20) && full >= PARTIAL_FULL_GRID)
+        p.grid = full;
+    else
+        p.grid = p.complete || !short_piece
+                     ? full_small
+                     : (unsigned)std::max<uint64_t>(
+                           full_small, std::min<uint64_t>(PARTIAL_FULL_GRID, piece / RANGE_MIN_CHUNK));
     return p;
 }
 

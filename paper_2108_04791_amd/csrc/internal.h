@@ -94,21 +94,25 @@ constexpr int SMALL_BLOCK = 256;
 constexpr unsigned SMALL_TEAM = 8;
 
 // Numbers per workgroup segment of the interval sieve (LDS holds the odd
-// ones: 2^18 bits), and numbers per piece of an interval call.
-constexpr int RANGE_SEG_LOG2 = 19;
+// ones: 2^19 bits), and numbers per piece of an interval call.  Pieces
+// whose sieving primes stay below 2^20, or that have fewer than 256 such
+// segments, use segments of RANGE_SEG_SMALL numbers (more workgroups for
+// less work each).
+constexpr int RANGE_SEG_LOG2 = 20;
 constexpr uint64_t RANGE_SEG = (uint64_t)1 << RANGE_SEG_LOG2;
+constexpr uint64_t RANGE_SEG_SMALL = RANGE_SEG / 2;
 constexpr uint64_t RANGE_PIECE = (uint64_t)1 << 30;
 constexpr int RANGE_PRIME_LOG2 = 25;      // interval sieve primes: the odd primes below 2^25
 constexpr int RANGE_PARTIAL_LOG2 = 22;    // primes used where the sieve cannot be complete
 constexpr int RANGE_MAX_PRIMES = 2063689; // odd primes below 2^25: 2063688
 constexpr int RANGE_LIST_GROUPS = 512;    // workgroups of the list build
-// bucket mode: primes above this come as precomputed hits (at most one per
-// segment of RANGE_SEG numbers); 2^20 rather than 2^19 leaves the primes
-// just above the segment length to the segment kernel, which is cheaper for
-// them than their scattered hits (6% at 2^48 .. 2^50, about 1% higher up;
-// 2^21 gains nothing more)
+// bucket mode (segments of RANGE_SEG numbers): primes above this come as
+// precomputed hits (at most one per segment); the primes just above half
+// the segment length are cheaper for the segment kernel than their
+// scattered hits (measured with segments of 2^19 numbers: 2^20 beat 2^19 by
+// 6% at 2^48 .. 2^50, about 1% higher up; 2^21 gained nothing more)
 constexpr uint32_t BUCKET_SMALL = (uint32_t)1 << 20;
-constexpr int MAX_BUCKET_SEGS = (int)(RANGE_PIECE / RANGE_SEG);  // 2048
+constexpr int MAX_BUCKET_SEGS = (int)(RANGE_PIECE / RANGE_SEG);  // 1024
 constexpr int MAX_BUCKET_GROUPS = 512;
 constexpr int BUCKET_FROM_LOG2 = 23;  // bucket mode for pieces whose root exceeds 2^23
 

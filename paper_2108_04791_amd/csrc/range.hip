@@ -11,15 +11,18 @@
 // bucket mode (below): the primes above 2^20 up to the square root are
 // sorted into per-segment buckets first, and the segments are complete
 // again.  A short piece is sieved by the odd primes below 2^22 (below 2^18
-// when it has fewer than 256 full segments; it is then cut into up to 256
-// shorter ones, since so few workgroups would wait on the sieve's latency)
+// when it has fewer than 256 full segments of 2^19 numbers; it is then cut
+// into up to 256 shorter ones, since so few workgroups would wait on the
+// sieve's latency)
 // and the survivors (about 3.4% of the numbers with no factor below 2^22,
 // 4.5% below 2^18) go to the same two Miller-Rabin kernels as array inputs,
 // through the same per-workgroup regions and counts.
 //
 // Segment layout: workgroup g covers numbers [lo + g*chunk, lo + (g+1)*chunk)
 // with chunk = classify_chunk(len, grid) (a multiple of 64, at most
-// RANGE_SEG); bit j of its LDS bitset stands for the odd number o0 + 2j.
+// RANGE_SEG = 2^20: that in bucket mode and where the sieving primes pass
+// 2^20 over at least 256 segments, else at most 2^19); bit j of its LDS
+// bitset stands for the odd number o0 + 2j.
 // The multiples of 3 .. 31 come from periodic word masks (pre-sieve);
 // primes 37 .. 8191 are crossed off by whole wavefronts (lane l takes the
 // multiples l, l+64, ... of the stride), larger primes one per thread.  The
@@ -227,7 +230,7 @@ struct RangeArgs {
 
 __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
 {
-    constexpr int MAX_WORDS = (int)(RANGE_SEG / 64);  // 2^13 words of odd-number bits
+    constexpr int MAX_WORDS = (int)(RANGE_SEG / 64);  // 2^14 words of odd-number bits
     __shared__ uint32_t bits[MAX_WORDS + 1];          // + one zero word past the end
     __shared__ uint32_t wsum[RANGE_THREADS / 64];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -351,7 +354,7 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
             const uint32_t j0 = __builtin_amdgcn_readlane(jl, i);
             if (j0 == ~0u)
                 continue;
-            // bit indices below 2^18: 32-bit arithmetic
+            // bit indices below 2^19: 32-bit arithmetic
             const uint32_t stride = 64u * p;
             for (uint32_t j = j0 + (uint32_t)lane * p; j < nbits; j += stride)
                 atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
@@ -472,9 +475,10 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
 
 // ---- bucket mode: crossing off by the primes above BUCKET_SMALL ----------
 //
-// A prime p > 2^19 has at most one odd multiple in a segment of 2^19
-// numbers (BUCKET_SMALL is at least that), so visiting every such prime in every segment costs one
-// reduction per prime and segment.  Bucket mode inverts the loop (the
+// A prime p > 2^19 has at most one odd multiple in a segment of 2^20
+// numbers (bucket mode's segments; BUCKET_SMALL is above that bound), so
+// visiting every such prime in every segment costs one reduction per prime
+// and segment.  Bucket mode inverts the loop (the
 // bucket sieve of segmented sieving): the odd primes in (BUCKET_SMALL,
 // sqrt(end)] are read from the device table, each prime's odd multiples at
 // or above max(lo, p^2) are enumerated once over the whole piece, and each
@@ -531,8 +535,8 @@ struct BucketArgs {
     uint64_t hit_cap;
 };
 
-// A hit in the stream: the segment (at most MAX_BUCKET_SEGS = 2^11) above
-// the bit index (below 2^18).
+// A hit in the stream: the segment (at most MAX_BUCKET_SEGS = 2^10) above
+// the bit index (below 2^19).
 constexpr int HIT_BITS = RANGE_SEG_LOG2 - 1;
 static_assert(MAX_BUCKET_SEGS <= (1 << (32 - HIT_BITS)), "segment fits above the bit index");
 // Hits per LDS round of the scatter kernel (1024 threads x 4).
