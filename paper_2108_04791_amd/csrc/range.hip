@@ -26,9 +26,10 @@
 // The multiples of 3 .. 31 come from periodic word masks (pre-sieve);
 // primes 37 .. 8191 are crossed off by whole wavefronts (lane l takes the
 // multiples l, l+64, ... of the stride), larger primes one per thread.  The
-// first odd multiple of p at or above max(o0, p^2) needs o0 mod p, taken
-// with a precomputed floor((2^64 - 1) / p) (one 64-bit multiply-high, no
-// division).
+// first odd multiple of p at or above o0 needs o0 mod p, taken with a
+// precomputed floor((2^64 - 1) / p) (one 64-bit multiply-high, no
+// division).  The sieving primes are below 2^25 and o0 is at least 2^32, so
+// every multiple crossed off is a proper one (no start at p^2 is needed).
 //
 // Output: 16 consecutive numbers per thread per pass, consecutive threads on
 // consecutive 16-byte pieces.  Their 8 odd members are 8 consecutive bits;
@@ -307,20 +308,14 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
         }
         np = lo_i;
     }
-    // first bit index of the odd multiples of p at or above max(o0, p^2), or
+    // first bit index of the odd multiples of p at or above o0 (> p), or
     // "none" (all offsets are taken from o0, so nothing wraps near 2^64)
     const uint64_t span = s_last - o0;  // valid only when nbits > 0
     auto first_bit = [&](uint32_t p, uint64_t inv) -> uint64_t {
-        const uint64_t pp = (uint64_t)p * p;  // < 2^50, odd
-        uint64_t off;
-        if (pp >= o0) {
-            off = pp - o0;
-        } else {
-            const uint64_t r = mod_small(o0, p, inv);
-            off = r ? p - r : 0;  // o0 + off: first multiple of p at or above o0
-            if (off & 1)
-                off += p;         // o0 is odd: an odd offset gives an even multiple
-        }
+        const uint64_t r = mod_small(o0, p, inv);
+        uint64_t off = r ? p - r : 0;  // o0 + off: first multiple of p at or above o0
+        if (off & 1)
+            off += p;                   // o0 is odd: an odd offset gives an even multiple
         return off > span ? ~(uint64_t)0 : off >> 1;
     };
     // primes 37 .. 8191: one wavefront per prime
@@ -481,7 +476,8 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
 // and segment.  Bucket mode inverts the loop (the
 // bucket sieve of segmented sieving): the odd primes in (BUCKET_SMALL,
 // sqrt(end)] are read from the device table, each prime's odd multiples at
-// or above max(lo, p^2) are enumerated once over the whole piece, and each
+// or above lo (which exceeds every such prime) are enumerated once over
+// the whole piece, and each
 // becomes a hit (its bit index) in the bucket of its segment.  `groups`
 // workgroups share the primes; no global atomic is needed:
 //   0. split (one workgroup): each group's table words;
@@ -562,16 +558,13 @@ __device__ __forceinline__ double mod_double(uint64_t x, double d)
     return r >= d ? r - d : r;
 }
 
-// Offset from lo of p's first odd multiple at or above max(lo, p^2) when it
-// is below len, else len (a piece holds at most 2^30 numbers, so the offset
-// fits 32 bits).
+// Offset from lo of p's first odd multiple at or above lo when it is below
+// len, else len (a piece holds at most 2^30 numbers, so the offset fits 32
+// bits).  Bucket mode's lo exceeds its primes (lo > root), so every such
+// multiple is a proper one: starting at p^2 would only skip multiples that
+// a smaller prime also crosses off.
 __device__ __forceinline__ uint32_t bucket_first(const BucketArgs &a, uint32_t p)
 {
-    const uint64_t pp = (uint64_t)p * p;
-    if (pp >= a.lo) {
-        const uint64_t off = pp - a.lo;  // p^2 is odd
-        return off < a.len ? (uint32_t)off : (uint32_t)a.len;
-    }
     // the odd multiples of p are the numbers congruent to p mod 2p: with
     // m = lo mod 2p, the first at or above lo is lo + p - m (m <= p) or
     // lo + 3p - m (all exact in double precision: below 2^35)
@@ -1312,7 +1305,8 @@ hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsign
     a.hit_cap = hit_bound;  // the layout's room; the buffers may hold more
     if (a.nseg > (uint32_t)MAX_BUCKET_SEGS || a.w_end > (uint64_t)TABLE_WORDS ||
         a.w_end <= a.w_begin || groups == 0 || groups > (unsigned)MAX_BUCKET_GROUPS ||
-        hit_bound > rw.hit_cap || hit_bound >= ((uint64_t)1 << 32) || !ds.chunk_primes)
+        hit_bound > rw.hit_cap || hit_bound >= ((uint64_t)1 << 32) || !ds.chunk_primes ||
+        lo <= root)
         return hipErrorInvalidValue;
     const BucketLayout L = bucket_layout(a.nseg, groups, hit_bound);
     if (!L.ok || rw.count_cap < L.count_words)
@@ -1370,8 +1364,9 @@ hipError_t launch_range_sieve(uint64_t lo, uint8_t *out, uint64_t len, unsigned 
                               const Workspace &ws, const RangeWs &rw, hipStream_t s,
                               int partial_log2, int complete_log2)
 {
+    // (lo >= 2^32 keeps every sieving prime, below 2^25, out of the piece)
     if (partial_log2 < 17 || partial_log2 > RANGE_PARTIAL_LOG2 || complete_log2 < partial_log2 ||
-        complete_log2 > RANGE_PRIME_LOG2)
+        complete_log2 > RANGE_PRIME_LOG2 || lo < TABLE_BOUND || chunk > RANGE_SEG)
         return hipErrorInvalidValue;
     RangeArgs a;
     a.partial_log2 = (uint32_t)partial_log2;
