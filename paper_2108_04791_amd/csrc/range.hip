@@ -1031,17 +1031,29 @@ __global__ void __launch_bounds__(1024, 8) bucket_scatter_kernel(BucketArgs a)
     }
     const uint64_t b0 = (uint64_t)a.sbase[q] + (uint64_t)t * a.tile;
     const uint64_t b1 = min((uint64_t)a.sbase[q] + a.filled[q], b0 + a.tile);
+    // each round's hits are loaded while the round before is sorted
+    uint32_t next[PER];
+    auto load = [&](uint64_t r0) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const uint64_t i = r0 + threadIdx.x + k * blockDim.x;
+            next[k] = i < b1 ? a.stream[i] : 0u;
+        }
+    };
+    load(b0);
     __syncthreads();
     for (uint64_t r0 = b0; r0 < b1; r0 += BUCKET_SORT_SUB) {
         const uint32_t n = (uint32_t)min((uint64_t)BUCKET_SORT_SUB, b1 - r0);
         uint32_t v[PER], rank[PER];
 #pragma unroll
+        for (int k = 0; k < PER; ++k)
+            v[k] = next[k];
+        load(r0 + BUCKET_SORT_SUB);
+#pragma unroll
         for (int k = 0; k < PER; ++k) {
             const uint32_t i = threadIdx.x + k * blockDim.x;
-            v[k] = 0;
             rank[k] = 0;
             if (i < n) {
-                v[k] = a.stream[r0 + i];
                 // (the clamp only keeps LDS indices inside the array: every
                 // entry was written by the fill pass with its segment)
                 v[k] = min(v[k] >> HIT_BITS, nseg - 1) << HIT_BITS | (v[k] & ((1u << HIT_BITS) - 1u));
