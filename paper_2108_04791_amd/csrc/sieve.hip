@@ -25,7 +25,9 @@
 //                       wavefront, lane l taking the multiples l, l+64,
 //                       l+128, ... of the stride p (in bit units), and each
 //                       larger one (at most 32 multiples per segment) by one
-//                       thread, with LDS atomic ANDs.
+//                       thread, with LDS atomic ANDs.  The first multiples
+//                       come from 32-bit remainders, 64 primes at a time
+//                       in a wavefront's lanes.
 #include "internal.h"
 #include "mont.h"
 
@@ -121,33 +123,46 @@ __global__ void __launch_bounds__(SIEVE_THREADS) sieve_kernel(uint32_t *__restri
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
-    // the wavefront index as a scalar, so the per-prime work of the
-    // wavefront loop runs on the scalar unit
+    // the wavefront index as a scalar (the wavefront loop below is uniform)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
     const int np = (int)*pcount;
     const uint64_t hi = (uint64_t)lo + 2ull * SEG_BITS;  // exclusive
     // bit index of p's first odd multiple at or above max(p^2, lo), or
-    // SEG_BITS or more when none falls in the segment (lo + p - 1 < 2^32:
-    // lo <= 2^32 - 2^19 + 1 and p < 2^16)
+    // SEG_BITS when none falls in the segment (32-bit remainders: lo < 2^32)
     auto first_bit = [&](uint32_t p) -> uint32_t {
         const uint64_t pp = (uint64_t)p * p;
         if (pp >= hi)
             return (uint32_t)SEG_BITS;
-        uint64_t start = pp;
-        if (pp < lo)
-            start = (uint64_t)(((lo + p - 1) / p) | 1u) * p;  // odd multiples only
-        return (uint32_t)((start - lo) >> 1);
+        if (pp >= lo)
+            return (uint32_t)((pp - lo) >> 1);  // p^2 is odd
+        const uint32_t r = lo % p;
+        uint32_t off = r ? p - r : 0u;  // lo + off: the first multiple at or above lo
+        if (off & 1u)
+            off += p;  // lo is odd: an odd offset gives an even multiple
+        return off >> 1;
     };
-    // primes 37 .. 8191 (the first 1027 odd primes): one wavefront per prime
+    // primes 37 .. 8191 (the first 1027 odd primes): one wavefront per
+    // prime.  The wavefront's primes are k = FIRST_CROSSED + wave + m nwaves;
+    // their first bits are computed 64 at a time, one per lane, and each
+    // crossing loop takes its prime and start from a lane (the remainders
+    // run on the vector units, not on the compute unit's one scalar unit).
     constexpr int WAVE_PRIMES = 1027;
     const int k_split = np < WAVE_PRIMES ? np : WAVE_PRIMES;
-    for (int k = FIRST_CROSSED + wave; k < k_split; k += nwaves) {
-        const uint32_t p = primes[k];
-        if ((uint64_t)p * p >= hi)
-            break;  // primes increase, so every later one starts beyond too
-        for (uint32_t j = first_bit(p) + (uint32_t)lane * p; j < (uint32_t)SEG_BITS; j += 64u * p)
-            atomicAnd(&seg[j >> 5], ~(1u << (j & 31)));
+    for (int kb = FIRST_CROSSED + wave; kb < k_split; kb += 64 * nwaves) {
+        const int k = kb + lane * nwaves;
+        uint32_t pl = 0, jl = (uint32_t)SEG_BITS;
+        if (k < k_split) {
+            pl = primes[k];
+            jl = first_bit(pl);
+        }
+        const int cnt = min(64, (k_split - kb + nwaves - 1) / nwaves);
+        for (int i = 0; i < cnt; ++i) {
+            const uint32_t p = __builtin_amdgcn_readlane(pl, i);
+            const uint32_t j0 = __builtin_amdgcn_readlane(jl, i);
+            for (uint32_t j = j0 + (uint32_t)lane * p; j < (uint32_t)SEG_BITS; j += 64u * p)
+                atomicAnd(&seg[j >> 5], ~(1u << (j & 31)));
+        }
     }
     // larger primes: at most 32 multiples in the segment, one thread each
     for (int k = k_split + (int)threadIdx.x; k < np; k += blockDim.x) {
