@@ -130,7 +130,8 @@ struct StreamWs {
     RangeWs rws;    // interval buckets
 };
 
-void free_range_ws(RangeWs &rw)
+// The bucket buffers only (the residues stay).
+void free_bucket_ws(RangeWs &rw)
 {
     if (rw.counts)
         (void)hipFree(rw.counts);
@@ -138,7 +139,29 @@ void free_range_ws(RangeWs &rw)
         (void)hipFree(rw.hits);
     if (rw.stream)
         (void)hipFree(rw.stream);
+    rw.counts = rw.hits = rw.stream = nullptr;
+    rw.count_cap = rw.hit_cap = 0;
+}
+
+void free_range_ws(RangeWs &rw)
+{
+    free_bucket_ws(rw);
+    if (rw.res)
+        (void)hipFree(rw.res);
     rw = RangeWs();
+}
+
+// The residue buffer of `rw` (RANGE_MAX_PRIMES words, allocated once).
+int ensure_range_res(RangeWs &rw)
+{
+    if (rw.res)
+        return ISP_OK;
+    const hipError_t e = hipMalloc(&rw.res, (size_t)RANGE_MAX_PRIMES * sizeof(uint32_t));
+    if (e != hipSuccess) {
+        rw.res = nullptr;
+        return fail(e);
+    }
+    return ISP_OK;
 }
 
 // Grows `rw` to the given capacities (words); `stream` is synchronised
@@ -154,14 +177,14 @@ int ensure_range_ws(RangeWs &rw, uint64_t count_cap, uint64_t hit_cap, hipStream
         if (e != hipSuccess)
             return fail(e);
     }
-    free_range_ws(rw);
+    free_bucket_ws(rw);
     hipError_t e = hipMalloc(&rw.counts, count_cap * sizeof(uint32_t));
     if (e == hipSuccess)
         e = hipMalloc(&rw.hits, hit_cap * sizeof(uint32_t));
     if (e == hipSuccess)
         e = hipMalloc(&rw.stream, hit_cap * sizeof(uint32_t));
     if (e != hipSuccess) {
-        free_range_ws(rw);
+        free_bucket_ws(rw);
         return fail(e);
     }
     rw.count_cap = count_cap;
@@ -916,10 +939,23 @@ int isprime_range_u64(uint64_t lo, uint8_t *out, size_t len, void *stream)
     // pieces decided by the sieve alone need no survivor workspace: it is
     // allocated (or grown) only for a piece that goes to Miller-Rabin
     const Workspace none;
+    st = ensure_range_res(sw->rws);
     for (uint64_t off = below; off < len && st == ISP_OK; off += RANGE_PIECE) {
         const uint64_t piece = std::min<uint64_t>(RANGE_PIECE, len - off);
         const RangePlan pl = plan_range_piece(lo + off, piece);
-        hipError_t e = hipSuccess;
+        // the piece's residues modulo every prime its segments sieve by:
+        // those up to the root, the primes up to BUCKET_SMALL in bucket mode,
+        // and for Miller-Rabin pieces those below 2^partial_log2 or, in a
+        // segment whose root is below 2^complete_log2, up to that root
+        const uint64_t bound =
+            pl.bucket ? std::min<uint64_t>(pl.root, BUCKET_SMALL)
+                      : std::max<uint64_t>(std::min<uint64_t>(pl.root, ((uint64_t)1 << pl.complete_log2) - 1),
+                                           ((uint64_t)1 << pl.partial_log2) - 1);
+        hipError_t e = launch_range_residues(lo + off, bound, ds, sw->rws.res, s);
+        if (e != hipSuccess) {
+            st = fail(e);
+            break;
+        }
         if (pl.bucket) {
             st = ensure_range_ws(sw->rws, pl.count_words, pl.hit_words, s);
             if (st != ISP_OK)
@@ -1155,7 +1191,9 @@ size_t isp_range_workspace_bytes(uint64_t lo, size_t len)
         else if (!p.complete)
             mr = std::max(mr, isp_workspace_bytes(piece));
     }
-    return mr + buckets;
+    // and the residues of the sieving primes, for any piece above 2^32
+    const size_t res = below < len ? (size_t)RANGE_MAX_PRIMES * sizeof(uint32_t) : 0;
+    return mr + buckets + res;
 }
 
 int isp_last_device_error(void) { return g_last_err.load(); }

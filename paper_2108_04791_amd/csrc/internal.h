@@ -221,6 +221,8 @@ struct RangeWs {
     uint32_t *hits = nullptr;    // hit_cap words
     uint32_t *stream = nullptr;  // hit_cap words: the fill pass's output, sorted into hits
     uint64_t count_cap = 0, hit_cap = 0;
+    // each piece's residues modulo the sieving primes (RANGE_MAX_PRIMES words)
+    uint32_t *res = nullptr;
 };
 
 struct Workspace {
@@ -274,6 +276,10 @@ BucketLayout bucket_layout(uint32_t nseg, unsigned groups, uint64_t hit_cap);
 hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsigned groups,
                                 uint64_t hit_bound, const DeviceState &ds, const RangeWs &rw,
                                 hipStream_t s);
+// res[k] = (lo | 1) mod (k-th interval prime) for every prime up to bound
+// (rw.res of the piece's stream, before the sieve kernel reads it).
+hipError_t launch_range_residues(uint64_t lo, uint64_t bound, const DeviceState &ds,
+                                 uint32_t *res, hipStream_t s);
 // Without buckets, a segment whose square root is below 2^complete_log2
 // (partial_log2 .. RANGE_PRIME_LOG2) is decided by the sieve alone; the others
 // are sieved by the primes below 2^partial_log2 (17 .. RANGE_PARTIAL_LOG2)

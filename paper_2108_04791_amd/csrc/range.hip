@@ -37,6 +37,9 @@
 // bit i to byte 2i (or 2i + 1), and the piece goes out as one 16-byte store.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+
 #include "internal.h"
 
 namespace isp {
@@ -215,6 +218,7 @@ struct RangeArgs {
     uint8_t *out;        // out[i] <-> lo + i
     const uint32_t *primes;
     const uint64_t *inv;
+    const uint32_t *res;  // res[k] = (lo | 1) mod primes[k] for every prime the piece uses
     uint32_t nprimes;
     Survivor *surv;      // grid regions of `chunk` entries
     uint32_t *counts;    // [grid]
@@ -309,15 +313,24 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
         np = lo_i;
     }
     // first bit index of the odd multiples of p at or above o0 (> p), or
-    // "none" (all offsets are taken from o0, so nothing wraps near 2^64)
+    // "none" (all offsets are taken from o0, so nothing wraps near 2^64).
+    // o0 = (lo | 1) + r0 (the chunk is even), so o0 mod p is the piece's
+    // residue res[k] plus r0 mod p; r0 < 2^30 is reduced with m = floor(2^32
+    // / p), the high word of floor((2^64 - 1) / p) (p odd): the estimate
+    // umulhi(r0, m) is floor(r0 / p) or one less, leaving a remainder below 2p
     const uint64_t span = s_last - o0;  // valid only when nbits > 0
-    auto first_bit = [&](uint32_t p, uint64_t inv) -> uint64_t {
-        const uint64_t r = mod_small(o0, p, inv);
-        uint64_t off = r ? p - r : 0;  // o0 + off: first multiple of p at or above o0
-        if (off & 1)
-            off += p;                   // o0 is odd: an odd offset gives an even multiple
-        return off > span ? ~(uint64_t)0 : off >> 1;
+    const uint32_t off0 = (uint32_t)r0;
+    auto first_bit = [&](uint32_t p, uint32_t m, uint32_t res) -> uint32_t {
+        uint32_t u = off0 - __umulhi(off0, m) * p;
+        u = u >= p ? u - p : u;
+        uint32_t r = res + u;  // o0 mod p, before one subtraction
+        r = r >= p ? r - p : r;
+        uint32_t off = r ? p - r : 0u;  // o0 + off: first multiple of p at or above o0
+        if (off & 1u)
+            off += p;                    // o0 is odd: an odd offset gives an even multiple
+        return (uint64_t)off > span ? ~0u : off >> 1;
     };
+    const uint32_t *inv_hi = reinterpret_cast<const uint32_t *>(a.inv) + 1;  // [2k]: high words
     // primes 37 .. 8191: one wavefront per prime
     uint32_t k_split;
     {
@@ -340,8 +353,8 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
         uint32_t pl = 0, jl = ~0u;
         if (k < k_split) {
             pl = a.primes[k];
-            const uint64_t j0 = first_bit(pl, a.inv[k]);
-            jl = j0 < nbits ? (uint32_t)j0 : ~0u;
+            const uint32_t j0 = first_bit(pl, inv_hi[2 * k], a.res[k]);
+            jl = j0 < nbits ? j0 : ~0u;
         }
         const uint32_t cnt = min(64u, (k_split - kb + nwaves - 1) / nwaves);
         for (uint32_t i = 0; i < cnt; ++i) {
@@ -360,27 +373,26 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
     // latency, not the arithmetic, bounds this loop)
     {
         uint32_t k = k_split + tid;
-        uint32_t p = 0;
-        uint64_t inv = 0;
+        uint32_t p = 0, m = 0, rs = 0;
         if (k < np) {
             p = a.primes[k];
-            inv = a.inv[k];
+            m = inv_hi[2 * k];
+            rs = a.res[k];
         }
         while (k < np) {
             const uint32_t kn = k + blockDim.x;
-            uint32_t pn = 0;
-            uint64_t invn = 0;
+            uint32_t pn = 0, mn = 0, rsn = 0;
             if (kn < np) {
                 pn = a.primes[kn];
-                invn = a.inv[kn];
+                mn = inv_hi[2 * kn];
+                rsn = a.res[kn];
             }
-            const uint64_t j0 = first_bit(p, inv);
-            if (j0 < nbits)
-                for (uint32_t j = (uint32_t)j0; j < nbits; j += p)
-                    atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
+            for (uint32_t j = first_bit(p, m, rs); j < nbits; j += p)
+                atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
             k = kn;
             p = pn;
-            inv = invn;
+            m = mn;
+            rs = rsn;
         }
     }
     // bucket mode: the hits of the primes above BUCKET_SMALL in this segment,
@@ -1246,6 +1258,35 @@ hipError_t launch_chunk_primes(DeviceState &ds, hipStream_t s)
     return hipGetLastError();
 }
 
+namespace {
+
+// The piece's residues: res[k] = base mod primes[k] for k < count.
+__global__ void __launch_bounds__(256) range_residue_kernel(uint64_t base,
+                                                           const uint32_t *__restrict__ primes,
+                                                           const uint64_t *__restrict__ inv,
+                                                           uint32_t count, uint32_t *__restrict__ res)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < count)
+        res[k] = (uint32_t)mod_small(base, primes[k], inv[k]);
+}
+
+}  // namespace
+
+hipError_t launch_range_residues(uint64_t lo, uint64_t bound, const DeviceState &ds,
+                                 uint32_t *res, hipStream_t s)
+{
+    // at most pi(bound) < 1.25506 bound / ln bound primes (Rosser and
+    // Schoenfeld, Illinois J. Math. 6, 1962), all of them below 100
+    uint64_t count = bound < 100 ? 25 : (uint64_t)(1.25506 * (double)bound / std::log((double)bound)) + 1;
+    count = std::min<uint64_t>(count, (uint64_t)ds.num_range_primes);
+    if (!res || count == 0)
+        return hipErrorInvalidValue;
+    range_residue_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(
+        lo | 1, ds.range_primes, ds.range_inv, (uint32_t)count, res);
+    return hipGetLastError();
+}
+
 hipError_t launch_range_primes(DeviceState &ds, hipStream_t s)
 {
     range_count_kernel<<<RANGE_LIST_GROUPS, 256, 0, s>>>(ds.table, ds.range_count);
@@ -1376,9 +1417,11 @@ hipError_t launch_range_sieve(uint64_t lo, uint8_t *out, uint64_t len, unsigned 
                               const Workspace &ws, const RangeWs &rw, hipStream_t s,
                               int partial_log2, int complete_log2)
 {
-    // (lo >= 2^32 keeps every sieving prime, below 2^25, out of the piece)
+    // (lo >= 2^32 keeps every sieving prime, below 2^25, out of the piece;
+    // an even chunk keeps o0 = (lo | 1) + segment offset)
     if (partial_log2 < 17 || partial_log2 > RANGE_PARTIAL_LOG2 || complete_log2 < partial_log2 ||
-        complete_log2 > RANGE_PRIME_LOG2 || lo < TABLE_BOUND || chunk > RANGE_SEG)
+        complete_log2 > RANGE_PRIME_LOG2 || lo < TABLE_BOUND || chunk > RANGE_SEG || (chunk & 1) ||
+        !rw.res || len > RANGE_PIECE)
         return hipErrorInvalidValue;
     RangeArgs a;
     a.partial_log2 = (uint32_t)partial_log2;
@@ -1393,6 +1436,7 @@ hipError_t launch_range_sieve(uint64_t lo, uint8_t *out, uint64_t len, unsigned 
     a.out = out;
     a.primes = ds.range_primes;
     a.inv = ds.range_inv;
+    a.res = rw.res;
     a.nprimes = (uint32_t)ds.num_range_primes;
     a.surv = ws.surv;
     a.counts = ws.counts;

@@ -64,14 +64,18 @@ def test_argument_errors_without_device(isp):
 
 def test_range_workspace_by_mode(isp):
     """An interval call holds survivor workspace only for pieces that go to
-    Miller-Rabin, and bucket workspace only for bucket-mode pieces."""
+    Miller-Rabin, and bucket workspace only for bucket-mode pieces; above
+    2^32 also one residue word per interval prime (2,063,688 odd primes
+    below 2^25, one word to spare)."""
     W = isp.lib().isp_range_workspace_bytes
+    res = 4 * 2063689
     assert W(0, 1 << 20) == 0                      # below 2^32: the table
-    assert W(1 << 34, 1 << 28) == 0                # complete segment sieve
-    assert W(1 << 44, 1 << 30) == 0
-    assert W(1 << 63, 1 << 24) == isp.workspace_bytes(1 << 24)  # short: Miller-Rabin
+    assert W(1 << 34, 1 << 28) == res              # complete segment sieve
+    assert W(1 << 44, 1 << 30) == res
+    assert W((1 << 32) - 10, 20) == res            # crosses 2^32
+    assert W(1 << 63, 1 << 24) == isp.workspace_bytes(1 << 24) + res  # short: Miller-Rabin
     b = W(1 << 62, 1 << 30)                        # bucket mode, no survivors
-    assert 0 < b < 3 << 30 and b < isp.workspace_bytes(1 << 28)
+    assert res < b < 3 << 30 and b < isp.workspace_bytes(1 << 28)
     assert W((1 << 64) - 5, 10) == 0                # passes 2^64 - 1
     assert W(5, 0) == 0
 
