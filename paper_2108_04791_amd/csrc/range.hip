@@ -368,31 +368,42 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
                 atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
         }
     }
-    // larger primes: one thread per prime; the thread's next prime and its
-    // constant are loaded while the current one is crossed off (the loads'
-    // latency, not the arithmetic, bounds this loop)
+    // larger primes: one thread per prime, four at a time; the thread's next
+    // four primes and their constants are loaded while the current ones are
+    // crossed off (the loads' latency, not the arithmetic, bounds this loop:
+    // at 2^44, one workgroup per CU, four in flight instead of one took the
+    // 2^28-number interval from 0.241 to 0.203 ms)
     {
-        uint32_t k = k_split + tid;
-        uint32_t p = 0, m = 0, rs = 0;
-        if (k < np) {
-            p = a.primes[k];
-            m = inv_hi[2 * k];
-            rs = a.res[k];
-        }
-        while (k < np) {
-            const uint32_t kn = k + blockDim.x;
-            uint32_t pn = 0, mn = 0, rsn = 0;
-            if (kn < np) {
-                pn = a.primes[kn];
-                mn = inv_hi[2 * kn];
-                rsn = a.res[kn];
+        constexpr int U = 4;
+        const uint32_t stride = blockDim.x;
+        uint32_t p[U], m[U], rs[U];
+        auto load = [&](uint32_t kb) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t k = kb + u * stride;
+                p[u] = m[u] = rs[u] = 0;
+                if (k < np) {
+                    p[u] = a.primes[k];
+                    m[u] = inv_hi[2 * k];
+                    rs[u] = a.res[k];
+                }
             }
-            for (uint32_t j = first_bit(p, m, rs); j < nbits; j += p)
-                atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
-            k = kn;
-            p = pn;
-            m = mn;
-            rs = rsn;
+        };
+        load(k_split + tid);
+        for (uint32_t kb = k_split + tid; kb < np; kb += U * stride) {
+            uint32_t cp[U], cm[U], cr[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                cp[u] = p[u];
+                cm[u] = m[u];
+                cr[u] = rs[u];
+            }
+            load(kb + U * stride);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (kb + u * stride < np)
+                    for (uint32_t j = first_bit(cp[u], cm[u], cr[u]); j < nbits; j += cp[u])
+                        atomicAnd(&bits[j >> 5], ~(1u << (j & 31)));
         }
     }
     // bucket mode: the hits of the primes above BUCKET_SMALL in this segment,
