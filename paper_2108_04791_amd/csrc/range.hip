@@ -408,18 +408,27 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
     }
     // bucket mode: the hits of the primes above BUCKET_SMALL in this segment,
     // one contiguous run (the clamp only keeps reads inside the allocation),
-    // eight per thread and round, all read before any is applied
+    // eight per thread and round, all read before any is applied and the
+    // next round's read while this one is
     if (buckets) {
         const uint32_t h0 = a.hit_start[blockIdx.x];
         const uint32_t h1 = (uint32_t)min((uint64_t)a.hit_start[blockIdx.x + 1], a.hit_cap);
         constexpr int UNROLL = 8;
-        for (uint32_t h = h0 + tid; h < h1; h += UNROLL * blockDim.x) {
-            uint32_t j[UNROLL];
+        uint32_t next[UNROLL];
+        auto load = [&](uint64_t h) {
 #pragma unroll
             for (int k = 0; k < UNROLL; ++k) {
-                const uint32_t i = h + k * blockDim.x;
-                j[k] = i < h1 ? a.hits[i] : ~0u;
+                const uint64_t i = h + (uint64_t)k * blockDim.x;
+                next[k] = i < h1 ? a.hits[i] : ~0u;
             }
+        };
+        load(h0 + tid);
+        for (uint64_t h = h0 + tid; h < h1; h += (uint64_t)UNROLL * blockDim.x) {
+            uint32_t j[UNROLL];
+#pragma unroll
+            for (int k = 0; k < UNROLL; ++k)
+                j[k] = next[k];
+            load(h + (uint64_t)UNROLL * blockDim.x);
 #pragma unroll
             for (int k = 0; k < UNROLL; ++k)
                 if (j[k] < nbits)
