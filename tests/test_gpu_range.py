@@ -16,7 +16,8 @@ pytestmark = pytest.mark.gpu
 
 U64 = (1 << 64) - 1
 NTHREADS = min(16, os.cpu_count() or 1)
-SEG = 1 << 19      # numbers per workgroup segment
+SEG = 1 << 19      # numbers per workgroup segment (2^20 in bucket mode and for long pieces whose primes pass 2^20)
+SEG20 = 1 << 20
 PIECE = 1 << 30    # numbers per piece of one call
 
 
@@ -138,14 +139,16 @@ def test_empty_and_invalid(isp):
 
 @pytest.mark.parametrize("lo,length", [((1 << 34) + 1, (1 << 27) + 5 * SEG + 3),
                                        ((1 << 44) + 3, 1 << 27),
+                                       ((1 << 44) + 3, (1 << 28) + 3 * SEG20 + 12345),
                                        ((1 << 50) - (1 << 26) - 5, 1 << 27)])
 def test_long_complete_pieces(isp, lo, length):
     """Intervals of at least 256 segments: below 2^50 every segment is
     complete, crossed off by all the primes up to its square root (2^17,
-    2^22, 2^25); the last interval crosses 2^50, where the segments switch to
-    the primes below 2^22 and Miller-Rabin.  The whole interval equals the
-    array call, and a sample (both ends and 20,000 random positions) equals
-    the oracle."""
+    2^22, 2^25); the third interval runs segments of 2^20 numbers (at least
+    256 of them, primes past 2^20) with a ragged last one; the last interval
+    crosses 2^50, where the segments switch to the primes below 2^22 and
+    Miller-Rabin.  The whole interval equals the array call, and a sample
+    (both ends and 20,000 random positions) equals the oracle."""
     got = isp.isprime_range(lo, length)
     arr = torch.arange(lo, lo + length, dtype=torch.int64, device="cuda")
     assert torch.equal(isp.isprime(arr), got)
@@ -158,6 +161,7 @@ def test_long_complete_pieces(isp, lo, length):
 
 
 @pytest.mark.parametrize("lo,length", [((1 << 56) + 12345, 1 << 26), ((1 << 62) - 3, 1 << 28),
+                                       ((1 << 60) + 7, (1 << 27) + 3 * SEG20 + 999),
                                        ((1 << 64) - (1 << 29), 1 << 29)])
 def test_bucket_mode_high_magnitude(isp, lo, length):
     """Intervals far above 2^50 that are long next to the number of primes up
