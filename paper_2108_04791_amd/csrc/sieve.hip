@@ -177,7 +177,10 @@ __global__ void __launch_bounds__(SIEVE_THREADS) sieve_kernel(uint32_t *__restri
 
 // The wheel table, one thread per 32-bit word: bit b stands for the number
 // 210 floor(b / 48) + res[b mod 48], whose bit is read from the odd-only
-// table (0 for the numbers of the last block at or above 2^32).
+// table (0 for the numbers of the last block at or above 2^32).  A word's 32
+// numbers increase and span at most 142 (the largest distance between a
+// residue coprime to 210 and the 31st after it, around the cycle), so their
+// table bits lie in four consecutive table words, read once.
 __global__ void __launch_bounds__(256) wheel_table_kernel(uint32_t *__restrict__ wtable,
                                                           const uint32_t *__restrict__ table)
 {
@@ -188,13 +191,25 @@ __global__ void __launch_bounds__(256) wheel_table_kernel(uint32_t *__restrict__
     const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= WHEEL_WORDS)
         return;
+    const uint32_t b0 = (uint32_t)(w * 32);  // < 2^30
+    uint32_t q = b0 / WHEEL_RES, r = b0 - q * WHEEL_RES;
+    const uint64_t t0 = ((uint64_t)q * WHEEL_MOD + res[r]) >> 6;  // the first number's table word
+    uint32_t tw[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        tw[i] = t0 + i < TABLE_WORDS ? table[t0 + i] : 0u;
+    const uint64_t lo64 = tw[0] | (uint64_t)tw[1] << 32, hi64 = tw[2] | (uint64_t)tw[3] << 32;
     uint32_t word = 0;
     for (uint32_t j = 0; j < 32; ++j) {
-        const uint64_t b = w * 32 + j;
-        const uint64_t q = b / WHEEL_RES;
-        const uint64_t v = q * WHEEL_MOD + res[b - q * WHEEL_RES];
+        const uint64_t v = (uint64_t)q * WHEEL_MOD + res[r];
+        const uint32_t idx = (uint32_t)((v >> 1) - (t0 << 5));  // below 103
+        const uint64_t bits = idx < 64 ? lo64 >> idx : hi64 >> (idx - 64);
         if (v < TABLE_BOUND)
-            word |= ((table[v >> 6] >> ((v >> 1) & 31)) & 1u) << j;
+            word |= (uint32_t)(bits & 1u) << j;
+        if (++r == WHEEL_RES) {
+            r = 0;
+            ++q;
+        }
     }
     wtable[w] = word;
 }
