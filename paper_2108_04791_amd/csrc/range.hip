@@ -1044,22 +1044,32 @@ __global__ void __launch_bounds__(256) bucket_starts_kernel(BucketArgs a)
 // out so that consecutive threads write consecutive places of one bucket;
 // each segment's cursor starts at the tile's scanned count and moves past
 // each round's hits.  The order of hits within a bucket is free (the sieve
-// clears each hit's bit).  Launched with 1024 threads (nseg <= 2 x 1024).
+// clears each hit's bit).  Launched with 1024 threads (nseg <=
+// MAX_BUCKET_SEGS).
 __global__ void __launch_bounds__(1024, 8) bucket_scatter_kernel(BucketArgs a)
 {
-    __shared__ uint32_t cursor[MAX_BUCKET_SEGS];
-    __shared__ uint32_t toff[MAX_BUCKET_SEGS + 1];
+    // Double-buffered per round (b = the round's parity): cnt[b] counts the
+    // round's hits per segment, off[b] is its exclusive scan, cur[b] each
+    // segment's next place.  Round r touches cnt/off/cur[b] and prepares
+    // cnt[b ^ 1] (zeroed) and cur[b ^ 1] (advanced); with the buffers of the
+    // next round apart, three barriers per round order every access.
+    __shared__ uint32_t cnt[2][MAX_BUCKET_SEGS];
+    __shared__ uint32_t off[2][MAX_BUCKET_SEGS];
+    __shared__ uint32_t cur[2][MAX_BUCKET_SEGS];
     __shared__ uint32_t sorted[BUCKET_SORT_SUB];
-    __shared__ uint32_t wsum[16];
     constexpr int PER = BUCKET_SORT_SUB / 1024;
+    constexpr int SCAN_PER = MAX_BUCKET_SEGS / 64;  // segments per lane of the one-wavefront scan
+    static_assert(MAX_BUCKET_SEGS % 64 == 0, "the scan's lanes cover the segments");
     uint32_t q, t, nt;
     if (!bucket_tile_of(a, blockIdx.x, q, t, nt))
         return;
-    const uint32_t nseg = a.nseg;
+    const uint32_t nseg = a.nseg;  // <= MAX_BUCKET_SEGS
+    const uint32_t mask = (1u << HIT_BITS) - 1u;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (uint32_t g = threadIdx.x; g < nseg; g += blockDim.x) {
-        cursor[g] = a.tcounts[bucket_count_at(a, g, blockIdx.x)];
-        toff[g] = 0;
+        cur[0][g] = a.tcounts[bucket_count_at(a, g, blockIdx.x)];
+        cnt[0][g] = 0;
+        cnt[1][g] = 0;
     }
     const uint64_t b0 = (uint64_t)a.sbase[q] + (uint64_t)t * a.tile;
     const uint64_t b1 = min((uint64_t)a.sbase[q] + a.filled[q], b0 + a.tile);
@@ -1074,7 +1084,8 @@ __global__ void __launch_bounds__(1024, 8) bucket_scatter_kernel(BucketArgs a)
     };
     load(b0);
     __syncthreads();
-    for (uint64_t r0 = b0; r0 < b1; r0 += BUCKET_SORT_SUB) {
+    uint32_t b = 0;
+    for (uint64_t r0 = b0; r0 < b1; r0 += BUCKET_SORT_SUB, b ^= 1u) {
         const uint32_t n = (uint32_t)min((uint64_t)BUCKET_SORT_SUB, b1 - r0);
         uint32_t v[PER], rank[PER];
 #pragma unroll
@@ -1086,19 +1097,23 @@ __global__ void __launch_bounds__(1024, 8) bucket_scatter_kernel(BucketArgs a)
             const uint32_t i = threadIdx.x + k * blockDim.x;
             rank[k] = 0;
             if (i < n) {
-                // (the clamp only keeps LDS indices inside the array: every
+                // (the clamp only keeps LDS indices inside the arrays: every
                 // entry was written by the fill pass with its segment)
-                v[k] = min(v[k] >> HIT_BITS, nseg - 1) << HIT_BITS | (v[k] & ((1u << HIT_BITS) - 1u));
-                rank[k] = atomicAdd(&toff[v[k] >> HIT_BITS], 1u);
+                v[k] = min(v[k] >> HIT_BITS, nseg - 1) << HIT_BITS | (v[k] & mask);
+                rank[k] = atomicAdd(&cnt[b][v[k] >> HIT_BITS], 1u);
             }
         }
-        __syncthreads();  // the round's counts are in toff
-        // exclusive scan of toff[0 .. nseg) in place, two consecutive
-        // entries per thread
-        {
-            const uint32_t g0 = 2 * threadIdx.x;
-            const uint32_t c0 = g0 < nseg ? toff[g0] : 0u, c1 = g0 + 1 < nseg ? toff[g0 + 1] : 0u;
-            const uint32_t local = c0 + c1;
+        __syncthreads();  // the round's counts are in cnt[b]
+        if (wave == 0) {
+            // exclusive scan of cnt[b] into off[b], SCAN_PER consecutive
+            // segments per lane
+            const uint32_t g0 = (uint32_t)lane * SCAN_PER;
+            uint32_t c[SCAN_PER], local = 0;
+#pragma unroll
+            for (int j = 0; j < SCAN_PER; ++j) {
+                c[j] = g0 + j < nseg ? cnt[b][g0 + j] : 0u;
+                local += c[j];
+            }
             uint32_t incl = local;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
@@ -1106,26 +1121,23 @@ __global__ void __launch_bounds__(1024, 8) bucket_scatter_kernel(BucketArgs a)
                 if (lane >= o)
                     incl += y;
             }
-            if (lane == 63)
-                wsum[wave] = incl;
-            __syncthreads();
             uint32_t run = incl - local;
-            for (int w = 0; w < wave; ++w)
-                run += wsum[w];
-            if (g0 < nseg)
-                toff[g0] = run;
-            if (g0 + 1 < nseg)
-                toff[g0 + 1] = run + c0;
-            if (threadIdx.x == 0)
-                toff[nseg] = n;
+#pragma unroll
+            for (int j = 0; j < SCAN_PER; ++j) {
+                if (g0 + j < nseg)
+                    off[b][g0 + j] = run;
+                run += c[j];
+            }
         }
-        __syncthreads();  // toff: the round's offset of each segment
+        __syncthreads();  // off[b]: each segment's offset in this round
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const uint32_t i = threadIdx.x + k * blockDim.x;
             if (i < n)
-                sorted[toff[v[k] >> HIT_BITS] + rank[k]] = v[k];
+                sorted[off[b][v[k] >> HIT_BITS] + rank[k]] = v[k];
         }
+        for (uint32_t g = threadIdx.x; g < nseg; g += blockDim.x)
+            cnt[b ^ 1u][g] = 0;  // the next round counts from zero
         __syncthreads();  // the round is in segment order
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
@@ -1133,25 +1145,13 @@ __global__ void __launch_bounds__(1024, 8) bucket_scatter_kernel(BucketArgs a)
             if (i < n) {
                 const uint32_t w = sorted[i];
                 const uint32_t g = w >> HIT_BITS;
-                const uint64_t at = (uint64_t)cursor[g] + (i - toff[g]);
+                const uint64_t at = (uint64_t)cur[b][g] + (i - off[b][g]);
                 if (at < a.hit_cap)
-                    a.hits[at] = w & ((1u << HIT_BITS) - 1u);
+                    a.hits[at] = w & mask;
             }
         }
-        // the round's count per segment, read before any thread clears toff
-        const uint32_t ga = threadIdx.x, gb = threadIdx.x + blockDim.x;
-        const uint32_t na = ga < nseg ? toff[ga + 1] - toff[ga] : 0u;
-        const uint32_t nb = gb < nseg ? toff[gb + 1] - toff[gb] : 0u;
-        __syncthreads();  // every place and count is taken from cursor and toff
-        if (ga < nseg) {
-            cursor[ga] += na;
-            toff[ga] = 0;
-        }
-        if (gb < nseg) {
-            cursor[gb] += nb;
-            toff[gb] = 0;
-        }
-        __syncthreads();  // ready for the next round
+        for (uint32_t g = threadIdx.x; g < nseg; g += blockDim.x)
+            cur[b ^ 1u][g] = cur[b][g] + cnt[b][g];
     }
 }
 
