@@ -202,20 +202,23 @@ __device__ __forceinline__ uint64_t r_mod_n(uint64_t n, int L)
     return x;
 }
 
-// 2^64 mod n for odd n >= 2^32 with bit length L, in a loop whose count is
-// the same on every lane: Lmin (wavefront-uniform, <= L) is the smallest bit
-// length in the wavefront.  A lane with n < 2^63 starts from 2^(Lmin - 1)
-// <= 2^(L - 1) < n and doubles 65 - Lmin times; for x < n < 2^63, 2x has no
-// carry and 2x >= n exactly when x >= (n + 1) / 2, so each doubling is one
-// compare, a select and one shift-and-add.  For n >= 2^63, 2^64 mod n is
-// 2^64 - n.
-__device__ __forceinline__ uint64_t r_mod_n_uniform(uint64_t n, int L, int Lmin)
+// 2^64 mod n for odd n >= 2^32 in a fixed number of instructions.  For n >=
+// 2^63 it is 2^64 - n.  Below, the quotient q = floor(2^64 / n) < 2^32 comes
+// from a double-precision estimate: n rounded to 53 bits, its reciprocal
+// from the hardware estimate refined by two Newton steps, and 2^64 times it
+// (an exact scaling) are within 2^-18 of 2^64 / n, so floor(2^64 (1/n) -
+// 1/2) is q or q - 1, and r = 2^64 - q n, formed modulo 2^64, lies in [0,
+// 2n) with 2n < 2^64: one conditional subtraction ends it.
+__device__ __forceinline__ uint64_t r_mod_n_wide(uint64_t n)
 {
-    const uint64_t half = (n >> 1) + 1, neg_n = 0 - n;
-    uint64_t x = (uint64_t)1 << (Lmin - 1);
-    for (int k = Lmin - 1; k < 64; ++k)
-        x = shl_add(x, 1, x >= half ? neg_n : 0);
-    return L == 64 ? neg_n : x;
+    const double d = (double)n;
+    double inv = __builtin_amdgcn_rcp(d);
+    inv = fma(inv, fma(-d, inv, 1.0), inv);
+    inv = fma(inv, fma(-d, inv, 1.0), inv);
+    const uint32_t q = (uint32_t)floor(fma(0x1p64, inv, -0.5));
+    uint64_t r = 0 - (uint64_t)q * n;
+    r = r >= n ? r - n : r;
+    return (int64_t)n < 0 ? 0 - n : r;
 }
 
 __device__ __forceinline__ MontCtx make_ctx(uint64_t n, int L)

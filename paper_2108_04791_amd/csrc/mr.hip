@@ -67,9 +67,8 @@ __device__ __forceinline__ int wave_max(int v)
     return acc;
 }
 
-// Extremes of the bit lengths L in [33, 64] of a wavefront's values.
+// The largest bit length L in [33, 64] of a wavefront's values.
 __device__ __forceinline__ int wave_max_len(int L) { return 33 + wave_max<5>(L - 33); }
-__device__ __forceinline__ int wave_min_len(int L) { return 64 - wave_max<5>(64 - L); }
 
 // Strong probable-prime test to base 2 for odd n >= 2^32, n - 1 = 2^s d.
 // Called with all 64 lanes of the wavefront active.
@@ -147,7 +146,7 @@ __device__ __forceinline__ bool sprp_base2(uint64_t n, MontCtx &c)
     const int Lmax = wave_max_len(L), smax = wave_max<6>(s);
     c.n = n;
     c.ninv = inv64(n);
-    c.one = r_mod_n_uniform(n, L, wave_min_len(L));
+    c.one = r_mod_n_wide(n);
     c.mone = n - c.one;
     if (Lmax <= 60)
         return sprp_base2_run<0>(n, c, e, s, L, Lmax, smax);

@@ -1,6 +1,8 @@
-"""Host checks of two pieces of arithmetic that the interval sieve's bucket
-passes run on the device (csrc/range.hip), written out here in exact Python
-arithmetic; the GPU tests (test_gpu_range.py) check the kernels' bytes.
+"""Host checks of arithmetic that the kernels run on the device, written out
+here in exact Python arithmetic: two pieces of the interval sieve's bucket
+passes (csrc/range.hip) and the Montgomery constant 2^64 mod n of the
+base-2 kernel (csrc/mont.h); the GPU tests (test_gpu_range.py,
+test_gpu_parity.py) check the kernels' bytes.
 
 1. lo mod d for 2^19 <= d < 2^34 in double precision: a reciprocal refined
    by two Newton steps, the quotient floor(lo * (1/d) - 1/2), and the
@@ -11,6 +13,9 @@ arithmetic; the GPU tests (test_gpu_range.py) check the kernels' bytes.
    prime p in (2^20, root], with the primes above (len - 1) / 2 (bound 1
    each) counted from per-chunk prime counts and the group boundaries'
    partial chunks, and the root's word counted up to root.
+3. 2^64 mod n for odd n >= 2^32: q = floor(2^64 (1/n) - 1/2) from the same
+   refined reciprocal is floor(2^64 / n) or one less, and 2^64 - q n taken
+   modulo 2^64 needs one conditional subtraction.
 """
 import math
 import random
@@ -117,3 +122,27 @@ def test_group_bounds_from_chunk_counts():
             mask = 0xFFFFFFFF if nb >= 32 else (1 << nb) - 1
             got[groups - 1] += bin(int(table[w_end - 1]) & mask).count("1")
         assert got == want, (root, length, groups)
+
+
+def _r_mod_n_wide(n, rel_err):
+    """The device's r_mod_n_wide with the reciprocal estimate off by rel_err."""
+    d = float(n)
+    inv = (1.0 / d) * (1.0 + rel_err)
+    inv = _fma(inv, _fma(-d, inv, 1.0), inv)
+    inv = _fma(inv, _fma(-d, inv, 1.0), inv)
+    q = math.floor(_fma(2.0 ** 64, inv, -0.5))
+    assert 0 <= q < 1 << 32
+    r = -(q * n) % (1 << 64)
+    r = r - n if r >= n else r
+    return (1 << 64) - n if n >= 1 << 63 else r
+
+
+def test_r_mod_n_matches_integers():
+    rng = random.Random(64)
+    for _ in range(20000):
+        n = rng.choice([rng.getrandbits(64), rng.randint(1 << 32, 1 << 40), (1 << 32) + rng.getrandbits(8),
+                        (1 << 63) - rng.getrandbits(8), (1 << 63) + rng.getrandbits(8),
+                        rng.getrandbits(rng.randint(33, 64))]) | 1
+        if n < 1 << 32:
+            continue
+        assert _r_mod_n_wide(n, rng.uniform(-2.0 ** -12, 2.0 ** -12)) == (1 << 64) % n, n
