@@ -505,18 +505,17 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
 // A prime p > 2^19 has at most one odd multiple in a segment of 2^20
 // numbers (bucket mode's segments; BUCKET_SMALL is above that bound), so
 // visiting every such prime in every segment costs one reduction per prime
-// and segment.  Bucket mode inverts the loop (the
-// bucket sieve of segmented sieving): the odd primes in (BUCKET_SMALL,
-// sqrt(end)] are read from the device table, each prime's odd multiples at
-// or above lo (which exceeds every such prime) are enumerated once over
-// the whole piece, and each
+// and segment.  Bucket mode inverts the loop (the bucket sieve of segmented
+// sieving): the odd primes in (BUCKET_SMALL, sqrt(end)] are read from the
+// device table, each prime's odd multiples at or above lo (which exceeds
+// every such prime) are enumerated once over the whole piece, and each
 // becomes a hit (its bit index) in the bucket of its segment.  `groups`
 // workgroups share the primes; no global atomic is needed:
 //   0. split (one workgroup): each group's table words;
 //   1. bound: an upper bound on each group's hits, floor((len - 1) / 2p) + 1
 //      per prime p (at most that many odd multiples of p lie in len
-//      consecutive numbers): a popcount of the table words, plus the
-//      quotient for the primes below len / 2;
+//      consecutive numbers): prime counts from the chunk count table for
+//      the primes above len / 2, the quotient for those below;
 //   2. plan (one workgroup): each group's stretch of the stream (its bound)
 //      and its number of sort tiles;
 //   3. fill: each group enumerates its hits and appends them, in the order
