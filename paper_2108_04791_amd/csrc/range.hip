@@ -869,18 +869,23 @@ __global__ void __launch_bounds__(BUCKET_THREADS) range_fill_kernel(BucketArgs a
     };
     // the primes of a chunk of 64 words (w0 .. w0 + 63; lane l holds word
     // w0 + l) are listed densely in LDS (a wavefront prefix sum of the
-    // words' popcounts) and then taken one per lane
+    // words' popcounts) and then taken one per lane; all lanes active
     auto chunk = [&](uint64_t w0, uint32_t word) {
         const uint64_t w = w0 + lane;
         const uint32_t c = (uint32_t)__popc(word);
+        // inclusive wavefront scan of c by data-parallel primitives: shifts
+        // by 1, 2, 4, 8 lanes within each row of 16 (lanes shifted in from
+        // outside a row read 0), then lane 15's sum added to rows 1 and 3
+        // and lane 31's to rows 2 and 3 (row broadcasts; the rows masked off
+        // add 0): six adds, no LDS round trips
         uint32_t inc = c;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t t = __shfl_up(inc, o, 64);
-            if (lane >= (uint32_t)o)
-                inc += t;
-        }
-        const uint32_t total = __shfl(inc, 63, 64);
+        inc += __builtin_amdgcn_update_dpp(0u, inc, 0x111, 0xf, 0xf, true);   // row_shr:1
+        inc += __builtin_amdgcn_update_dpp(0u, inc, 0x112, 0xf, 0xf, true);   // row_shr:2
+        inc += __builtin_amdgcn_update_dpp(0u, inc, 0x114, 0xf, 0xf, true);   // row_shr:4
+        inc += __builtin_amdgcn_update_dpp(0u, inc, 0x118, 0xf, 0xf, true);   // row_shr:8
+        inc += __builtin_amdgcn_update_dpp(0u, inc, 0x142, 0xa, 0xf, false);  // row_bcast:15
+        inc += __builtin_amdgcn_update_dpp(0u, inc, 0x143, 0xc, 0xf, false);  // row_bcast:31
+        const uint32_t total = __builtin_amdgcn_readlane(inc, 63);
         if (total <= BUCKET_PBUF) {
             uint32_t at = inc - c;
             while (word) {
