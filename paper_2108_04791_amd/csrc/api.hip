@@ -583,7 +583,7 @@ RangePlan plan_range_piece(uint64_t first, uint64_t piece)
                                                                           : MAX_BUCKET_GROUPS;
         p.groups = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(gmax, words / 1024));
         p.hit_words = bucket_hit_bound(piece, p.root);
-        p.count_words = bucket_layout(p.grid, p.groups, p.hit_words).count_words;
+        p.count_words = bucket_layout(p.grid, p.groups, p.hit_words, piece, p.root).count_words;
         p.complete = true;
         return p;
     }

@@ -263,14 +263,15 @@ hipError_t launch_chunk_primes(DeviceState &ds, hipStream_t s);
 hipError_t launch_range_table(uint64_t lo, uint8_t *out, uint64_t len, const DeviceState &ds,
                               hipStream_t s);
 // Bucket mode's sort tile, per-tile launch size and count words for nseg
-// segments, `groups` workgroups and room for hit_cap hits (ok false: no
-// tile fits the scan).
+// segments, `groups` workgroups, room for hit_cap hits and a piece of len
+// numbers up to root (ok false: no tile fits the scan).
 struct BucketLayout {
     uint32_t tile = 0, max_tiles = 0;
     uint64_t count_words = 0;
     bool ok = false;
 };
-BucketLayout bucket_layout(uint32_t nseg, unsigned groups, uint64_t hit_cap);
+BucketLayout bucket_layout(uint32_t nseg, unsigned groups, uint64_t hit_cap, uint64_t len,
+                           uint64_t root);
 // hit_bound: an upper bound on the piece's hits (at most rw.hit_cap), from
 // which the layout is sized.
 hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsigned groups,

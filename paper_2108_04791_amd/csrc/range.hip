@@ -568,6 +568,10 @@ constexpr int HIT_BITS = RANGE_SEG_LOG2 - 1;
 static_assert(MAX_BUCKET_SEGS <= (1 << (32 - HIT_BITS)), "segment fits above the bit index");
 // Hits per LDS round of the scatter kernel (1024 threads x 4).
 constexpr uint32_t BUCKET_SORT_SUB = 4096;
+// Full sort tiles the layout keeps at least while it lengthens them: about
+// 1.5 waves of the per-tile kernels at two 1024-thread workgroups on each of
+// the 256 compute units.
+constexpr uint64_t SCATTER_MIN_TILES = 768;
 
 // x mod d for integers 2^19 <= d < 2^34, in double precision with exact
 // remainder arithmetic.  The reciprocal is the hardware estimate refined by
@@ -1333,29 +1337,44 @@ hipError_t launch_range_table(uint64_t lo, uint8_t *out, uint64_t len, const Dev
     return hipGetLastError();
 }
 
-BucketLayout bucket_layout(uint32_t nseg, unsigned groups, uint64_t hit_cap)
+BucketLayout bucket_layout(uint32_t nseg, unsigned groups, uint64_t hit_cap, uint64_t len,
+                           uint64_t root)
 {
     BucketLayout L{};
-    // the smallest tile of at least 16 rounds (a power-of-two multiple of
-    // BUCKET_SORT_SUB) whose count array fits the three-pass scan (at most
-    // 1024 scan tiles); longer tiles leave fewer counts and let one
-    // workgroup's consecutive rounds complete more of each bucket's lines
-    // (measured at 2^63: 2^14-hit tiles 1.46 ms and 866 MiB written per
-    // 2^28 numbers, 2^16-hit tiles 1.37 ms and 732 MiB)
-    for (uint64_t tile = 16 * BUCKET_SORT_SUB; tile <= ((uint64_t)1 << 24); tile *= 2) {
-        const uint64_t max_tiles = (hit_cap + tile - 1) / tile + groups;
-        const uint64_t n2 = (uint64_t)nseg * max_tiles;
-        if (n2 <= (uint64_t)SCAN_TILE * 1024) {
-            L.tile = (uint32_t)tile;
-            L.max_tiles = (uint32_t)max_tiles;
-            const uint64_t ntiles = (n2 + SCAN_TILE - 1) / SCAN_TILE;
-            // starts, wsplit, totals, filled, sbase, tprefix, counts + total,
-            // scan sums + total
-            L.count_words = (uint64_t)nseg + 1 + 2 * (uint64_t)groups +
-                            3 * ((uint64_t)groups + 1) + n2 + 1 + ntiles + 1;
-            L.ok = true;
-            return L;
-        }
+    // Tiles of 8 or 16 rounds (a power-of-two multiple of BUCKET_SORT_SUB):
+    // 16 while at least SCATTER_MIN_TILES full tiles of 16 remain, and longer
+    // only until the count array fits the three-pass scan (at most 1024 scan
+    // tiles).  Longer tiles leave fewer counts and partial lines (measured at
+    // 2^63: 2^14-hit tiles 1.46 ms and 866 MiB written per 2^28 numbers,
+    // 2^16-hit tiles 1.37 ms and 732 MiB); enough tiles keep the scatter's
+    // workgroups balanced (2^28 numbers at 2^50, 30 M hits: 2^15-hit tiles
+    // 0.417 ms against 0.455 with 2^16; at 2^63, 61 M hits, 2^16 against 2^15:
+    // 0.903 against 0.939 ms; tiles of 2^18 for the 2^30-number piece below
+    // 2^64: 3.18 against 3.07 ms with 2^16).
+    auto words = [&](uint64_t tile, uint64_t &max_tiles) {
+        max_tiles = (hit_cap + tile - 1) / tile + groups;
+        return (uint64_t)nseg * max_tiles;
+    };
+    // (the tiles counted from the expected hits, len / 2 times the sum of 1/p
+    // over the primes in (BUCKET_SMALL, root], about len / 2 (ln ln root -
+    // ln ln BUCKET_SMALL) by Mertens: hit_cap also bounds one hit per prime)
+    const double lr = std::log(std::log((double)std::max<uint64_t>(root, BUCKET_SMALL + 1)));
+    const double hits = 0.5 * (double)len * std::max(0.0, lr - std::log(std::log((double)BUCKET_SMALL)));
+    uint64_t tile = 8 * BUCKET_SORT_SUB, max_tiles = 0;
+    if (hits / (double)(2 * tile) >= (double)SCATTER_MIN_TILES)
+        tile *= 2;
+    while (tile < ((uint64_t)1 << 24) && words(tile, max_tiles) > (uint64_t)SCAN_TILE * 1024)
+        tile *= 2;
+    const uint64_t n2 = words(tile, max_tiles);
+    if (n2 <= (uint64_t)SCAN_TILE * 1024) {
+        L.tile = (uint32_t)tile;
+        L.max_tiles = (uint32_t)max_tiles;
+        const uint64_t ntiles = (n2 + SCAN_TILE - 1) / SCAN_TILE;
+        // starts, wsplit, totals, filled, sbase, tprefix, counts + total,
+        // scan sums + total
+        L.count_words = (uint64_t)nseg + 1 + 2 * (uint64_t)groups +
+                        3 * ((uint64_t)groups + 1) + n2 + 1 + ntiles + 1;
+        L.ok = true;
     }
     return L;
 }
@@ -1385,7 +1404,7 @@ hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsign
         hit_bound > rw.hit_cap || hit_bound >= ((uint64_t)1 << 32) || !ds.chunk_primes ||
         lo <= root)
         return hipErrorInvalidValue;
-    const BucketLayout L = bucket_layout(a.nseg, groups, hit_bound);
+    const BucketLayout L = bucket_layout(a.nseg, groups, hit_bound, len, root);
     if (!L.ok || rw.count_cap < L.count_words)
         return hipErrorInvalidValue;
     a.tile = L.tile;
