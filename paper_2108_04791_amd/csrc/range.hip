@@ -409,7 +409,8 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
     // bucket mode: the hits of the primes above BUCKET_SMALL in this segment,
     // one contiguous run (the clamp only keeps reads inside the allocation),
     // eight per thread and round, all read before any is applied and the
-    // next round's read while this one is
+    // next round's read while this one is (streaming loads: this is their
+    // last use, and the caches are left to the hits still to be sorted)
     if (buckets) {
         const uint32_t h0 = a.hit_start[blockIdx.x];
         const uint32_t h1 = (uint32_t)min((uint64_t)a.hit_start[blockIdx.x + 1], a.hit_cap);
@@ -419,7 +420,7 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
 #pragma unroll
             for (int k = 0; k < UNROLL; ++k) {
                 const uint64_t i = h + (uint64_t)k * blockDim.x;
-                next[k] = i < h1 ? a.hits[i] : ~0u;
+                next[k] = i < h1 ? __builtin_nontemporal_load(&a.hits[i]) : ~0u;
             }
         };
         load(h0 + tid);
@@ -1081,13 +1082,15 @@ __global__ void __launch_bounds__(1024, 8) bucket_scatter_kernel(BucketArgs a)
     }
     const uint64_t b0 = (uint64_t)a.sbase[q] + (uint64_t)t * a.tile;
     const uint64_t b1 = min((uint64_t)a.sbase[q] + a.filled[q], b0 + a.tile);
-    // each round's hits are loaded while the round before is sorted
+    // each round's hits are loaded while the round before is sorted, as
+    // streaming loads (their last use: with these and the segment kernel's,
+    // 2^63: 0.911 -> 0.888 ms for 2^28 numbers)
     uint32_t next[PER];
     auto load = [&](uint64_t r0) {
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const uint64_t i = r0 + threadIdx.x + k * blockDim.x;
-            next[k] = i < b1 ? a.stream[i] : 0u;
+            next[k] = i < b1 ? __builtin_nontemporal_load(&a.stream[i]) : 0u;
         }
     };
     load(b0);
