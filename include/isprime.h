@@ -162,8 +162,9 @@ size_t isp_workspace_bytes(size_t len);
 /* Bytes of device workspace isprime_range_u64(lo, ..., len) holds: the
  * survivor workspace of its largest piece that goes to Miller-Rabin and the
  * bucket workspace of its largest bucket-mode piece (pieces decided by the
- * sieve alone need neither), and, when any part lies above 2^32, each
- * piece's residues modulo the interval primes (8.3 MB); 0 for an empty or
+ * sieve alone need neither), and, when any part lies above 2^32, the
+ * piece's table of interval primes with their residues (12 bytes per
+ * prime, 24.8 MB); 0 for an empty or
  * invalid interval.  The interval sieve's prime list and chunk prime counts
  * (28.9 MB per device, built on the first interval call) are not counted. */
 size_t isp_range_workspace_bytes(uint64_t lo, size_t len);

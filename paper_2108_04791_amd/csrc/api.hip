@@ -151,12 +151,12 @@ void free_range_ws(RangeWs &rw)
     rw = RangeWs();
 }
 
-// The residue buffer of `rw` (RANGE_MAX_PRIMES words, allocated once).
+// The residue buffer of `rw` (RANGE_MAX_PRIMES entries, allocated once).
 int ensure_range_res(RangeWs &rw)
 {
     if (rw.res)
         return ISP_OK;
-    const hipError_t e = hipMalloc(&rw.res, (size_t)RANGE_MAX_PRIMES * sizeof(uint32_t));
+    const hipError_t e = hipMalloc(&rw.res, (size_t)RANGE_MAX_PRIMES * sizeof(SievePrime));
     if (e != hipSuccess) {
         rw.res = nullptr;
         return fail(e);
@@ -1191,8 +1191,8 @@ size_t isp_range_workspace_bytes(uint64_t lo, size_t len)
         else if (!p.complete)
             mr = std::max(mr, isp_workspace_bytes(piece));
     }
-    // and the residues of the sieving primes, for any piece above 2^32
-    const size_t res = below < len ? (size_t)RANGE_MAX_PRIMES * sizeof(uint32_t) : 0;
+    // and the sieving primes with their residues, for any piece above 2^32
+    const size_t res = below < len ? (size_t)RANGE_MAX_PRIMES * sizeof(SievePrime) : 0;
     return mr + buckets + res;
 }
 

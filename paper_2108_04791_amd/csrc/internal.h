@@ -216,13 +216,20 @@ struct DeviceState {
 
 // Per-call workspace (one per stream, or per batched context).
 // Interval buckets: per-(segment, group) counts turned offsets, and the hits.
+// One sieving prime of an interval piece, with what a segment needs to find
+// its first multiple: m = floor(2^32 / p) and the piece's residue
+// (lo | 1) mod p, read by the segment kernel in one 12-byte load.
+struct SievePrime {
+    uint32_t p, m, res;
+};
+
 struct RangeWs {
     uint32_t *counts = nullptr;  // count_cap words
     uint32_t *hits = nullptr;    // hit_cap words
     uint32_t *stream = nullptr;  // hit_cap words: the fill pass's output, sorted into hits
     uint64_t count_cap = 0, hit_cap = 0;
-    // each piece's residues modulo the sieving primes (RANGE_MAX_PRIMES words)
-    uint32_t *res = nullptr;
+    // each piece's sieving primes with their residues (RANGE_MAX_PRIMES entries)
+    SievePrime *res = nullptr;
 };
 
 struct Workspace {
@@ -277,10 +284,11 @@ BucketLayout bucket_layout(uint32_t nseg, unsigned groups, uint64_t hit_cap, uin
 hipError_t launch_range_buckets(uint64_t lo, uint64_t len, uint64_t root, unsigned groups,
                                 uint64_t hit_bound, const DeviceState &ds, const RangeWs &rw,
                                 hipStream_t s);
-// res[k] = (lo | 1) mod (k-th interval prime) for every prime up to bound
-// (rw.res of the piece's stream, before the sieve kernel reads it).
+// res[k] = {p, floor(2^32 / p), (lo | 1) mod p} for the k-th interval prime p,
+// every prime up to bound (rw.res of the piece's stream, before the sieve
+// kernel reads it).
 hipError_t launch_range_residues(uint64_t lo, uint64_t bound, const DeviceState &ds,
-                                 uint32_t *res, hipStream_t s);
+                                 SievePrime *res, hipStream_t s);
 // Without buckets, a segment whose square root is below 2^complete_log2
 // (partial_log2 .. RANGE_PRIME_LOG2) is decided by the sieve alone; the others
 // are sieved by the primes below 2^partial_log2 (17 .. RANGE_PARTIAL_LOG2)

@@ -217,8 +217,8 @@ struct RangeArgs {
     uint64_t chunk;      // numbers per segment (the last one may be shorter)
     uint8_t *out;        // out[i] <-> lo + i
     const uint32_t *primes;
-    const uint64_t *inv;
-    const uint32_t *res;  // res[k] = (lo | 1) mod primes[k] for every prime the piece uses
+    const SievePrime *res;  // res[k]: primes[k], floor(2^32 / primes[k]) and
+                            // (lo | 1) mod primes[k], for every prime the piece uses
     uint32_t nprimes;
     Survivor *surv;      // grid regions of `chunk` entries
     uint32_t *counts;    // [grid]
@@ -330,7 +330,6 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
             off += p;                    // o0 is odd: an odd offset gives an even multiple
         return (uint64_t)off > span ? ~0u : off >> 1;
     };
-    const uint32_t *inv_hi = reinterpret_cast<const uint32_t *>(a.inv) + 1;  // [2k]: high words
     // primes 37 .. 8191: one wavefront per prime
     uint32_t k_split;
     {
@@ -352,8 +351,9 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
         const uint32_t k = kb + (uint32_t)lane * nwaves;
         uint32_t pl = 0, jl = ~0u;
         if (k < k_split) {
-            pl = a.primes[k];
-            const uint32_t j0 = first_bit(pl, inv_hi[2 * k], a.res[k]);
+            const SievePrime e = a.res[k];
+            pl = e.p;
+            const uint32_t j0 = first_bit(e.p, e.m, e.res);
             jl = j0 < nbits ? j0 : ~0u;
         }
         const uint32_t cnt = min(64u, (k_split - kb + nwaves - 1) / nwaves);
@@ -383,9 +383,10 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
                 const uint32_t k = kb + u * stride;
                 p[u] = m[u] = rs[u] = 0;
                 if (k < np) {
-                    p[u] = a.primes[k];
-                    m[u] = inv_hi[2 * k];
-                    rs[u] = a.res[k];
+                    const SievePrime e = a.res[k];
+                    p[u] = e.p;
+                    m[u] = e.m;
+                    rs[u] = e.res;
                 }
             }
         };
@@ -1291,21 +1292,26 @@ hipError_t launch_chunk_primes(DeviceState &ds, hipStream_t s)
 
 namespace {
 
-// The piece's residues: res[k] = base mod primes[k] for k < count.
+// The piece's sieving primes: res[k] = {primes[k], floor(2^32 / primes[k]),
+// base mod primes[k]} for k < count.
 __global__ void __launch_bounds__(256) range_residue_kernel(uint64_t base,
                                                            const uint32_t *__restrict__ primes,
                                                            const uint64_t *__restrict__ inv,
-                                                           uint32_t count, uint32_t *__restrict__ res)
+                                                           uint32_t count, SievePrime *__restrict__ res)
 {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < count)
-        res[k] = (uint32_t)mod_small(base, primes[k], inv[k]);
+    if (k < count) {
+        const uint32_t p = primes[k];
+        const uint64_t q = inv[k];
+        // the high word of floor((2^64 - 1) / p) is floor(2^32 / p) (p odd)
+        res[k] = SievePrime{p, (uint32_t)(q >> 32), (uint32_t)mod_small(base, p, q)};
+    }
 }
 
 }  // namespace
 
 hipError_t launch_range_residues(uint64_t lo, uint64_t bound, const DeviceState &ds,
-                                 uint32_t *res, hipStream_t s)
+                                 SievePrime *res, hipStream_t s)
 {
     // at most pi(bound) < 1.25506 bound / ln bound primes (Rosser and
     // Schoenfeld, Illinois J. Math. 6, 1962), all of them below 100
@@ -1481,7 +1487,6 @@ hipError_t launch_range_sieve(uint64_t lo, uint8_t *out, uint64_t len, unsigned 
     a.groups = groups;
     a.out = out;
     a.primes = ds.range_primes;
-    a.inv = ds.range_inv;
     a.res = rw.res;
     a.nprimes = (uint32_t)ds.num_range_primes;
     a.surv = ws.surv;

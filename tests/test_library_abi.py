@@ -65,10 +65,11 @@ def test_argument_errors_without_device(isp):
 def test_range_workspace_by_mode(isp):
     """An interval call holds survivor workspace only for pieces that go to
     Miller-Rabin, and bucket workspace only for bucket-mode pieces; above
-    2^32 also one residue word per interval prime (2,063,688 odd primes
-    below 2^25, one word to spare)."""
+    2^32 also one 12-byte entry per interval prime: the prime, its 32-bit
+    reciprocal and the piece's residue (2,063,688 odd primes below 2^25, one
+    entry to spare)."""
     W = isp.lib().isp_range_workspace_bytes
-    res = 4 * 2063689
+    res = 12 * 2063689
     assert W(0, 1 << 20) == 0                      # below 2^32: the table
     assert W(1 << 34, 1 << 28) == res              # complete segment sieve
     assert W(1 << 44, 1 << 30) == res
