@@ -181,6 +181,31 @@ def test_bucket_mode_high_magnitude(isp, lo, length):
     assert np.array_equal(got[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.uint8), exp)
 
 
+@pytest.mark.parametrize("p,length", [(131071, 1 << 26), (4194301, 1 << 28),
+                                      (2147483647, 1 << 28), (4294967291, 1 << 28)])
+def test_interval_ending_at_a_prime_square(isp, p, length):
+    """Intervals whose last number is p^2 for a prime p, so that p is exactly
+    the square root of the last segment and its only sieving prime for p^2:
+    131071 = 2^17 - 1 (segments of 2^19, complete), 4194301 (the largest
+    prime below 2^22: segments of 2^20, complete), 2^31 - 1 and 4294967291
+    (the largest prime below 2^32: bucket mode, p in the last table word the
+    bucket passes count).  p^2 must come out composite, the whole interval
+    must equal the array call, and a sample must equal the oracle."""
+    lo = p * p - length + 1
+    got = isp.isprime_range(lo, length)
+    assert int(got[-1].item()) == 0
+    base = lo if lo < (1 << 63) else lo - (1 << 64)
+    arr = torch.arange(base, base + length, dtype=torch.int64, device="cuda")
+    assert torch.equal(isp.isprime(arr), got)
+    del arr
+    rng = np.random.default_rng(p & 0xffff)
+    idx = np.unique(np.concatenate([np.arange(0, 2000), np.arange(length - 5000, length),
+                                    rng.integers(0, length, 20000)])).astype(np.int64)
+    a = np.uint64(lo) + idx.astype(np.uint64)
+    exp, _ = oracle.isprime_array(a, nthreads=NTHREADS, use_table=False)
+    assert np.array_equal(got[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.uint8), exp)
+
+
 def test_larger_than_one_piece_sampled(isp):
     """A call of more than 2^30 numbers runs in pieces; the outputs around the
     piece boundary and a random sample are checked one by one, and the whole
