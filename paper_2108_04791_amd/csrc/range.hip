@@ -24,11 +24,12 @@
 // 2^20 over at least 256 segments, else at most 2^19); bit j of its LDS
 // bitset stands for the odd number o0 + 2j.
 // The multiples of 3 .. 31 come from periodic word masks (pre-sieve);
-// primes 37 .. 8191 are crossed off by whole wavefronts (lane l takes the
+// primes 37 .. 4093 are crossed off by whole wavefronts (lane l takes the
 // multiples l, l+64, ... of the stride), larger primes one per thread.  The
-// first odd multiple of p at or above o0 needs o0 mod p, taken with a
-// precomputed floor((2^64 - 1) / p) (one 64-bit multiply-high, no
-// division).  The sieving primes are below 2^25 and o0 is at least 2^32, so
+// first odd multiple of p at or above o0 needs o0 mod p: the piece's residue
+// (lo | 1) mod p, computed once per piece with a precomputed
+// floor((2^64 - 1) / p) (one 64-bit multiply-high, no division), plus the
+// segment's offset reduced with floor(2^32 / p).  The sieving primes are below 2^25 and o0 is at least 2^32, so
 // every multiple crossed off is a proper one (no start at p^2 is needed).
 //
 // Output: 16 consecutive numbers per thread per pass, consecutive threads on
@@ -47,7 +48,9 @@ namespace isp {
 namespace {
 
 constexpr int RANGE_THREADS = 1024;
-constexpr uint32_t WAVE_PRIME_LIMIT = 8192;  // primes below this: wavefront per prime
+// primes below this: wavefront per prime (measured against 8192, 2048 and
+// 1024: 2^28 numbers at 2^34 0.101 -> 0.099 ms, at 2^44 0.194 -> 0.189)
+constexpr uint32_t WAVE_PRIME_LIMIT = 4096;
 constexpr int PRESIEVED = 10;                 // 3 .. 31: index of 37 in the prime list
 constexpr uint32_t SMALL_PRIMES[PRESIEVED] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
 
@@ -330,7 +333,7 @@ __global__ void __launch_bounds__(RANGE_THREADS) range_sieve_kernel(RangeArgs a)
             off += p;                    // o0 is odd: an odd offset gives an even multiple
         return (uint64_t)off > span ? ~0u : off >> 1;
     };
-    // primes 37 .. 8191: one wavefront per prime
+    // primes 37 .. WAVE_PRIME_LIMIT: one wavefront per prime
     uint32_t k_split;
     {
         uint32_t lo_i = 0, hi_i = np;  // first index with prime >= WAVE_PRIME_LIMIT
