@@ -301,7 +301,7 @@ def bench_intervals(isp, torch, reps: int = 5, array_call: bool = True, only=Non
     """The interval call above 2^32, where each workgroup sieves a segment of
     2^20 or 2^19 numbers in LDS, in each of its modes: segments decided by the primes
     up to their square root (2^34, 2^44), the bucket sieve of the primes
-    above 2^20 (2^50, 2^63, 2^64 - 2^28), and, for an interval short next
+    above 2^21 (2^50, 2^63, 2^64 - 2^28), and, for an interval short next
     to the number of primes up to its square root, the primes below 2^22
     followed by Miller-Rabin on the survivors (2^24 numbers at 2^63); each
     against the array call on the same values."""

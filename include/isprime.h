@@ -145,7 +145,7 @@ int isprime_u64_batched_offsets(const uint64_t *n, uint8_t *out, const uint64_t 
  * at most 2^30 numbers.  A piece ending below 2^50 is sieved by every odd prime up
  * to the square root of its end, which decides it.  Above, a piece long
  * enough for the primes up to its square root (pi(sqrt) below 0.8 times its
- * length) also gets every such prime: those above 2^20 are sorted once into
+ * length) also gets every such prime: those above 2^21 are sorted once into
  * per-segment buckets (bucket sieve), and the segments are again complete.
  * Otherwise it is sieved by the odd primes below 2^22 (below 2^18 for a
  * piece of fewer than 256 segments of 2^19, which is then cut into up to 256

@@ -107,11 +107,12 @@ constexpr int RANGE_PARTIAL_LOG2 = 22;    // primes used where the sieve cannot 
 constexpr int RANGE_MAX_PRIMES = 2063689; // odd primes below 2^25: 2063688
 constexpr int RANGE_LIST_GROUPS = 512;    // workgroups of the list build
 // bucket mode (segments of RANGE_SEG numbers): primes above this come as
-// precomputed hits (at most one per segment); the primes just above half
-// the segment length are cheaper for the segment kernel than their
-// scattered hits (measured with segments of 2^19 numbers: 2^20 beat 2^19 by
-// 6% at 2^48 .. 2^50, about 1% higher up; 2^21 gained nothing more)
-constexpr uint32_t BUCKET_SMALL = (uint32_t)1 << 20;
+// precomputed hits (at most one per segment); the primes up to twice the
+// segment length are cheaper for the segment kernel, which reads each with
+// its constants in one load, than their scattered hits (measured on 2^28
+// numbers against 2^20: 2^48 0.377 -> 0.328 ms, 2^50 0.400 -> 0.348, 2^63
+// 0.876 -> 0.859; 2^22 was faster at 2^62 but slower at 2^63 and above)
+constexpr uint32_t BUCKET_SMALL = (uint32_t)1 << 21;
 constexpr int MAX_BUCKET_SEGS = (int)(RANGE_PIECE / RANGE_SEG);  // 1024
 constexpr int MAX_BUCKET_GROUPS = 512;
 constexpr int BUCKET_FROM_LOG2 = 23;  // bucket mode for pieces whose root exceeds 2^23

@@ -8,7 +8,7 @@
 // one segment of the interval in LDS by the odd primes up to
 // sqrt(segment end) while that is below 2^25 (segment end below 2^50); then
 // the survivors are exactly the primes.  Above it, a long piece runs in
-// bucket mode (below): the primes above 2^20 up to the square root are
+// bucket mode (below): the primes above 2^21 up to the square root are
 // sorted into per-segment buckets first, and the segments are complete
 // again.  A short piece is sieved by the odd primes below 2^22 (below 2^18
 // when it has fewer than 256 full segments of 2^19 numbers; it is then cut
@@ -574,9 +574,10 @@ static_assert(MAX_BUCKET_SEGS <= (1 << (32 - HIT_BITS)), "segment fits above the
 // Hits per LDS round of the scatter kernel (1024 threads x 4).
 constexpr uint32_t BUCKET_SORT_SUB = 4096;
 // Full sort tiles the layout keeps at least while it lengthens them: about
-// 1.5 waves of the per-tile kernels at two 1024-thread workgroups on each of
-// the 256 compute units.
-constexpr uint64_t SCATTER_MIN_TILES = 768;
+// 1.3 waves of the per-tile kernels at two 1024-thread workgroups on each of
+// the 256 compute units (measured on 2^28 numbers at 2^60, 47 M hits: 2^16-hit
+// tiles 0.615 ms against 0.657 with 2^15, which 768 chose there).
+constexpr uint64_t SCATTER_MIN_TILES = 650;
 
 // x mod d for integers 2^19 <= d < 2^34, in double precision with exact
 // remainder arithmetic.  The reciprocal is the hardware estimate refined by

@@ -10,7 +10,7 @@ test_gpu_parity.py) check the kernels' bytes.
    is exact (the fused result is an integer below 2^35 in magnitude).  The
    first odd multiple of p at or above lo follows from m = lo mod 2p.
 2. The hit bound of each group of primes: floor((len - 1) / 2p) + 1 per
-   prime p in (2^20, root], with the primes above (len - 1) / 2 (bound 1
+   prime p in (2^21, root], with the primes above (len - 1) / 2 (bound 1
    each) counted from per-chunk prime counts and the group boundaries'
    partial chunks, and the root's word counted up to root.
 3. 2^64 mod n for odd n >= 2^32: q = floor(2^64 (1/n) - 1/2) from the same
@@ -88,7 +88,7 @@ def _table(n):
 
 
 def test_group_bounds_from_chunk_counts():
-    small = 1 << 20
+    small = 1 << 21
     table, primes = _table(1 << 24)
     popc = np.unpackbits(table.view(np.uint8)).reshape(-1, 32).sum(axis=1).astype(np.int64)
     cum = np.concatenate([[0], np.cumsum(popc.reshape(-1, 64).sum(axis=1))])
